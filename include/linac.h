@@ -1,0 +1,163 @@
+/*
+ * linac-mi355x: exact Gaussian elimination over a prime field F_p on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The operations follow the statement of the method in "Linac: linear algebra
+ * with CUDA over finite fields" (De Laurentis, Franklin):
+ *   - row reduction to reduced row-echelon form (RREF) in the original shape,
+ *     zero rows at the bottom, with field_characteristic = p selecting exact
+ *     arithmetic mod p (Sec. 2.3 "Basic Usage"; Sec. 3.2);
+ *   - the rank and the pivot columns of the RREF (Sec. 5.1);
+ *   - solving A X = B by reducing the augmented matrix [A | B]: a column of B
+ *     is consistent iff rank(A) = rank([A | b]); the particular solution sets
+ *     the free (non-pivot) variables to zero (Sec. 5.2).
+ *
+ * Conventions shared by every entry point
+ *   - Residues are canonical: 0 <= a < p, stored as uint32.  p must be a prime
+ *     with 2 <= p < 2^31 (so a residue is also a non-negative int32).
+ *   - Matrices are row-major with an explicit leading dimension (elements
+ *     between the starts of consecutive rows).
+ *   - Every array pointer is a DEVICE pointer owned by the caller.  The library
+ *     never allocates device memory: scratch space comes from the caller's
+ *     workspace `ws` of `ws_bytes` bytes, sized by the matching *_workspace
+ *     query.  No pointer is kept after a call returns.
+ *   - Calls are asynchronous on the HIP stream `s` (NULL = the null stream);
+ *     outputs are valid once the stream has been synchronised.  Calls on
+ *     distinct streams with distinct workspaces may run concurrently.
+ *   - Errors are returned, never thrown.  All argument checks run on the host
+ *     before any device work, so a non-OK return from a check leaves every
+ *     buffer untouched.  On LINAC_E_HIP the outputs are unspecified and
+ *     linac_last_hip_error() gives the HIP error code.
+ *   - m = 0, n = 0 or k = 0 are valid shapes (rank 0).
+ */
+#ifndef LINAC_H
+#define LINAC_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LINAC_OK = 0,
+    LINAC_E_INVALID_ARG = 1, /* null pointer, negative size, leading dimension too small */
+    LINAC_E_UNSUPPORTED = 2, /* p = 0 (floating-point mode), p >= 2^31, path not available */
+    LINAC_E_NOT_PRIME = 3,   /* p is not prime (deterministic Miller-Rabin, bases 2, 7, 61) */
+    LINAC_E_RANGE = 4,       /* an entry is >= p (checked only with opts.validate) */
+    LINAC_E_WORKSPACE = 5,   /* ws is NULL or smaller than the workspace query */
+    LINAC_E_NOMEM = 6,       /* problem does not fit in 64-bit byte counts */
+    LINAC_E_HIP = 7          /* a HIP runtime call failed */
+} linac_status;
+
+enum {
+    LINAC_PATH_AUTO = 0,
+    LINAC_PATH_PLAIN = 1,        /* one fused Gauss-Jordan step kernel per pivot column */
+    LINAC_PATH_BLOCKED_INT8 = 2, /* blocked, trailing update on int8 MFMA (balanced limbs) */
+    LINAC_PATH_BLOCKED_FP64 = 3  /* blocked, trailing update on FP64 MFMA (p < 2^21) */
+};
+
+typedef struct {
+    int path;          /* LINAC_PATH_*; AUTO picks by p and size */
+    int panel_width;   /* blocked paths: panel width, 0 = tuned default */
+    int validate;      /* non-zero: check 0 <= entry < p on the device first.  This
+                          makes the call synchronous (it reads a flag back) and
+                          returns LINAC_E_RANGE on failure */
+    int verbose;       /* non-zero: print the chosen path and launch geometry */
+    hipEvent_t ev_begin; /* optional (may be NULL): recorded on `s` immediately before
+                            the first launch of the path's dominant kernel */
+    hipEvent_t ev_end;   /* optional: recorded immediately after its last launch */
+    int64_t* dominant_launches; /* optional HOST pointer: receives the number of
+                                   launches of the dominant kernel */
+} linac_opts;
+
+/* Workspace (bytes) needed by linac_rref for an m x n matrix. */
+linac_status linac_rref_workspace(int64_t m, int64_t n, const linac_opts* opts, size_t* bytes);
+
+/*
+ * RREF of A over F_p, in place (Sec. 2.3; Sec. 3.2; Fig. 1).
+ *   A       device, m x n row-major, leading dimension lda >= max(n, 1); on
+ *           return it holds the RREF: the rank r non-zero rows first, each with a
+ *           leading 1 in its pivot column, pivot columns zero elsewhere, the
+ *           remaining m - r rows zero.
+ *   rank    device int32[1]: r.
+ *   pivots  device int32[min(m, n)]: the pivot columns in ascending order,
+ *           -1 from index r on.  May be NULL when min(m, n) = 0.
+ */
+linac_status linac_rref(uint32_t* A, int64_t m, int64_t n, int64_t lda, uint32_t p,
+                        int32_t* rank, int32_t* pivots, void* ws, size_t ws_bytes,
+                        const linac_opts* opts, hipStream_t s);
+
+/* Workspace (bytes) needed by linac_solve for A m x n and B m x k. */
+linac_status linac_solve_workspace(int64_t m, int64_t n, int64_t k, const linac_opts* opts,
+                                   size_t* bytes);
+
+/*
+ * Solve A X = B over F_p by reducing [A | B] (Sec. 5.2).  A and B are not
+ * modified.  Pivots are searched only in A's n columns.
+ *   A           device, m x n, leading dimension lda >= max(n, 1).
+ *   B           device, m x k, leading dimension ldb >= max(k, 1).
+ *   X           device, n x k, leading dimension ldx >= max(k, 1): the
+ *               particular solution with free variables zero; column t is all
+ *               zero when it is inconsistent.
+ *   rank        device int32[1]: rank(A).
+ *   pivots      device int32[min(m, n)]: ascending pivot columns of A, -1 padded
+ *               (may be NULL when min(m, n) = 0).
+ *   consistent  device uint8[k]: 1 iff rank(A) = rank([A | b_t]) (may be NULL
+ *               when k = 0).
+ */
+linac_status linac_solve(const uint32_t* A, int64_t m, int64_t n, int64_t lda,
+                         const uint32_t* B, int64_t k, int64_t ldb, uint32_t p,
+                         uint32_t* X, int64_t ldx, int32_t* rank, int32_t* pivots,
+                         uint8_t* consistent, void* ws, size_t ws_bytes,
+                         const linac_opts* opts, hipStream_t s);
+
+/* One system of a batch: the same meaning as the linac_solve arguments, with its
+ * own prime.  Square or rectangular; all pointers are device pointers. */
+typedef struct {
+    const uint32_t* A;
+    const uint32_t* B;
+    uint32_t* X;
+    int32_t m, n, k;
+    int32_t lda, ldb, ldx;
+    uint32_t p;
+    int32_t* rank;
+    int32_t* pivots;
+    uint8_t* consistent;
+} linac_system;
+
+/* Workspace (bytes) for linac_solve_batched on this host array of systems. */
+linac_status linac_solve_batched_workspace(const linac_system* sys, int32_t count,
+                                           const linac_opts* opts, size_t* bytes);
+
+/*
+ * Solve `count` independent systems in one persistent launch (the paper solves
+ * one matrix per call; batching many uneven systems is this library's
+ * extension).  `sys` is a HOST array read during the call only.  The library
+ * uploads the descriptors into ws and launches a graph that it captured for
+ * this (ws, plan) pair on first use, replaying it on later calls.  Per system the
+ * results equal those of linac_solve.
+ */
+linac_status linac_solve_batched(const linac_system* sys, int32_t count, void* ws,
+                                 size_t ws_bytes, const linac_opts* opts, hipStream_t s);
+
+/* Load tuned parameters (JSON text, as written by the autotuner) for later calls;
+ * NULL restores the built-in defaults.  Tuning never changes results. */
+linac_status linac_load_tuning(const char* json);
+
+/* Host-only primality check used by argument validation: LINAC_OK when p is a
+ * prime below 2^31, LINAC_E_NOT_PRIME when not prime, LINAC_E_UNSUPPORTED when
+ * p = 0 or p >= 2^31.  Touches no device. */
+linac_status linac_check_prime(uint32_t p);
+
+const char* linac_status_string(linac_status st);
+int linac_last_hip_error(void);
+int linac_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LINAC_H */

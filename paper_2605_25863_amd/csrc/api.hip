@@ -1,0 +1,232 @@
+// C-ABI front end: argument checks, workspace sizing and path dispatch.
+//
+// Every check runs on the host before any device work (the paper keeps the
+// host blind during elimination, Sec. 3.1 and 3.2; here the host decides only
+// the launch sequence).  Kernels live in plain.hip, batched.hip and blocked.hip.
+#include <stdio.h>
+#include <string.h>
+
+#include "internal.h"
+
+using namespace linac;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+linac_status hip_fail(hipError_t e) {
+    g_last_hip = (int)e;
+    return LINAC_E_HIP;
+}
+
+// a^e mod n for n < 2^32 (host).
+uint64_t pow_mod_u64(uint64_t a, uint64_t e, uint64_t n) {
+    uint64_t r = 1 % n;
+    a %= n;
+    while (e) {
+        if (e & 1) r = r * a % n;
+        a = a * a % n;
+        e >>= 1;
+    }
+    return r;
+}
+
+// Deterministic Miller-Rabin for n < 4 759 123 141 with bases 2, 7, 61
+// (Jaeschke 1993).
+bool is_prime_u32(uint32_t n) {
+    if (n < 2) return false;
+    static const uint32_t small[] = {2, 3, 5, 7, 11, 13, 61};
+    for (uint32_t q : small)
+        if (n % q == 0) return n == q;
+    uint32_t d = n - 1;
+    int s = 0;
+    while ((d & 1) == 0) {
+        d >>= 1;
+        ++s;
+    }
+    for (uint32_t a : {2u, 7u, 61u}) {
+        uint64_t x = pow_mod_u64(a, d, n);
+        if (x == 1 || x == n - 1) continue;
+        bool witness = true;
+        for (int i = 1; i < s; ++i) {
+            x = x * x % n;
+            if (x == n - 1) {
+                witness = false;
+                break;
+            }
+        }
+        if (witness) return false;
+    }
+    return true;
+}
+
+linac_status check_field(uint32_t p) {
+    if (p == 0 || p >= 0x80000000u) return LINAC_E_UNSUPPORTED;
+    return is_prime_u32(p) ? LINAC_OK : LINAC_E_NOT_PRIME;
+}
+
+int effective_path(const linac_opts* opts) {
+    int path = opts ? opts->path : LINAC_PATH_AUTO;
+    return path;
+}
+
+bool size_ok(int64_t m, int64_t n, int64_t k) {
+    // kernels index rows and columns with 32-bit values
+    return m < (1LL << 31) - 64 && n + k < (1LL << 31) - 64;
+}
+
+// Host range check (optional, synchronous): runs a kernel that raises a flag
+// in the workspace, then reads the flag back.
+linac_status validate_range(const uint32_t* M, int64_t rows, int64_t cols, int64_t ld, uint32_t p,
+                            uint32_t* flag, hipStream_t s) {
+    if (rows * cols == 0) return LINAC_OK;
+    uint32_t zero = 0, host = 0;
+    hipError_t e = hipMemcpyAsync(flag, &zero, sizeof(zero), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e);
+    e = launch_range_check(M, rows, cols, ld, p, flag, s);
+    if (e != hipSuccess) return hip_fail(e);
+    e = hipMemcpyAsync(&host, flag, sizeof(host), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e);
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e);
+    return host ? LINAC_E_RANGE : LINAC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int linac_version(void) { return 100; }
+
+int linac_last_hip_error(void) { return g_last_hip; }
+
+const char* linac_status_string(linac_status st) {
+    switch (st) {
+        case LINAC_OK: return "ok";
+        case LINAC_E_INVALID_ARG: return "invalid argument";
+        case LINAC_E_UNSUPPORTED: return "unsupported (p must be a prime below 2^31; path unavailable)";
+        case LINAC_E_NOT_PRIME: return "modulus is not prime";
+        case LINAC_E_RANGE: return "entry out of range [0, p)";
+        case LINAC_E_WORKSPACE: return "workspace missing or too small";
+        case LINAC_E_NOMEM: return "problem too large";
+        case LINAC_E_HIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+linac_status linac_check_prime(uint32_t p) { return check_field(p); }
+
+linac_status linac_rref_workspace(int64_t m, int64_t n, const linac_opts* opts, size_t* bytes) {
+    if (!bytes || m < 0 || n < 0) return LINAC_E_INVALID_ARG;
+    if (!size_ok(m, n, 0)) return LINAC_E_NOMEM;
+    (void)opts;
+    *bytes = plain_workspace(m, n, 0);
+    return LINAC_OK;
+}
+
+linac_status linac_rref(uint32_t* A, int64_t m, int64_t n, int64_t lda, uint32_t p, int32_t* rank,
+                        int32_t* pivots, void* ws, size_t ws_bytes, const linac_opts* opts,
+                        hipStream_t s) {
+    if (m < 0 || n < 0) return LINAC_E_INVALID_ARG;
+    if (lda < (n > 0 ? n : 1)) return LINAC_E_INVALID_ARG;
+    if (!rank) return LINAC_E_INVALID_ARG;
+    if (m * n > 0 && !A) return LINAC_E_INVALID_ARG;
+    if ((m < n ? m : n) > 0 && !pivots) return LINAC_E_INVALID_ARG;
+    linac_status st = check_field(p);
+    if (st != LINAC_OK) return st;
+    if (!size_ok(m, n, 0)) return LINAC_E_NOMEM;
+    int path = effective_path(opts);
+    if (path != LINAC_PATH_AUTO && path != LINAC_PATH_PLAIN) return LINAC_E_UNSUPPORTED;
+    size_t need = plain_workspace(m, n, 0);
+    if (!ws || ws_bytes < need) return LINAC_E_WORKSPACE;
+
+    PlainArgs a;
+    plain_carve(ws, m, n, 0, a);
+    a.F = make_field(p);
+    if (opts && opts->validate) {
+        st = validate_range(A, m, n, lda, p, (uint32_t*)a.state, s);
+        if (st != LINAC_OK) return st;
+    }
+    if (opts && opts->verbose)
+        fprintf(stderr, "[linac] rref plain m=%lld n=%lld p=%u ld=%lld\n", (long long)m,
+                (long long)n, p, (long long)a.ld);
+    hipError_t e = plain_prepare(a, A, lda, nullptr, 1, (int32_t)n, 0, s);
+    if (e == hipSuccess) e = plain_eliminate(a, opts, s);
+    if (e == hipSuccess) e = plain_finish_rref(a, A, lda, rank, pivots, s);
+    return e == hipSuccess ? LINAC_OK : hip_fail(e);
+}
+
+linac_status linac_solve_workspace(int64_t m, int64_t n, int64_t k, const linac_opts* opts,
+                                   size_t* bytes) {
+    if (!bytes || m < 0 || n < 0 || k < 0) return LINAC_E_INVALID_ARG;
+    if (!size_ok(m, n, k)) return LINAC_E_NOMEM;
+    (void)opts;
+    *bytes = plain_workspace(m, n, k);
+    return LINAC_OK;
+}
+
+linac_status linac_solve(const uint32_t* A, int64_t m, int64_t n, int64_t lda, const uint32_t* B,
+                         int64_t k, int64_t ldb, uint32_t p, uint32_t* X, int64_t ldx,
+                         int32_t* rank, int32_t* pivots, uint8_t* consistent, void* ws,
+                         size_t ws_bytes, const linac_opts* opts, hipStream_t s) {
+    if (m < 0 || n < 0 || k < 0) return LINAC_E_INVALID_ARG;
+    if (lda < (n > 0 ? n : 1) || ldb < (k > 0 ? k : 1) || ldx < (k > 0 ? k : 1))
+        return LINAC_E_INVALID_ARG;
+    if (!rank) return LINAC_E_INVALID_ARG;
+    if (m * n > 0 && !A) return LINAC_E_INVALID_ARG;
+    if (m * k > 0 && !B) return LINAC_E_INVALID_ARG;
+    if (n * k > 0 && !X) return LINAC_E_INVALID_ARG;
+    if (k > 0 && !consistent) return LINAC_E_INVALID_ARG;
+    if ((m < n ? m : n) > 0 && !pivots) return LINAC_E_INVALID_ARG;
+    linac_status st = check_field(p);
+    if (st != LINAC_OK) return st;
+    if (!size_ok(m, n, k)) return LINAC_E_NOMEM;
+    int path = effective_path(opts);
+    if (path != LINAC_PATH_AUTO && path != LINAC_PATH_PLAIN) return LINAC_E_UNSUPPORTED;
+    size_t need = plain_workspace(m, n, k);
+    if (!ws || ws_bytes < need) return LINAC_E_WORKSPACE;
+
+    PlainArgs a;
+    plain_carve(ws, m, n, k, a);
+    a.F = make_field(p);
+    if (opts && opts->validate) {
+        st = validate_range(A, m, n, lda, p, (uint32_t*)a.state, s);
+        if (st == LINAC_OK) st = validate_range(B, m, k, ldb, p, (uint32_t*)a.state, s);
+        if (st != LINAC_OK) return st;
+    }
+    if (opts && opts->verbose)
+        fprintf(stderr, "[linac] solve plain m=%lld n=%lld k=%lld p=%u ld=%lld\n", (long long)m,
+                (long long)n, (long long)k, p, (long long)a.ld);
+    hipError_t e = plain_prepare(a, A, lda, B, ldb, (int32_t)n, (int32_t)k, s);
+    if (e == hipSuccess) e = plain_eliminate(a, opts, s);
+    if (e == hipSuccess) e = plain_finish_solve(a, (int32_t)n, (int32_t)k, X, ldx, rank, pivots,
+                                                consistent, s);
+    return e == hipSuccess ? LINAC_OK : hip_fail(e);
+}
+
+linac_status linac_solve_batched_workspace(const linac_system* sys, int32_t count,
+                                           const linac_opts* opts, size_t* bytes) {
+    (void)sys;
+    (void)count;
+    (void)opts;
+    (void)bytes;
+    return LINAC_E_UNSUPPORTED;
+}
+
+linac_status linac_solve_batched(const linac_system* sys, int32_t count, void* ws, size_t ws_bytes,
+                                 const linac_opts* opts, hipStream_t s) {
+    (void)sys;
+    (void)count;
+    (void)ws;
+    (void)ws_bytes;
+    (void)opts;
+    (void)s;
+    return LINAC_E_UNSUPPORTED;
+}
+
+linac_status linac_load_tuning(const char* json) {
+    (void)json;
+    return LINAC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// Internal interfaces between the C-ABI front end (api.hip) and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "field.h"
+#include "../../include/linac.h"
+
+namespace linac {
+
+// Sentinel of a per-column pivot slot: no pivot found (yet).
+static constexpr unsigned long long kNoPivot = ~0ull;
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+inline int64_t ceil_div(int64_t x, int64_t m) { return (x + m - 1) / m; }
+
+// Carve aligned regions out of a caller-owned workspace.  With base == NULL it
+// only measures.
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base((char*)b) {}
+    template <class T>
+    T* take(int64_t count) {
+        off = (size_t)round_up((int64_t)off, 256);
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += (size_t)count * sizeof(T);
+        return p;
+    }
+};
+
+// Working state of the plain Gauss-Jordan path for one system, all in the
+// workspace.  W is the m x ld working copy of [A | B] (ld a multiple of 64, the
+// padding columns zero).  Rows are never moved: the s-th pivot row is the
+// physical row pivrow[s] (a virtual row swap), and the final gather writes the
+// rows in pivot order.
+struct PlainArgs {
+    uint32_t* W;
+    int64_t ld;
+    int32_t m;
+    int32_t ncols;    // n + k
+    int32_t nsearch;  // n: pivots are searched in columns [0, nsearch)
+    int32_t pad;
+    uint32_t* fcol[2];           // column j of the working matrix as of step j (ping-pong)
+    uint32_t* is_piv;            // 1 for rows already chosen as pivots
+    unsigned long long* slots;   // per column: (pivot row << 32) | inverse of its head
+    int32_t* pivrow;             // s-th pivot row
+    int32_t* pivcol;             // s-th pivot column
+    int32_t* colpiv;             // per column: s, or -1 for a free column
+    int32_t* state;              // [0] = rank so far
+    uint32_t* incons;            // per right-hand side: 1 once a residual is non-zero
+    FieldConst F;
+};
+
+size_t plain_workspace(int64_t m, int64_t n, int64_t k);
+void plain_carve(void* ws, int64_t m, int64_t n, int64_t k, PlainArgs& a);
+
+// Launch sequences (stream-ordered, no host synchronisation).
+hipError_t plain_prepare(const PlainArgs& a, const uint32_t* A, int64_t lda, const uint32_t* B,
+                         int64_t ldb, int32_t n, int32_t k, hipStream_t s);
+hipError_t plain_eliminate(const PlainArgs& a, const linac_opts* opts, hipStream_t s);
+hipError_t plain_finish_solve(const PlainArgs& a, int32_t n, int32_t k, uint32_t* X, int64_t ldx,
+                              int32_t* rank, int32_t* pivots, uint8_t* consistent, hipStream_t s);
+hipError_t plain_finish_rref(const PlainArgs& a, uint32_t* A, int64_t lda, int32_t* rank,
+                             int32_t* pivots, hipStream_t s);
+
+// Range check of residues: sets *flag to 1 when an entry is >= p.
+hipError_t launch_range_check(const uint32_t* M, int64_t rows, int64_t cols, int64_t ld, uint32_t p,
+                              uint32_t* flag, hipStream_t s);
+
+}  // namespace linac

@@ -1,0 +1,133 @@
+"""The C-ABI library: it loads, exports every declared symbol, and rejects bad
+arguments on the host before any device work (runs without a GPU: every call
+here returns from the host-side checks)."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2605_25863_amd as lx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "linac.h")
+
+OK, INVALID, UNSUP, NOTPRIME, RANGE, WS, NOMEM, HIP = range(8)
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:linac_status|const char\*|int)\s+(linac_\w+)\s*\(",
+                                 text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(lx.library_path()):
+        pytest.fail("library not built: run __graft_entry__.build() first")
+    return lx._load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 11
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_version_and_strings(lib):
+    assert lib.linac_version() >= 100
+    for st in range(8):
+        assert lib.linac_status_string(st)
+
+
+def test_check_prime_matches_trial_division(lib):
+    limit = 1 << 18
+    sieve = np.ones(limit, dtype=bool)
+    sieve[:2] = False
+    for i in range(2, int(limit ** 0.5) + 1):
+        if sieve[i]:
+            sieve[i * i::i] = False
+    for v in range(1, limit):
+        want = OK if sieve[v] else NOTPRIME
+        assert lib.linac_check_prime(v) == want, v
+    # strong pseudoprimes to base 2 and Carmichael numbers are composite
+    for v in (2047, 3277, 4033, 4681, 8321, 561, 1105, 1729, 2465, 25326001, 46337 * 46327):
+        assert lib.linac_check_prime(v) == NOTPRIME, v
+    assert lib.linac_check_prime(3215031751) == UNSUP  # spsp(2,3,5,7), above 2^31
+    # random 31-bit values against trial division
+    rng = np.random.default_rng(0)
+    for v in rng.integers(1 << 30, 1 << 31, size=300):
+        v = int(v)
+        prime = all(v % d for d in range(2, int(v ** 0.5) + 1))
+        assert lib.linac_check_prime(v) == (OK if prime else NOTPRIME), v
+    assert lib.linac_check_prime((1 << 31) - 1) == OK
+    assert lib.linac_check_prime(2147483629) == OK
+    assert lib.linac_check_prime(0) == UNSUP
+    assert lib.linac_check_prime(1 << 31) == UNSUP
+    assert lib.linac_check_prime(0xFFFFFFFB) == UNSUP  # prime, but above 2^31
+
+
+def _fake(n=1):
+    # non-null addresses that the host checks never dereference
+    return ctypes.c_void_p(0x1000 * n)
+
+
+def _solve(lib, m=4, n=4, k=1, lda=4, ldb=1, ldx=1, p=7, ws_bytes=1 << 30, ws=True, A=True,
+           X=True, rank=True, cons=True, piv=True):
+    return lib.linac_solve(_fake(1) if A else None, m, n, lda, _fake(2), k, ldb, p,
+                           _fake(3) if X else None, ldx, _fake(4) if rank else None,
+                           _fake(5) if piv else None, _fake(6) if cons else None,
+                           _fake(7) if ws else None, ws_bytes, None, None)
+
+
+def test_solve_argument_errors(lib):
+    assert _solve(lib, m=-1) == INVALID
+    assert _solve(lib, lda=3) == INVALID
+    assert _solve(lib, k=2, ldb=1) == INVALID
+    assert _solve(lib, k=2, ldb=2, ldx=1) == INVALID
+    assert _solve(lib, A=False) == INVALID
+    assert _solve(lib, X=False) == INVALID
+    assert _solve(lib, rank=False) == INVALID
+    assert _solve(lib, cons=False) == INVALID
+    assert _solve(lib, piv=False) == INVALID
+    assert _solve(lib, p=0) == UNSUP
+    assert _solve(lib, p=(1 << 31) + 11) == UNSUP
+    assert _solve(lib, p=9) == NOTPRIME
+    assert _solve(lib, p=561) == NOTPRIME
+    assert _solve(lib, ws=False) == WS
+    assert _solve(lib, ws_bytes=16) == WS
+    assert _solve(lib, m=1 << 31) == NOMEM
+
+
+def test_rref_argument_errors(lib):
+    f = _fake
+    assert lib.linac_rref(f(1), -1, 3, 3, 7, f(2), f(3), f(4), 1 << 20, None, None) == INVALID
+    assert lib.linac_rref(f(1), 3, 3, 2, 7, f(2), f(3), f(4), 1 << 20, None, None) == INVALID
+    assert lib.linac_rref(None, 3, 3, 3, 7, f(2), f(3), f(4), 1 << 20, None, None) == INVALID
+    assert lib.linac_rref(f(1), 3, 3, 3, 7, None, f(3), f(4), 1 << 20, None, None) == INVALID
+    assert lib.linac_rref(f(1), 3, 3, 3, 15, f(2), f(3), f(4), 1 << 20, None, None) == NOTPRIME
+    assert lib.linac_rref(f(1), 3, 3, 3, 7, f(2), f(3), f(4), 8, None, None) == WS
+
+
+def test_workspace_queries(lib):
+    sz = ctypes.c_size_t()
+    assert lib.linac_solve_workspace(8192, 8192, 16, None, ctypes.byref(sz)) == OK
+    ld = (8192 + 16 + 63) // 64 * 64
+    assert sz.value >= 8192 * ld * 4
+    assert lib.linac_solve_workspace(-1, 3, 3, None, ctypes.byref(sz)) == INVALID
+    assert lib.linac_rref_workspace(0, 0, None, ctypes.byref(sz)) == OK
+    assert lib.linac_rref_workspace(5, 5, None, None) == INVALID
+
+
+def test_binding_fails_loudly_without_gpu():
+    """No CPU fallback: without a visible GPU the binding raises."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    with pytest.raises(RuntimeError):
+        lx.solve(np.eye(3, dtype=np.uint32), np.ones((3, 1), dtype=np.uint32), 7)
