@@ -170,6 +170,20 @@ def bench_dense(args):
     return rec
 
 
+def copy_calibration(mib: int = 1024, reps: int = 3):
+    """A plain device copy of a known size, for scaling the FETCH_SIZE /
+    WRITE_SIZE hardware counters into bytes (run it under the same rocprofv3
+    --pmc command as the kernel being measured)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.int32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 4, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,7 +193,12 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="resize the dense workload")
     ap.add_argument("--path", default="plain", choices=["plain", "int8", "auto"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
