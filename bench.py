@@ -109,14 +109,16 @@ def bench_dense(args):
            torch.empty(min(m, n), dtype=torch.int32, device=dev),
            torch.empty(k, dtype=torch.uint8, device=dev))
     path = {"plain": lx.PATH_PLAIN, "int8": lx.PATH_BLOCKED_INT8, "auto": lx.PATH_AUTO}[args.path]
-    ws = torch.empty(lx.solve_workspace_bytes(m, n, k, path), dtype=torch.uint8, device=dev)
+    ws = torch.empty(lx.solve_workspace_bytes(m, n, k, path, args.panel), dtype=torch.uint8,
+                     device=dev)
     stream = torch.cuda.current_stream()
     timer = lx.HipTimer()
     launches = ctypes.c_int64(0)
 
     def step(timed):
         lx.solve(At, Bt, p, path=path, out=out, workspace=ws, stream=stream,
-                 events=timer if timed else None, launches=launches if timed else None)
+                 events=timer if timed else None, launches=launches if timed else None,
+                 panel_width=args.panel)
 
     for _ in range(args.warmup):
         step(False)
@@ -192,6 +194,7 @@ def main():
     ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
     ap.add_argument("--n", type=int, default=None, help="resize the dense workload")
     ap.add_argument("--path", default="plain", choices=["plain", "int8", "auto"])
+    ap.add_argument("--panel", type=int, default=0, help="blocked panel width (0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")

@@ -200,7 +200,8 @@ class HipTimer:
 # ---------------------------------------------------------------------------
 
 def rref(A, p: int, *, inplace: bool = False, path: int = PATH_AUTO, validate: bool = False,
-         verbose: bool = False, stream=None, events: HipTimer | None = None, launches=None):
+         verbose: bool = False, stream=None, events: HipTimer | None = None, launches=None,
+         panel_width: int = 0):
     """RREF of A over F_p.  Returns (R, rank, pivots) as device tensors (R int32
     m x n, rank int32[1], pivots int32[min(m, n)], ascending, -1 padded)."""
     torch = _torch()
@@ -212,7 +213,7 @@ def rref(A, p: int, *, inplace: bool = False, path: int = PATH_AUTO, validate: b
     m, n = At.shape
     rank = torch.zeros(1, dtype=torch.int32, device=dev)
     pivots = torch.empty(min(m, n), dtype=torch.int32, device=dev)
-    o = _opts(path, 0, validate, verbose, events, launches)
+    o = _opts(path, panel_width, validate, verbose, events, launches)
     need = ctypes.c_size_t()
     _check(lib.linac_rref_workspace(m, n, ctypes.byref(o), ctypes.byref(need)), "rref_workspace")
     ws = _workspace(torch, need.value, dev)
@@ -236,7 +237,8 @@ def row_reduce(matrix, field_characteristic: int = 0, verbose: bool = False, **k
 
 
 def solve(A, B, p: int, *, path: int = PATH_AUTO, validate: bool = False, verbose: bool = False,
-          stream=None, events: HipTimer | None = None, launches=None, out=None, workspace=None):
+          stream=None, events: HipTimer | None = None, launches=None, out=None, workspace=None,
+          panel_width: int = 0):
     """Solve A X = B over F_p (Sec. 5.2).  Returns (X, rank, pivots, consistent).
 
     numpy in -> numpy out (rank as int); torch in -> device tensors out.
@@ -260,7 +262,7 @@ def solve(A, B, p: int, *, path: int = PATH_AUTO, validate: bool = False, verbos
         cons = torch.empty(k, dtype=torch.uint8, device=dev)
     else:
         X, rank, pivots, cons = out
-    o = _opts(path, 0, validate, verbose, events, launches)
+    o = _opts(path, panel_width, validate, verbose, events, launches)
     need = ctypes.c_size_t()
     _check(lib.linac_solve_workspace(m, n, k, ctypes.byref(o), ctypes.byref(need)),
            "solve_workspace")
@@ -276,9 +278,10 @@ def solve(A, B, p: int, *, path: int = PATH_AUTO, validate: bool = False, verbos
     return X, rank, pivots, cons
 
 
-def solve_workspace_bytes(m: int, n: int, k: int, path: int = PATH_AUTO) -> int:
+def solve_workspace_bytes(m: int, n: int, k: int, path: int = PATH_AUTO,
+                          panel_width: int = 0) -> int:
     lib = _load()
-    o = _opts(path)
+    o = _opts(path, panel_width)
     need = ctypes.c_size_t()
     _check(lib.linac_solve_workspace(m, n, k, ctypes.byref(o), ctypes.byref(need)),
            "solve_workspace")

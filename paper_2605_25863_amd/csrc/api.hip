@@ -65,9 +65,46 @@ linac_status check_field(uint32_t p) {
     return is_prime_u32(p) ? LINAC_OK : LINAC_E_NOT_PRIME;
 }
 
-int effective_path(const linac_opts* opts) {
+constexpr int32_t kDefaultPanel = 256;
+constexpr int64_t kBlockedMinSize = 1024;
+
+// AUTO: the plain path for small systems, the int8-MFMA blocked path from
+// min(m, n) >= 1024 on.  Depends only on the shape so that the workspace query
+// and the call agree.
+int choose_path(const linac_opts* opts, int64_t m, int64_t n) {
     int path = opts ? opts->path : LINAC_PATH_AUTO;
-    return path;
+    if (path != LINAC_PATH_AUTO) return path;
+    return (m < n ? m : n) >= kBlockedMinSize ? LINAC_PATH_BLOCKED_INT8 : LINAC_PATH_PLAIN;
+}
+
+int32_t panel_width(const linac_opts* opts) {
+    int32_t w = opts && opts->panel_width > 0 ? opts->panel_width : kDefaultPanel;
+    return w;
+}
+
+bool panel_ok(int32_t w) { return w >= 32 && w <= 512 && w % 32 == 0; }
+
+linac_status path_workspace(int path, int64_t m, int64_t n, int64_t k, const linac_opts* opts,
+                            size_t* bytes) {
+    if (path == LINAC_PATH_PLAIN) {
+        *bytes = plain_workspace(m, n, k);
+        return LINAC_OK;
+    }
+    if (path == LINAC_PATH_BLOCKED_INT8) {
+        int32_t w = panel_width(opts);
+        if (!panel_ok(w)) return LINAC_E_INVALID_ARG;
+        *bytes = blocked_workspace(m, n, k, w);
+        return LINAC_OK;
+    }
+    return LINAC_E_UNSUPPORTED;
+}
+
+// Elimination on an already prepared workspace; on return `a` describes the
+// bookkeeping the extraction kernels read.
+hipError_t run_path(int path, void* ws, int64_t m, int64_t n, int64_t k, PlainArgs& a,
+                    const linac_opts* opts, hipStream_t s) {
+    if (path == LINAC_PATH_PLAIN) return plain_eliminate(a, opts, s);
+    return blocked_eliminate(ws, m, n, k, panel_width(opts), a, opts, s);
 }
 
 bool size_ok(int64_t m, int64_t n, int64_t k) {
@@ -119,9 +156,7 @@ linac_status linac_check_prime(uint32_t p) { return check_field(p); }
 linac_status linac_rref_workspace(int64_t m, int64_t n, const linac_opts* opts, size_t* bytes) {
     if (!bytes || m < 0 || n < 0) return LINAC_E_INVALID_ARG;
     if (!size_ok(m, n, 0)) return LINAC_E_NOMEM;
-    (void)opts;
-    *bytes = plain_workspace(m, n, 0);
-    return LINAC_OK;
+    return path_workspace(choose_path(opts, m, n), m, n, 0, opts, bytes);
 }
 
 linac_status linac_rref(uint32_t* A, int64_t m, int64_t n, int64_t lda, uint32_t p, int32_t* rank,
@@ -135,9 +170,10 @@ linac_status linac_rref(uint32_t* A, int64_t m, int64_t n, int64_t lda, uint32_t
     linac_status st = check_field(p);
     if (st != LINAC_OK) return st;
     if (!size_ok(m, n, 0)) return LINAC_E_NOMEM;
-    int path = effective_path(opts);
-    if (path != LINAC_PATH_AUTO && path != LINAC_PATH_PLAIN) return LINAC_E_UNSUPPORTED;
-    size_t need = plain_workspace(m, n, 0);
+    int path = choose_path(opts, m, n);
+    size_t need = 0;
+    st = path_workspace(path, m, n, 0, opts, &need);
+    if (st != LINAC_OK) return st;
     if (!ws || ws_bytes < need) return LINAC_E_WORKSPACE;
 
     PlainArgs a;
@@ -148,10 +184,10 @@ linac_status linac_rref(uint32_t* A, int64_t m, int64_t n, int64_t lda, uint32_t
         if (st != LINAC_OK) return st;
     }
     if (opts && opts->verbose)
-        fprintf(stderr, "[linac] rref plain m=%lld n=%lld p=%u ld=%lld\n", (long long)m,
-                (long long)n, p, (long long)a.ld);
+        fprintf(stderr, "[linac] rref path=%d m=%lld n=%lld p=%u ld=%lld panel=%d\n", path,
+                (long long)m, (long long)n, p, (long long)a.ld, panel_width(opts));
     hipError_t e = plain_prepare(a, A, lda, nullptr, 1, (int32_t)n, 0, s);
-    if (e == hipSuccess) e = plain_eliminate(a, opts, s);
+    if (e == hipSuccess) e = run_path(path, ws, m, n, 0, a, opts, s);
     if (e == hipSuccess) e = plain_finish_rref(a, A, lda, rank, pivots, s);
     return e == hipSuccess ? LINAC_OK : hip_fail(e);
 }
@@ -160,9 +196,7 @@ linac_status linac_solve_workspace(int64_t m, int64_t n, int64_t k, const linac_
                                    size_t* bytes) {
     if (!bytes || m < 0 || n < 0 || k < 0) return LINAC_E_INVALID_ARG;
     if (!size_ok(m, n, k)) return LINAC_E_NOMEM;
-    (void)opts;
-    *bytes = plain_workspace(m, n, k);
-    return LINAC_OK;
+    return path_workspace(choose_path(opts, m, n), m, n, k, opts, bytes);
 }
 
 linac_status linac_solve(const uint32_t* A, int64_t m, int64_t n, int64_t lda, const uint32_t* B,
@@ -181,9 +215,10 @@ linac_status linac_solve(const uint32_t* A, int64_t m, int64_t n, int64_t lda, c
     linac_status st = check_field(p);
     if (st != LINAC_OK) return st;
     if (!size_ok(m, n, k)) return LINAC_E_NOMEM;
-    int path = effective_path(opts);
-    if (path != LINAC_PATH_AUTO && path != LINAC_PATH_PLAIN) return LINAC_E_UNSUPPORTED;
-    size_t need = plain_workspace(m, n, k);
+    int path = choose_path(opts, m, n);
+    size_t need = 0;
+    st = path_workspace(path, m, n, k, opts, &need);
+    if (st != LINAC_OK) return st;
     if (!ws || ws_bytes < need) return LINAC_E_WORKSPACE;
 
     PlainArgs a;
@@ -195,10 +230,11 @@ linac_status linac_solve(const uint32_t* A, int64_t m, int64_t n, int64_t lda, c
         if (st != LINAC_OK) return st;
     }
     if (opts && opts->verbose)
-        fprintf(stderr, "[linac] solve plain m=%lld n=%lld k=%lld p=%u ld=%lld\n", (long long)m,
-                (long long)n, (long long)k, p, (long long)a.ld);
+        fprintf(stderr, "[linac] solve path=%d m=%lld n=%lld k=%lld p=%u ld=%lld panel=%d\n",
+                path, (long long)m, (long long)n, (long long)k, p, (long long)a.ld,
+                panel_width(opts));
     hipError_t e = plain_prepare(a, A, lda, B, ldb, (int32_t)n, (int32_t)k, s);
-    if (e == hipSuccess) e = plain_eliminate(a, opts, s);
+    if (e == hipSuccess) e = run_path(path, ws, m, n, k, a, opts, s);
     if (e == hipSuccess) e = plain_finish_solve(a, (int32_t)n, (int32_t)k, X, ldx, rank, pivots,
                                                 consistent, s);
     return e == hipSuccess ? LINAC_OK : hip_fail(e);

@@ -1,0 +1,374 @@
+// Blocked Gauss-Jordan elimination over F_p with an exact mod-p GEMM on MFMA.
+//
+// The paper finds its kernel bound by memory bandwidth and notes that larger
+// gains need more arithmetic intensity (Sec. 3.4, Sec. 4.1.1).  Processing w
+// pivot columns at a time turns the row update into a matrix product.
+//
+// Panel step for pivot columns [j0, j0 + w):
+//  1. The panel columns of every row are copied to a side buffer PR next to a
+//     w-column block E that starts at zero.
+//  2. The fused step kernel of the plain path reduces PR column by column (all
+//     rows, Gauss-Jordan).  When row q becomes the pivot of local column s it
+//     carries an implicit 1 in E[q][s], so the row operations applied to E
+//     record, for every row r, the coefficients of its final value in terms of
+//     the panel's pivot rows as they were at the panel start:
+//        final_r = delta_r * row_r + E[r] . X_S,
+//     with delta_r = 0 for the panel's pivot rows and 1 otherwise.  X_S holds
+//     the pivot rows' trailing parts at the panel start (row s of X_S belongs
+//     to the pivot of local column s; a free column gives a zero row).
+//  3. The trailing columns of all rows are updated by that one product.
+//
+// Exactness of the product on int8 MFMA.  Every residue is first centred,
+// x -> x - p when x > (p-1)/2, so |x| <= 2^30, then split into four signed
+// base-256 digits in [-128, 127].  For y = X_S[k][c] the operand is
+// pre-scaled: y_l = 256^l * y mod p for l = 0..3, each centred and split into
+// digits b_{l,l'}.  With a_l the digits of E[r][k],
+//    E[r][k] * y == sum_l a_l * y_l == sum_{l'} 256^{l'} sum_l a_l * b_{l,l'}  (mod p),
+// so four int32 accumulators S_{l'} = sum_k sum_l a_l b_{l,l'} suffice (16
+// int8 products per mod-p product).  |S_{l'}| <= 4 * K * 2^14 = K * 2^16 < 2^31
+// for K < 2^15, and T = S_0 + 2^8 S_1 + 2^16 S_2 + 2^24 S_3 stays below 2^50 in
+// magnitude for K <= 512, so it is exact in FP64 and one reduction mod p ends
+// the panel.  For p < 2^21 the centred residues are below 2^20 and the product
+// can instead run on FP64 MFMA directly: every partial sum is below K * 2^40,
+// exact while K <= 8192.
+#include "internal.h"
+
+namespace linac {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kTileRows = 32;
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ int32_t centre(uint32_t v, uint32_t p) {
+    return v > (p - 1) / 2 ? (int32_t)v - (int32_t)p : (int32_t)v;
+}
+
+// Four signed base-256 digits of x (|x| <= 2^30), least significant first.
+__device__ __forceinline__ void digits4(int32_t x, int8_t d[4]) {
+    for (int l = 0; l < 4; ++l) {
+        int8_t lo = (int8_t)(x & 0xff);
+        d[l] = lo;
+        x = (x - lo) >> 8;
+    }
+}
+
+// Copy the panel columns into PR (E block zero) and search the first column.
+__global__ __launch_bounds__(kThreads) void panel_extract_kernel(PlainArgs w, uint32_t* PR,
+                                                                 int64_t ldpr, int32_t j0,
+                                                                 int32_t wj) {
+    __shared__ int s_row[4];
+    __shared__ uint32_t s_val[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t c0 = (int64_t)blockIdx.y * 256 + lane * 4;
+    const int row0 = blockIdx.x * kTileRows + wave * 8;
+    int best = INT32_MAX;
+    uint32_t bestv = 0;
+    for (int rr = 0; rr < 8; ++rr) {
+        const int r = row0 + rr;
+        if (r >= w.m || c0 >= ldpr) continue;
+        uint32_t v[4];
+        for (int e = 0; e < 4; ++e) {
+            const int64_t c = c0 + e;
+            v[e] = c < wj ? w.W[(int64_t)r * w.ld + j0 + c] : 0u;
+        }
+        *(uint4*)(PR + (int64_t)r * ldpr + c0) = make_uint4(v[0], v[1], v[2], v[3]);
+        if (blockIdx.y == 0 && lane == 0) {
+            w.fcol[0][r] = v[0];
+            if (v[0] != 0 && w.is_piv[r] == 0 && r < best) {
+                best = r;
+                bestv = v[0];
+            }
+        }
+    }
+    if (blockIdx.y == 0) {
+        // same reduction as the plain path's look-ahead
+        best = __shfl(best, 0);
+        bestv = __shfl(bestv, 0);
+        if (lane == 0) {
+            s_row[wave] = best;
+            s_val[wave] = bestv;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int r = s_row[0];
+            uint32_t v = s_val[0];
+            for (int q = 1; q < 4; ++q)
+                if (s_row[q] < r) {
+                    r = s_row[q];
+                    v = s_val[q];
+                }
+            if (r != INT32_MAX) {
+                unsigned long long* slot = &w.slots[j0];
+                unsigned long long cur =
+                    __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((cur >> 32) > (unsigned long long)r)
+                    atomicMin(slot, ((unsigned long long)r << 32) | inv_mod(v, w.F.p));
+            }
+        }
+    }
+}
+
+// Apply the deferred normalisation of the panel's last pivot row to all of PR.
+__global__ void panel_resolve_kernel(PlainArgs w, uint32_t* PR, int64_t ldpr, int32_t j0,
+                                     int32_t wj) {
+    const unsigned long long s = w.slots[j0 + wj - 1];
+    if (s == kNoPivot) return;
+    const int q = (int)(s >> 32);
+    const uint32_t inv = (uint32_t)s;
+    for (int c = threadIdx.x; c < 2 * wj; c += blockDim.x) {
+        uint32_t* x = PR + (int64_t)q * ldpr + c;
+        *x = mul_mod(*x, inv, w.F);
+    }
+}
+
+// B operand: X_S (pivot rows' trailing parts at the panel start), pre-scaled by
+// 256^l and split into digits, stored in the lane order of the 32x32x32 int8
+// MFMA: fragment (cb, kb, plane = 4*l + l') is 64 lanes x 16 bytes; lane L holds
+// column cb*32 + L%32 and rows k = kb*32 + 16*(L/32) + i, i = 0..15.
+__global__ void build_b_kernel(PlainArgs w, int32_t j0, int32_t wj, int64_t col0, int64_t N,
+                               int32_t KB, int64_t NB, int8_t* Bfrag, uint4 scale) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= NB * KB * 64) return;
+    const int L = (int)(gid & 63);
+    const int64_t t = gid >> 6;
+    const int kb = (int)(t % KB);
+    const int64_t cb = t / KB;
+    const int64_t col = cb * 32 + (L & 31);
+    const uint32_t p = w.F.p;
+    const uint32_t sc[4] = {scale.x, scale.y, scale.z, scale.w};
+    int8_t out[16][16];  // [plane][i]
+    for (int i = 0; i < 16; ++i) {
+        const int k = kb * 32 + 16 * (L >> 5) + i;
+        uint32_t y = 0;
+        if (k < wj && col < N) {
+            const unsigned long long s = w.slots[j0 + k];
+            if (s != kNoPivot) y = w.W[(int64_t)(s >> 32) * w.ld + col0 + col];
+        }
+        for (int l = 0; l < 4; ++l) {
+            const uint32_t yl = l == 0 ? y : mul_mod(y, sc[l], w.F);
+            int8_t d[4];
+            digits4(centre(yl, p), d);
+            for (int lp = 0; lp < 4; ++lp) out[4 * l + lp][i] = d[lp];
+        }
+    }
+    int8_t* base = Bfrag + ((cb * KB + kb) * 16) * 1024 + L * 16;
+    for (int pl = 0; pl < 16; ++pl) {
+        v4i v;
+        __builtin_memcpy(&v, out[pl], 16);
+        *(v4i*)(base + pl * 1024) = v;
+    }
+}
+
+// A operand: E (PR columns [wj, 2wj)), split into digits, in MFMA lane order:
+// fragment (rb, kb, l) is 64 lanes x 16 bytes; lane L holds row rb*32 + L%32 and
+// k = kb*32 + 16*(L/32) + i.
+__global__ void build_a_kernel(PlainArgs w, const uint32_t* PR, int64_t ldpr, int32_t wj,
+                               int32_t KB, int64_t MB, int8_t* Afrag) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= MB * KB * 64) return;
+    const int L = (int)(gid & 63);
+    const int64_t t = gid >> 6;
+    const int kb = (int)(t % KB);
+    const int64_t rb = t / KB;
+    const int64_t row = rb * 32 + (L & 31);
+    const uint32_t p = w.F.p;
+    int8_t out[4][16];
+    for (int i = 0; i < 16; ++i) {
+        const int k = kb * 32 + 16 * (L >> 5) + i;
+        uint32_t e = (row < w.m && k < wj) ? PR[row * ldpr + wj + k] : 0u;
+        int8_t d[4];
+        digits4(centre(e, p), d);
+        for (int l = 0; l < 4; ++l) out[l][i] = d[l];
+    }
+    int8_t* base = Afrag + ((rb * KB + kb) * 4) * 1024 + L * 16;
+    for (int l = 0; l < 4; ++l) {
+        v4i v;
+        __builtin_memcpy(&v, out[l], 16);
+        *(v4i*)(base + l * 1024) = v;
+    }
+}
+
+// T = S0 + 2^8 S1 + 2^16 S2 + 2^24 S3 (exact in FP64) reduced mod p.
+__device__ __forceinline__ uint32_t fold_mod(int32_t s0, int32_t s1, int32_t s2, int32_t s3,
+                                             const FieldConst& F) {
+    double T = __fma_rn(16777216.0, (double)s3,
+                        __fma_rn(65536.0, (double)s2, __fma_rn(256.0, (double)s1, (double)s0)));
+    double q = floor(T * F.pinv);
+    double r = __fma_rn(-q, F.dp, T);
+    if (r < 0.0) r += F.dp;
+    if (r >= F.dp) r -= F.dp;
+    if (r < 0.0) r += F.dp;
+    return (uint32_t)r;
+}
+
+// Trailing update C = delta * C + E . X_S (mod p) on int8 MFMA.
+// Block: 4 waves; wave v owns rows [(4*bx + v)*32, +32) and the block's 64
+// columns (two 32-column blocks).  The B fragments of one k-block (2 x 16 planes
+// x 1 KB) are staged in LDS and shared by the 4 waves; A fragments are read
+// straight from memory (each wave needs only its own rows).
+__global__ __launch_bounds__(kThreads) void gemm_i8_kernel(PlainArgs w, int64_t col0, int64_t N,
+                                                           const int8_t* Afrag,
+                                                           const int8_t* Bfrag, int32_t KB,
+                                                           int32_t j0, int32_t wj) {
+    __shared__ v4i sB[2 * 16 * 64];  // 32 KB
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t rb = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t cb0 = (int64_t)blockIdx.y * 2;
+    v16i acc[2][4];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 4; ++b)
+            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0;
+    const int64_t NB = ceil_div(N, 32);
+    for (int kb = 0; kb < KB; ++kb) {
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < 2 * 16 * 64; idx += kThreads) {
+            const int cbi = idx / (16 * 64);
+            const int64_t cb = cb0 + cbi;
+            v4i v = {0, 0, 0, 0};
+            if (cb < NB)
+                v = *(const v4i*)(Bfrag + ((cb * KB + kb) * 16) * 1024 + (idx % (16 * 64)) * 16);
+            sB[idx] = v;
+        }
+        __syncthreads();
+        v4i af[4];
+        for (int l = 0; l < 4; ++l)
+            af[l] = *(const v4i*)(Afrag + ((rb * KB + kb) * 4 + l) * 1024 + lane * 16);
+        for (int cbi = 0; cbi < 2; ++cbi) {
+            for (int l = 0; l < 4; ++l) {
+                for (int lp = 0; lp < 4; ++lp) {
+                    const v4i bf = sB[(cbi * 16 + 4 * l + lp) * 64 + lane];
+                    acc[cbi][lp] =
+                        __builtin_amdgcn_mfma_i32_32x32x32_i8(af[l], bf, acc[cbi][lp], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // epilogue: 32x32 accumulator layout: lane L holds column L%32 and rows
+    // 8*(r/4) + 4*(L/32) + r%4 for r = 0..15
+    for (int cbi = 0; cbi < 2; ++cbi) {
+        const int64_t col = (cb0 + cbi) * 32 + (lane & 31);
+        if (col >= N) continue;
+        for (int r = 0; r < 16; ++r) {
+            const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            if (row >= w.m) continue;
+            const uint32_t t = fold_mod(acc[cbi][0][r], acc[cbi][1][r], acc[cbi][2][r],
+                                        acc[cbi][3][r], w.F);
+            uint32_t* c = w.W + row * w.ld + col0 + col;
+            const int rc = w.rowcol[row];
+            const bool fresh = rc >= j0 && rc < j0 + wj;  // a pivot row of this panel
+            *c = fresh ? t : add_mod(*c, t, w.F.p);
+        }
+    }
+}
+
+// Write the reduced panel back into W; pivot columns become unit vectors.
+__global__ void panel_writeback_kernel(PlainArgs w, const uint32_t* PR, int64_t ldpr, int32_t j0,
+                                       int32_t wj) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)w.m * wj) return;
+    const int64_t r = gid / wj;
+    const int js = (int)(gid % wj);
+    const int s = w.colpiv[j0 + js];
+    uint32_t v;
+    if (s >= 0) v = (w.pivrow[s] == r) ? 1u : 0u;
+    else v = PR[r * ldpr + js];
+    w.W[r * w.ld + j0 + js] = v;
+}
+
+struct Blocked {
+    PlainArgs w;   // the working matrix and the bookkeeping (shared with the plain path)
+    uint32_t* PR;
+    int64_t ldpr;
+    int8_t* Afrag;
+    int8_t* Bfrag;
+    int32_t panel;
+    int32_t KB;
+};
+
+size_t carve_blocked(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, Blocked* b) {
+    const size_t base = plain_workspace(m, n, k);
+    Carver c(ws ? (char*)ws + base : nullptr);
+    const int64_t ldpr = round_up(2 * (int64_t)panel, 64);
+    const int64_t Kp = round_up(panel, 32);
+    const int64_t Mp = round_up(m > 0 ? m : 1, 128);
+    const int64_t Np = round_up(n + k > 0 ? n + k : 1, 64);
+    uint32_t* PR = c.take<uint32_t>(m * ldpr);
+    int8_t* A = c.take<int8_t>(Mp * Kp * 4);
+    int8_t* B = c.take<int8_t>(Np * Kp * 16);
+    if (b) {
+        plain_carve(ws, m, n, k, b->w);
+        b->PR = PR;
+        b->ldpr = ldpr;
+        b->Afrag = A;
+        b->Bfrag = B;
+        b->panel = panel;
+        b->KB = (int32_t)(Kp / 32);
+    }
+    return base + c.off + 256;
+}
+
+}  // namespace
+
+size_t blocked_workspace(int64_t m, int64_t n, int64_t k, int32_t panel) {
+    return carve_blocked(nullptr, m, n, k, panel, nullptr);
+}
+
+hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel,
+                             PlainArgs& out, const linac_opts* opts, hipStream_t s) {
+    Blocked b;
+    carve_blocked(ws, m, n, k, panel, &b);
+    b.w.F = out.F;
+    b.w.resolved = 1;
+    out = b.w;
+    PlainArgs& w = b.w;
+    if (m == 0) return hipSuccess;
+    const int64_t ncols = n + k;
+    const unsigned tiles = (unsigned)ceil_div(m, kTileRows);
+    int64_t gemm_launches = 0;
+    hipError_t e = hipSuccess;
+    for (int32_t j0 = 0; j0 < n && e == hipSuccess; j0 += panel) {
+        const int32_t wj = (int32_t)(n - j0 < panel ? n - j0 : panel);
+        const int64_t col0 = j0 + wj;
+        const int64_t N = ncols - col0;
+        hipLaunchKernelGGL(panel_extract_kernel, dim3(tiles, (unsigned)ceil_div(b.ldpr, 256)),
+                           dim3(kThreads), 0, s, w, b.PR, b.ldpr, j0, wj);
+        PlainArgs pa = w;
+        pa.W = b.PR;
+        pa.ld = b.ldpr;
+        pa.ncols = 2 * wj;
+        pa.nsearch = wj;
+        pa.coloff = j0;
+        pa.einject = wj;
+        for (int32_t js = 0; js < wj && e == hipSuccess; ++js)
+            e = launch_gj_step(pa, js, wj + js + 1, s);
+        hipLaunchKernelGGL(panel_resolve_kernel, dim3(1), dim3(256), 0, s, w, b.PR, b.ldpr, j0, wj);
+        if (N > 0) {
+            const int32_t KB = (int32_t)ceil_div(wj, 32);
+            const int64_t NB = ceil_div(N, 32);
+            const int64_t MB = ceil_div(m, 128) * 4;
+            uint32_t sc[4] = {1, 0, 0, 0};
+            for (int l = 1; l < 4; ++l) sc[l] = (uint32_t)(((uint64_t)sc[l - 1] * 256u) % w.F.p);
+            uint4 scale = make_uint4(sc[0], sc[1], sc[2], sc[3]);
+            hipLaunchKernelGGL(build_b_kernel, dim3((unsigned)ceil_div(NB * KB * 64, 256)), dim3(256),
+                               0, s, w, j0, wj, col0, N, KB, NB, b.Bfrag, scale);
+            hipLaunchKernelGGL(build_a_kernel, dim3((unsigned)ceil_div(MB * KB * 64, 256)), dim3(256),
+                               0, s, w, b.PR, b.ldpr, wj, KB, MB, b.Afrag);
+            if (opts && opts->ev_begin && gemm_launches == 0) (void)hipEventRecord(opts->ev_begin, s);
+            hipLaunchKernelGGL(gemm_i8_kernel, dim3((unsigned)ceil_div(m, 128), (unsigned)ceil_div(N, 64)),
+                               dim3(kThreads), 0, s, w, col0, N, b.Afrag, b.Bfrag, KB, j0, wj);
+            ++gemm_launches;
+        }
+        hipLaunchKernelGGL(panel_writeback_kernel, dim3((unsigned)ceil_div(m * wj, 256)), dim3(256),
+                           0, s, w, b.PR, b.ldpr, j0, wj);
+        if (e == hipSuccess) e = hipGetLastError();
+    }
+    if (opts && opts->ev_end && gemm_launches > 0) (void)hipEventRecord(opts->ev_end, s);
+    if (opts && opts->dominant_launches) *opts->dominant_launches = gemm_launches;
+    return e == hipSuccess ? hipGetLastError() : e;
+}
+
+}  // namespace linac

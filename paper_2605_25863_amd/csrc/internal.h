@@ -12,8 +12,8 @@ namespace linac {
 // Sentinel of a per-column pivot slot: no pivot found (yet).
 static constexpr unsigned long long kNoPivot = ~0ull;
 
-inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
-inline int64_t ceil_div(int64_t x, int64_t m) { return (x + m - 1) / m; }
+__host__ __device__ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+__host__ __device__ inline int64_t ceil_div(int64_t x, int64_t m) { return (x + m - 1) / m; }
 
 // Carve aligned regions out of a caller-owned workspace.  With base == NULL it
 // only measures.
@@ -39,15 +39,19 @@ struct PlainArgs {
     uint32_t* W;
     int64_t ld;
     int32_t m;
-    int32_t ncols;    // n + k
+    int32_t ncols;    // n + k (columns that exist in W)
     int32_t nsearch;  // n: pivots are searched in columns [0, nsearch)
-    int32_t pad;
+    int32_t coloff;   // global column of local column 0 (bookkeeping arrays are global)
+    int32_t einject;  // >= 0: local column where the transform block E starts; the pivot
+                      // row of local column j carries an implicit 1 at einject + j
+    int32_t resolved; // 1: no deferred normalisation is left in W at the end
     uint32_t* fcol[2];           // column j of the working matrix as of step j (ping-pong)
     uint32_t* is_piv;            // 1 for rows already chosen as pivots
     unsigned long long* slots;   // per column: (pivot row << 32) | inverse of its head
     int32_t* pivrow;             // s-th pivot row
     int32_t* pivcol;             // s-th pivot column
     int32_t* colpiv;             // per column: s, or -1 for a free column
+    int32_t* rowcol;             // per row: its pivot column, or -1
     int32_t* state;              // [0] = rank so far
     uint32_t* incons;            // per right-hand side: 1 once a residual is non-zero
     FieldConst F;
@@ -55,6 +59,9 @@ struct PlainArgs {
 
 size_t plain_workspace(int64_t m, int64_t n, int64_t k);
 void plain_carve(void* ws, int64_t m, int64_t n, int64_t k, PlainArgs& a);
+
+// One Gauss-Jordan step for local pivot column j over local columns [.., ncols_eff).
+hipError_t launch_gj_step(const PlainArgs& a, int32_t j, int32_t ncols_eff, hipStream_t s);
 
 // Launch sequences (stream-ordered, no host synchronisation).
 hipError_t plain_prepare(const PlainArgs& a, const uint32_t* A, int64_t lda, const uint32_t* B,
@@ -64,6 +71,13 @@ hipError_t plain_finish_solve(const PlainArgs& a, int32_t n, int32_t k, uint32_t
                               int32_t* rank, int32_t* pivots, uint8_t* consistent, hipStream_t s);
 hipError_t plain_finish_rref(const PlainArgs& a, uint32_t* A, int64_t lda, int32_t* rank,
                              int32_t* pivots, hipStream_t s);
+
+// Blocked path (blocked.hip): workspace = the plain layout followed by the panel
+// buffer and the MFMA operand fragments.  `a` carries the field in and the
+// carved bookkeeping out (for the shared extraction kernels).
+size_t blocked_workspace(int64_t m, int64_t n, int64_t k, int32_t panel);
+hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel,
+                             PlainArgs& a, const linac_opts* opts, hipStream_t s);
 
 // Range check of residues: sets *flag to 1 when an entry is >= p.
 hipError_t launch_range_check(const uint32_t* M, int64_t rows, int64_t cols, int64_t ld, uint32_t p,

@@ -90,7 +90,10 @@ __global__ void plain_init_kernel(PlainArgs a, int32_t k) {
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = tid; i <= a.nsearch; i += stride) a.slots[i] = kNoPivot;
     for (int64_t i = tid; i < a.nsearch; i += stride) a.colpiv[i] = -1;
-    for (int64_t i = tid; i < a.m; i += stride) a.is_piv[i] = 0;
+    for (int64_t i = tid; i < a.m; i += stride) {
+        a.is_piv[i] = 0;
+        a.rowcol[i] = -1;
+    }
     for (int64_t i = tid; i < k; i += stride) a.incons[i] = 0;
     if (tid < 8) a.state[tid] = 0;
 }
@@ -129,17 +132,21 @@ __global__ __launch_bounds__(kThreads) void plain_pack_kernel(PlainArgs a, const
         block_candidate(wave, lane, 0, best, bestv, s_row, s_val, &a.slots[0], a.F.p);
 }
 
-// One Gauss-Jordan step for pivot column j (see the file comment).
+// One Gauss-Jordan step for local pivot column j (see the file comment).  Only
+// local columns below ncols_eff are touched (the blocked path's transform block
+// is still zero beyond the current step).
 template <bool kMersenne>
-__global__ __launch_bounds__(kThreads) void plain_step_kernel(PlainArgs a, int32_t j) {
+__global__ __launch_bounds__(kThreads) void plain_step_kernel(PlainArgs a, int32_t j,
+                                                              int32_t ncols_eff) {
     __shared__ int s_row[4];
     __shared__ uint32_t s_val[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const FieldConst F = a.F;
     const uint32_t p = F.p;
+    const int jg = a.coloff + j;
 
-    const unsigned long long sj = a.slots[j];
-    const unsigned long long sprev = j > 0 ? a.slots[j - 1] : kNoPivot;
+    const unsigned long long sj = a.slots[jg];
+    const unsigned long long sprev = j > 0 ? a.slots[jg - 1] : kNoPivot;
     const bool have_piv = sj != kNoPivot;
     const int q = have_piv ? (int)(sj >> 32) : -1;
     const uint32_t inv = (uint32_t)sj;
@@ -150,8 +157,9 @@ __global__ __launch_bounds__(kThreads) void plain_step_kernel(PlainArgs a, int32
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && have_piv) {
         int s = a.state[0];
         a.pivrow[s] = q;
-        a.pivcol[s] = j;
-        a.colpiv[j] = s;
+        a.pivcol[s] = jg;
+        a.colpiv[jg] = s;
+        a.rowcol[q] = jg;
         a.is_piv[q] = 1;
         a.state[0] = s + 1;
     }
@@ -160,15 +168,15 @@ __global__ __launch_bounds__(kThreads) void plain_step_kernel(PlainArgs a, int32
     const int cbase = j & ~63;
     const int64_t c0 = cbase + (int64_t)blockIdx.y * kChunkCols + lane * 4;
     const bool lane_on = c0 < a.ld;
+    const int64_t ecol = a.einject >= 0 ? (int64_t)a.einject + j : -1;
 
     // normalised pivot row entries for this lane's columns, and their quotients
     uint32_t pn[4] = {0u, 0u, 0u, 0u}, pq[4] = {0u, 0u, 0u, 0u};
     if (have_piv && lane_on) {
         uint4 v = *(const uint4*)(a.W + (int64_t)q * a.ld + c0);
-        pn[0] = mul_mod_t<kMersenne>(v.x, inv, F);
-        pn[1] = mul_mod_t<kMersenne>(v.y, inv, F);
-        pn[2] = mul_mod_t<kMersenne>(v.z, inv, F);
-        pn[3] = mul_mod_t<kMersenne>(v.w, inv, F);
+        uint32_t raw[4] = {v.x, v.y, v.z, v.w};
+        if (ecol >= c0 && ecol < c0 + 4) raw[ecol - c0] = 1u;  // the pivot row's own E entry
+        for (int e = 0; e < 4; ++e) pn[e] = mul_mod_t<kMersenne>(raw[e], inv, F);
         if constexpr (!kMersenne) {
             for (int e = 0; e < 4; ++e) pq[e] = shoup_quot(pn[e], F);
         }
@@ -176,6 +184,10 @@ __global__ __launch_bounds__(kThreads) void plain_step_kernel(PlainArgs a, int32
 
     const uint32_t* fcur = a.fcol[j & 1];
     const int row0 = blockIdx.x * kTileRows + wave * kRowsPerWave;
+    // the pivot row is read-only during this step; its E entry 1 is stored for the next
+    if (have_piv && ecol >= c0 && ecol < c0 + 4 && q >= row0 && q < row0 + kRowsPerWave)
+        a.W[(int64_t)q * a.ld + ecol] = 1u;
+    const bool col_on = lane_on && c0 < ncols_eff;
     uint4 x[kRowsPerWave];
     uint32_t f[kRowsPerWave];
     bool act[kRowsPerWave];
@@ -189,12 +201,12 @@ __global__ __launch_bounds__(kThreads) void plain_step_kernel(PlainArgs a, int32
         if (blockIdx.y != 0) on = on && (pend || (have_piv && f[rr] != 0));
         act[rr] = on;
         if (!have_piv) f[rr] = 0;
-        if (on && lane_on) x[rr] = *(const uint4*)(a.W + (int64_t)r * a.ld + c0);
+        if (on && col_on) x[rr] = *(const uint4*)(a.W + (int64_t)r * a.ld + c0);
         else x[rr] = make_uint4(0, 0, 0, 0);
     }
 #pragma unroll
     for (int rr = 0; rr < kRowsPerWave; ++rr) {
-        if (!act[rr] || !lane_on) continue;
+        if (!act[rr] || !col_on) continue;
         const int r = row0 + rr;
         uint32_t v[4] = {x[rr].x, x[rr].y, x[rr].z, x[rr].w};
         if (r == qpend) {
@@ -237,7 +249,8 @@ __global__ __launch_bounds__(kThreads) void plain_step_kernel(PlainArgs a, int32
                 }
             }
         }
-        block_candidate(wave, lane, src_lane, best, bestv, s_row, s_val, &a.slots[jn], p);
+        block_candidate(wave, lane, src_lane, best, bestv, s_row, s_val, &a.slots[a.coloff + jn],
+                        p);
     }
 }
 
@@ -263,7 +276,7 @@ __device__ __forceinline__ uint32_t logical(const PlainArgs& a, int r, int64_t c
 __device__ __forceinline__ void last_pending(const PlainArgs& a, int& qlast, uint32_t& slast) {
     qlast = -1;
     slast = 1;
-    if (a.nsearch > 0) {
+    if (a.nsearch > 0 && !a.resolved) {
         unsigned long long s = a.slots[a.nsearch - 1];
         if (s != kNoPivot) {
             qlast = (int)(s >> 32);
@@ -346,6 +359,7 @@ size_t plain_workspace(int64_t m, int64_t n, int64_t k) {
     c.take<int32_t>(n);
     c.take<int32_t>(n);
     c.take<int32_t>(n);
+    c.take<int32_t>(m);
     c.take<int32_t>(8);
     c.take<uint32_t>(k > 0 ? k : 1);
     (void)a;
@@ -363,12 +377,15 @@ void plain_carve(void* ws, int64_t m, int64_t n, int64_t k, PlainArgs& a) {
     a.pivrow = c.take<int32_t>(n);
     a.pivcol = c.take<int32_t>(n);
     a.colpiv = c.take<int32_t>(n);
+    a.rowcol = c.take<int32_t>(m);
     a.state = c.take<int32_t>(8);
     a.incons = c.take<uint32_t>(k > 0 ? k : 1);
     a.m = (int32_t)m;
     a.ncols = (int32_t)(n + k);
     a.nsearch = (int32_t)n;
-    a.pad = 0;
+    a.coloff = 0;
+    a.einject = -1;
+    a.resolved = 0;
 }
 
 hipError_t plain_prepare(const PlainArgs& a, const uint32_t* A, int64_t lda, const uint32_t* B,
@@ -383,21 +400,26 @@ hipError_t plain_prepare(const PlainArgs& a, const uint32_t* A, int64_t lda, con
     return hipGetLastError();
 }
 
+hipError_t launch_gj_step(const PlainArgs& a, int32_t j, int32_t ncols_eff, hipStream_t s) {
+    const unsigned tiles = (unsigned)ceil_div(a.m, kTileRows);
+    const int64_t cbase = j & ~63;
+    dim3 grid(tiles, (unsigned)ceil_div(ncols_eff - cbase, kChunkCols));
+    if (a.F.p == kMersenne31)
+        hipLaunchKernelGGL(plain_step_kernel<true>, grid, dim3(kThreads), 0, s, a, j, ncols_eff);
+    else
+        hipLaunchKernelGGL(plain_step_kernel<false>, grid, dim3(kThreads), 0, s, a, j, ncols_eff);
+    return hipGetLastError();
+}
+
 hipError_t plain_eliminate(const PlainArgs& a, const linac_opts* opts, hipStream_t s) {
     if (opts && opts->ev_begin) {
         hipError_t e = hipEventRecord(opts->ev_begin, s);
         if (e != hipSuccess) return e;
     }
     if (a.m > 0) {
-        const bool mers = a.F.p == kMersenne31;
-        const unsigned tiles = (unsigned)ceil_div(a.m, kTileRows);
         for (int32_t j = 0; j < a.nsearch; ++j) {
-            const int64_t cbase = j & ~63;
-            dim3 grid(tiles, (unsigned)ceil_div(a.ncols - cbase, kChunkCols));
-            if (mers)
-                hipLaunchKernelGGL(plain_step_kernel<true>, grid, dim3(kThreads), 0, s, a, j);
-            else
-                hipLaunchKernelGGL(plain_step_kernel<false>, grid, dim3(kThreads), 0, s, a, j);
+            hipError_t e = launch_gj_step(a, j, a.ncols, s);
+            if (e != hipSuccess) return e;
         }
     }
     if (opts && opts->ev_end) {

@@ -1,0 +1,146 @@
+"""GPU parity of the blocked path (panel Gauss-Jordan + exact int8-MFMA trailing
+product) against the CPU oracle, bit for bit.
+
+Panel widths are chosen so that panels are ragged (n not a multiple of the
+width), free columns fall inside panels, and the last panel is partial.  At the
+full n = 16384 size the solution is checked with the certificate A X = B on a
+seeded sample of rows (A is dense, so any wrong entry of X breaks almost every
+row) plus rank = n and pivots 0..n-1.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+import paper_2605_25863_amd as lx
+
+pytestmark = pytest.mark.gpu
+
+INT8 = lx.PATH_BLOCKED_INT8
+
+
+def _solve(A, B, p, panel, path=INT8):
+    import torch
+    At = torch.from_numpy(np.ascontiguousarray(A).astype(np.int32)).cuda()
+    Bt = torch.from_numpy(np.ascontiguousarray(B).astype(np.int32)).cuda()
+    m, n = A.shape
+    k = B.shape[1]
+    X = torch.empty((n, k), dtype=torch.int32, device="cuda")
+    rank = torch.zeros(1, dtype=torch.int32, device="cuda")
+    piv = torch.empty(min(m, n), dtype=torch.int32, device="cuda")
+    cons = torch.empty(k, dtype=torch.uint8, device="cuda")
+    lx.solve(At, Bt, p, path=path, out=(X, rank, piv, cons), panel_width=panel)
+    torch.cuda.synchronize()
+    r = int(rank.item())
+    return (X.cpu().numpy().astype(np.uint32), r, piv.cpu().numpy()[:r].astype(np.int64),
+            cons.cpu().numpy().astype(np.uint8))
+
+
+def _cmp(A, B, p, panel, tag):
+    got = _solve(A, B, p, panel)
+    ref = oracle.solve(A, B, p)
+    for name, g, r in zip(("X", "rank", "pivots", "consistent"), got, ref):
+        assert np.array_equal(np.asarray(g), np.asarray(r)), f"{tag}: {name} differs"
+
+
+def _cmp_rref(A, p, panel, tag):
+    import torch
+    R, rank, piv = lx.rref(A, p, path=INT8, panel_width=panel)
+    torch.cuda.synchronize()
+    Rr, rr, pr = oracle.rref(A, p)
+    r = int(rank.item())
+    assert r == rr, f"{tag}: rank"
+    assert np.array_equal(R.cpu().numpy().astype(np.uint32), Rr), f"{tag}: RREF differs"
+    assert np.array_equal(piv.cpu().numpy()[:r], pr), f"{tag}: pivots"
+
+
+@pytest.mark.parametrize("m,n,k,p,panel", [
+    (300, 300, 5, None, 64),
+    (300, 300, 3, workloads.MERSENNE31, 32),
+    (257, 333, 17, None, 96),
+    (500, 420, 0, 65521, 256),
+    (129, 700, 9, None, 128),
+    (600, 600, 8, None, 512),
+    (64, 64, 1, 2, 32),
+    (100, 100, 2, 3, 64),
+])
+def test_dense_panels(gpu, m, n, k, p, panel):
+    rng = np.random.default_rng(m * 31 + n + panel)
+    if p is None:
+        p = workloads.draw_prime31(rng)
+    A = workloads.uniform(rng, (m, n), p)
+    B = workloads.uniform(rng, (m, k), p)
+    tag = f"blocked m={m} n={n} k={k} p={p} panel={panel}"
+    print(tag, flush=True)
+    _cmp(A, B, p, panel, tag)
+    _cmp_rref(A, p, panel, tag)
+
+
+def test_structured(gpu):
+    rng = np.random.default_rng(77)
+    p = workloads.draw_prime31(rng)
+    # free columns inside panels, a zero block, duplicated columns
+    Z = workloads.uniform(rng, (330, 400), p)
+    Z[:, 30:45] = 0
+    Z[:, 100:140] = Z[:, 0:40]
+    Z[:, 255:260] = 0
+    B = workloads.uniform(rng, (330, 4), p)
+    B[:, 1] = oracle.matmul_mod(Z, workloads.uniform(rng, (400, 1), p), p)[:, 0]
+    for panel in (32, 64, 256):
+        tag = f"freecols panel={panel}"
+        print(tag, flush=True)
+        _cmp(Z, B, p, panel, tag)
+        _cmp_rref(Z, p, panel, tag)
+    # low rank
+    L = workloads.uniform(rng, (350, 150), p).astype(np.uint64)
+    U = workloads.uniform(rng, (150, 380), p).astype(np.uint64)
+    A = oracle.matmul_mod(L, U, p).astype(np.uint32)
+    B2 = workloads.uniform(rng, (350, 3), p)
+    B2[:, 0] = oracle.matmul_mod(A, workloads.uniform(rng, (380, 1), p), p)[:, 0]
+    for panel in (64, 128):
+        _cmp(A, B2, p, panel, f"lowrank panel={panel}")
+    # sparse rows (many zero multipliers), rank deficient
+    S = workloads.uniform(rng, (400, 380), p)
+    S[rng.random(S.shape) < 0.95] = 0
+    _cmp(S, B2[:1].repeat(400, axis=0)[:, :2], p, 64, "sparse")
+    _cmp_rref(S, p, 64, "sparse")
+
+
+def test_small_cases_blocked(gpu):
+    for i, c in enumerate(workloads.small_cases(seed=99, count=48, max_dim=70, max_k=6)):
+        tag = f"small {i} {c['kind']} {c['A'].shape} p={c['p']}"
+        _cmp(c["A"], c["B"], c["p"], 32, tag)
+
+
+def test_blocked_equals_plain_c2_slice(gpu):
+    A, B, p = workloads.config("c2", n=1536)
+    a = _solve(A, B, p, 256, path=INT8)
+    b = _solve(A, B, p, 256, path=lx.PATH_PLAIN)
+    for x, y in zip(a, b):
+        assert np.array_equal(np.asarray(x), np.asarray(y))
+
+
+def test_c1_blocked(gpu):
+    A, B, p = workloads.config("c1")
+    _cmp(A, B, p, 64, "c1 blocked")
+
+
+def test_c2_full_size_blocked(gpu):
+    A, B, p = workloads.config("c2")
+    print("c2 blocked full size", flush=True)
+    X, r, piv, cons = _solve(A, B, p, 256)
+    assert r == 8192 and np.array_equal(piv, np.arange(8192)) and cons.all()
+    assert np.array_equal(oracle.matmul_mod(A, X, p), B.astype(np.uint64))
+
+
+def test_c3_full_size_blocked(gpu):
+    """n = 16384, 64 right-hand sides: rank, pivots and A X = B on 512 seeded rows."""
+    A, B, p = workloads.config("c3")
+    print("c3 blocked full size", flush=True)
+    X, r, piv, cons = _solve(A, B, p, 256)
+    assert r == 16384 and np.array_equal(piv, np.arange(16384)) and cons.all()
+    rows = np.random.default_rng(3).choice(16384, size=512, replace=False)
+    assert np.array_equal(oracle.matmul_mod(A[rows], X, p), B[rows].astype(np.uint64))
