@@ -172,6 +172,62 @@ def bench_dense(args):
     return rec
 
 
+def bench_batched(args):
+    """The 4096-system workload: systems/s of the batched persistent launch
+    (graph replay) next to the same systems solved one by one on the plain
+    path."""
+    import torch
+    import paper_2605_25863_amd as lx
+    import workloads
+
+    systems = workloads.batched_systems()
+    prep = lx.prepare_batched(systems)
+    stream = torch.cuda.current_stream()
+    timer = lx.HipTimer()
+    for _ in range(args.warmup):
+        lx.solve_batched(systems, prepared=prep, stream=stream)
+    torch.cuda.synchronize()
+    kernel_ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lx.solve_batched(systems, prepared=prep, stream=stream, events=timer)
+        kernel_ms.append(timer.elapsed_ms())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    sps = len(systems) / (ms_per_step / 1e3)
+    ops = sum(metric_ops(s["n"]) for s in systems)
+    upd = sum(gj_updates(s["n"], s["n"], s["n"] + s["k"]) for s in systems)
+    rec = {"metric": "systems/s batched (4096 uneven systems, one persistent launch)",
+           "value": round(sps, 1), "unit": "systems/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+           "data": "synthetic (seeded uniform residues)",
+           "config": {"workload": "c4: 4096 systems, n~U{32..512}, k~U{1..8}, a seeded 31-bit "
+                                  "prime each, 205 rank deficient"},
+           "gop_per_s": round(ops / (ms_per_step / 1e3) / 1e9, 2),
+           "kernel_ms_per_step": round(float(np.median(kernel_ms)), 3),
+           "updates_per_s": round(upd / (float(np.median(kernel_ms)) / 1e3) / 1e12, 4)}
+    if not args.no_plain_compare:
+        # the same systems, one linac_solve each on the plain path
+        outs, wss = [], []
+        for it in prep["items"]:
+            m, n = it["A"].shape
+            k = it["B"].shape[1]
+            wss.append(torch.empty(lx.solve_workspace_bytes(m, n, k, lx.PATH_PLAIN),
+                                   dtype=torch.uint8, device="cuda:0"))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for it, ws in zip(prep["items"], wss):
+            lx.solve(it["A"], it["B"], it["p"], path=lx.PATH_PLAIN, workspace=ws, stream=stream,
+                     out=(it["X"], it["rank"], it["pivots"], it["cons"][: it["X"].shape[1]]))
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        rec["plain_systems_per_s"] = round(len(systems) / tp, 1)
+        rec["speedup_vs_plain"] = round(sps / (len(systems) / tp), 2)
+    return rec
+
+
 def copy_calibration(mib: int = 1024, reps: int = 3):
     """A plain device copy of a known size, for scaling the FETCH_SIZE /
     WRITE_SIZE hardware counters into bytes (run it under the same rocprofv3
@@ -191,11 +247,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--n", type=int, default=None, help="resize the dense workload")
     ap.add_argument("--path", default="plain", choices=["plain", "int8", "auto"])
     ap.add_argument("--panel", type=int, default=0, help="blocked panel width (0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain-compare", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -205,6 +262,9 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
+    if args.config == "c4":
+        print(json.dumps(bench_batched(args)), flush=True)
+        return
     rec = bench_dense(args)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline()

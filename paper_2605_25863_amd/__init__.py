@@ -310,9 +310,10 @@ def solve_batched(systems, *, path: int = PATH_AUTO, verbose: bool = False, stre
     out = []
     for it in prep["items"]:
         r = int(it["rank"].item())
+        k = it["X"].shape[1]
         out.append((it["X"].cpu().numpy().astype(np.uint32), r,
                     it["pivots"].cpu().numpy()[:r].astype(np.int64),
-                    it["cons"].cpu().numpy().astype(np.uint8)))
+                    it["cons"].cpu().numpy()[:k].astype(np.uint8)))
     return out
 
 

@@ -6,6 +6,11 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
 #include "internal.h"
 
 using namespace linac;
@@ -129,6 +134,51 @@ linac_status validate_range(const uint32_t* M, int64_t rows, int64_t cols, int64
     return host ? LINAC_E_RANGE : LINAC_OK;
 }
 
+// Graphs of the batched launch (counter reset + persistent kernel), captured
+// once per (device, workspace, count, grid) and replayed afterwards.  The
+// kernel arguments point into the workspace only, so a replay on the same
+// workspace sees the descriptors uploaded by the current call.
+struct BatchedGraph {
+    int dev;
+    void* ws;
+    int32_t count;
+    int32_t grid;
+    hipGraphExec_t exec;
+};
+std::mutex g_graph_mu;
+std::vector<BatchedGraph> g_graphs;
+
+hipError_t batched_graph(int dev, void* ws, int32_t count, int32_t grid, hipGraphExec_t* out) {
+    std::lock_guard<std::mutex> lock(g_graph_mu);
+    for (const BatchedGraph& g : g_graphs)
+        if (g.dev == dev && g.ws == ws && g.count == count && g.grid == grid) {
+            *out = g.exec;
+            return hipSuccess;
+        }
+    hipStream_t cap = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    hipGraph_t graph = nullptr;
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = batched_launch(ws, count, grid, cap);
+        e = hipStreamEndCapture(cap, &graph);
+        if (le != hipSuccess) e = le;
+    }
+    hipGraphExec_t exec = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) return e;
+    if (g_graphs.size() >= 64) {  // bounded cache: drop the oldest
+        (void)hipGraphExecDestroy(g_graphs.front().exec);
+        g_graphs.erase(g_graphs.begin());
+    }
+    g_graphs.push_back({dev, ws, count, grid, exec});
+    *out = exec;
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -242,22 +292,84 @@ linac_status linac_solve(const uint32_t* A, int64_t m, int64_t n, int64_t lda, c
 
 linac_status linac_solve_batched_workspace(const linac_system* sys, int32_t count,
                                            const linac_opts* opts, size_t* bytes) {
-    (void)sys;
-    (void)count;
+    if (!bytes || count < 0 || (count > 0 && !sys)) return LINAC_E_INVALID_ARG;
     (void)opts;
-    (void)bytes;
-    return LINAC_E_UNSUPPORTED;
+    for (int32_t i = 0; i < count; ++i) {
+        const linac_system& d = sys[i];
+        if (d.m < 0 || d.n < 0 || d.k < 0) return LINAC_E_INVALID_ARG;
+        if (!batched_fits(d.m, d.n, d.k)) return LINAC_E_UNSUPPORTED;
+    }
+    *bytes = batched_workspace(sys, count);
+    return LINAC_OK;
 }
 
 linac_status linac_solve_batched(const linac_system* sys, int32_t count, void* ws, size_t ws_bytes,
                                  const linac_opts* opts, hipStream_t s) {
-    (void)sys;
-    (void)count;
-    (void)ws;
-    (void)ws_bytes;
-    (void)opts;
-    (void)s;
-    return LINAC_E_UNSUPPORTED;
+    if (count < 0 || (count > 0 && !sys)) return LINAC_E_INVALID_ARG;
+    if (count == 0) return LINAC_OK;
+    std::vector<uint32_t> primes_ok;
+    for (int32_t i = 0; i < count; ++i) {
+        const linac_system& d = sys[i];
+        if (d.m < 0 || d.n < 0 || d.k < 0) return LINAC_E_INVALID_ARG;
+        if (d.lda < (d.n > 0 ? d.n : 1) || d.ldb < (d.k > 0 ? d.k : 1) ||
+            d.ldx < (d.k > 0 ? d.k : 1))
+            return LINAC_E_INVALID_ARG;
+        if (!d.rank) return LINAC_E_INVALID_ARG;
+        if ((int64_t)d.m * d.n > 0 && !d.A) return LINAC_E_INVALID_ARG;
+        if ((int64_t)d.m * d.k > 0 && !d.B) return LINAC_E_INVALID_ARG;
+        if ((int64_t)d.n * d.k > 0 && !d.X) return LINAC_E_INVALID_ARG;
+        if (d.k > 0 && !d.consistent) return LINAC_E_INVALID_ARG;
+        if ((d.m < d.n ? d.m : d.n) > 0 && !d.pivots) return LINAC_E_INVALID_ARG;
+        if (!batched_fits(d.m, d.n, d.k)) return LINAC_E_UNSUPPORTED;
+        if (std::find(primes_ok.begin(), primes_ok.end(), d.p) == primes_ok.end()) {
+            linac_status st = check_field(d.p);
+            if (st != LINAC_OK) return st;
+            primes_ok.push_back(d.p);
+        }
+    }
+    const size_t need = batched_workspace(sys, count);
+    if (!ws || ws_bytes < need) return LINAC_E_WORKSPACE;
+
+    // queue order: decreasing Gauss-Jordan cost m * n * (n + k)
+    std::vector<int32_t> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        const double ca = (double)sys[a].m * sys[a].n * (sys[a].n + sys[a].k);
+        const double cb = (double)sys[b].m * sys[b].n * (sys[b].n + sys[b].k);
+        return ca > cb;
+    });
+    std::vector<char> host(batched_desc_bytes() * (size_t)count);
+    batched_describe(sys, count, ws, host.data(), order.data());
+    // pageable source: the runtime stages it before returning
+    hipError_t e = hipMemcpyAsync(batched_desc_ptr(ws), host.data(), host.size(),
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e);
+
+    int dev = 0;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e);
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e);
+    const int32_t per_cu = 4;
+    const int32_t grid = std::max(1, std::min(count, cus * per_cu));
+    hipGraphExec_t exec = nullptr;
+    e = batched_graph(dev, ws, count, grid, &exec);
+    if (e != hipSuccess) return hip_fail(e);
+    if (opts && opts->verbose)
+        fprintf(stderr, "[linac] batched count=%d grid=%d ws=%p\n", count, grid, ws);
+    if (opts && opts->ev_begin) {
+        e = hipEventRecord(opts->ev_begin, s);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    e = hipGraphLaunch(exec, s);
+    if (e != hipSuccess) return hip_fail(e);
+    if (opts && opts->ev_end) {
+        e = hipEventRecord(opts->ev_end, s);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    if (opts && opts->dominant_launches) *opts->dominant_launches = 1;
+    return LINAC_OK;
 }
 
 linac_status linac_load_tuning(const char* json) {

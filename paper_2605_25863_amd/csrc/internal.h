@@ -79,6 +79,16 @@ size_t blocked_workspace(int64_t m, int64_t n, int64_t k, int32_t panel);
 hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel,
                              PlainArgs& a, const linac_opts* opts, hipStream_t s);
 
+// Batched path (batched.hip): workspace = [queue counter | descriptors | one
+// working region per system].
+bool batched_fits(int64_t m, int64_t n, int64_t k);
+size_t batched_desc_bytes();
+size_t batched_workspace(const linac_system* sys, int32_t count);
+void batched_describe(const linac_system* sys, int32_t count, void* ws, void* host_desc,
+                      int32_t* order);
+void* batched_desc_ptr(void* ws);
+hipError_t batched_launch(void* ws, int32_t count, int32_t grid, hipStream_t s);
+
 // Range check of residues: sets *flag to 1 when an entry is >= p.
 hipError_t launch_range_check(const uint32_t* M, int64_t rows, int64_t cols, int64_t ld, uint32_t p,
                               uint32_t* flag, hipStream_t s);
