@@ -95,7 +95,7 @@ linac_status path_workspace(int path, int64_t m, int64_t n, int64_t k, const lin
         *bytes = plain_workspace(m, n, k);
         return LINAC_OK;
     }
-    if (path == LINAC_PATH_BLOCKED_INT8) {
+    if (path == LINAC_PATH_BLOCKED_INT8 || path == LINAC_PATH_BLOCKED_FP64) {
         int32_t w = panel_width(opts);
         if (!panel_ok(w)) return LINAC_E_INVALID_ARG;
         *bytes = blocked_workspace(m, n, k, w);
@@ -109,7 +109,8 @@ linac_status path_workspace(int path, int64_t m, int64_t n, int64_t k, const lin
 hipError_t run_path(int path, void* ws, int64_t m, int64_t n, int64_t k, PlainArgs& a,
                     const linac_opts* opts, hipStream_t s) {
     if (path == LINAC_PATH_PLAIN) return plain_eliminate(a, opts, s);
-    return blocked_eliminate(ws, m, n, k, panel_width(opts), a, opts, s);
+    return blocked_eliminate(ws, m, n, k, panel_width(opts), path == LINAC_PATH_BLOCKED_FP64, a,
+                             opts, s);
 }
 
 bool size_ok(int64_t m, int64_t n, int64_t k) {
@@ -221,6 +222,7 @@ linac_status linac_rref(uint32_t* A, int64_t m, int64_t n, int64_t lda, uint32_t
     if (st != LINAC_OK) return st;
     if (!size_ok(m, n, 0)) return LINAC_E_NOMEM;
     int path = choose_path(opts, m, n);
+    if (path == LINAC_PATH_BLOCKED_FP64 && p >= (1u << 21)) return LINAC_E_UNSUPPORTED;
     size_t need = 0;
     st = path_workspace(path, m, n, 0, opts, &need);
     if (st != LINAC_OK) return st;
@@ -266,6 +268,7 @@ linac_status linac_solve(const uint32_t* A, int64_t m, int64_t n, int64_t lda, c
     if (st != LINAC_OK) return st;
     if (!size_ok(m, n, k)) return LINAC_E_NOMEM;
     int path = choose_path(opts, m, n);
+    if (path == LINAC_PATH_BLOCKED_FP64 && p >= (1u << 21)) return LINAC_E_UNSUPPORTED;
     size_t need = 0;
     st = path_workspace(path, m, n, k, opts, &need);
     if (st != LINAC_OK) return st;

@@ -265,6 +265,88 @@ __global__ __launch_bounds__(kThreads) void gemm_i8_kernel(PlainArgs w, int64_t 
     }
 }
 
+// FP64 operands for p < 2^21: centred residues as doubles in the lane order of
+// the 16x16x4 FP64 MFMA.  A fragment (rb, kb): lane L holds E[rb*16 + L%16]
+// [kb*4 + L/16]; B fragment (cb, kb): lane L holds X_S[kb*4 + L/16][cb*16 + L%16].
+__global__ void build_a_f64_kernel(PlainArgs w, const uint32_t* PR, int64_t ldpr, int32_t wj,
+                                   int32_t KB, int64_t MB, double* Afrag) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= MB * KB * 64) return;
+    const int L = (int)(gid & 63);
+    const int64_t t = gid >> 6;
+    const int kb = (int)(t % KB);
+    const int64_t rb = t / KB;
+    const int64_t row = rb * 16 + (L & 15);
+    const int k = kb * 4 + (L >> 4);
+    const uint32_t e = (row < w.m && k < wj) ? PR[row * ldpr + wj + k] : 0u;
+    Afrag[gid] = (double)centre(e, w.F.p);
+}
+
+__global__ void build_b_f64_kernel(PlainArgs w, int32_t j0, int32_t wj, int64_t col0, int64_t N,
+                                   int32_t KB, int64_t NB, double* Bfrag) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= NB * KB * 64) return;
+    const int L = (int)(gid & 63);
+    const int64_t t = gid >> 6;
+    const int kb = (int)(t % KB);
+    const int64_t cb = t / KB;
+    const int64_t col = cb * 16 + (L & 15);
+    const int k = kb * 4 + (L >> 4);
+    uint32_t y = 0;
+    if (k < wj && col < N) {
+        const unsigned long long s = w.slots[j0 + k];
+        if (s != kNoPivot) y = w.W[(int64_t)(s >> 32) * w.ld + col0 + col];
+    }
+    Bfrag[gid] = (double)centre(y, w.F.p);
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Trailing update on FP64 MFMA: block = 4 waves over a 64 x 64 tile, each wave
+// a 32 x 32 quarter (2 x 2 MFMA blocks of 16 x 16).  Accumulator layout of the
+// 16x16x4 FP64 MFMA (checked on gfx950): lane L holds column L%16 and rows
+// L/16 + 4*i, i = 0..3 (interleaved, unlike the int8 and FP32 shapes).
+__global__ __launch_bounds__(kThreads) void gemm_f64_kernel(PlainArgs w, int64_t col0, int64_t N,
+                                                            const double* Afrag,
+                                                            const double* Bfrag, int32_t KB,
+                                                            int64_t NB, int32_t j0, int32_t wj) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t rb0 = (int64_t)blockIdx.x * 4 + (wave >> 1) * 2;
+    const int64_t cb0 = (int64_t)blockIdx.y * 4 + (wave & 1) * 2;
+    v4d acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+    for (int kb = 0; kb < KB; ++kb) {
+        double af[2], bf[2];
+        for (int a = 0; a < 2; ++a) af[a] = Afrag[((rb0 + a) * KB + kb) * 64 + lane];
+        for (int b = 0; b < 2; ++b)
+            bf[b] = cb0 + b < NB ? Bfrag[((cb0 + b) * KB + kb) * 64 + lane] : 0.0;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+    for (int a = 0; a < 2; ++a) {
+        for (int b = 0; b < 2; ++b) {
+            const int64_t col = (cb0 + b) * 16 + (lane & 15);
+            if (col >= N) continue;
+            for (int i = 0; i < 4; ++i) {
+                const int64_t row = (rb0 + a) * 16 + (lane >> 4) + 4 * i;
+                if (row >= w.m) continue;
+                const double T = acc[a][b][i];  // exact: |T| < K * 2^40
+                double q = floor(T * w.F.pinv);
+                double r = __fma_rn(-q, w.F.dp, T);
+                if (r < 0.0) r += w.F.dp;
+                if (r >= w.F.dp) r -= w.F.dp;
+                const uint32_t t = (uint32_t)r;
+                uint32_t* c = w.W + row * w.ld + col0 + col;
+                const int rc = w.rowcol[row];
+                const bool fresh = rc >= j0 && rc < j0 + wj;
+                *c = fresh ? t : add_mod(*c, t, w.F.p);
+            }
+        }
+    }
+}
+
 // Write the reduced panel back into W; pivot columns become unit vectors.
 __global__ void panel_writeback_kernel(PlainArgs w, const uint32_t* PR, int64_t ldpr, int32_t j0,
                                        int32_t wj) {
@@ -289,6 +371,9 @@ struct Blocked {
     int32_t KB;
 };
 
+// Workspace after the plain layout: PR (m x ldpr) and the operand fragments,
+// sized for the larger of the int8 (A 4 B, B 16 B per element) and FP64 (8 B
+// each) layouts.
 size_t carve_blocked(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, Blocked* b) {
     const size_t base = plain_workspace(m, n, k);
     Carver c(ws ? (char*)ws + base : nullptr);
@@ -297,7 +382,7 @@ size_t carve_blocked(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, B
     const int64_t Mp = round_up(m > 0 ? m : 1, 128);
     const int64_t Np = round_up(n + k > 0 ? n + k : 1, 64);
     uint32_t* PR = c.take<uint32_t>(m * ldpr);
-    int8_t* A = c.take<int8_t>(Mp * Kp * 4);
+    int8_t* A = c.take<int8_t>(Mp * Kp * 8);
     int8_t* B = c.take<int8_t>(Np * Kp * 16);
     if (b) {
         plain_carve(ws, m, n, k, b->w);
@@ -317,7 +402,7 @@ size_t blocked_workspace(int64_t m, int64_t n, int64_t k, int32_t panel) {
     return carve_blocked(nullptr, m, n, k, panel, nullptr);
 }
 
-hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel,
+hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, bool fp64,
                              PlainArgs& out, const linac_opts* opts, hipStream_t s) {
     Blocked b;
     carve_blocked(ws, m, n, k, panel, &b);
@@ -346,7 +431,21 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
         for (int32_t js = 0; js < wj && e == hipSuccess; ++js)
             e = launch_gj_step(pa, js, wj + js + 1, s);
         hipLaunchKernelGGL(panel_resolve_kernel, dim3(1), dim3(256), 0, s, w, b.PR, b.ldpr, j0, wj);
-        if (N > 0) {
+        if (N > 0 && fp64) {
+            const int32_t KB = (int32_t)ceil_div(wj, 4);
+            const int64_t NB = ceil_div(N, 16);
+            const int64_t MB = ceil_div(m, 64) * 4;
+            double* Ad = (double*)b.Afrag;
+            double* Bd = (double*)b.Bfrag;
+            hipLaunchKernelGGL(build_b_f64_kernel, dim3((unsigned)ceil_div(NB * KB * 64, 256)),
+                               dim3(256), 0, s, w, j0, wj, col0, N, KB, NB, Bd);
+            hipLaunchKernelGGL(build_a_f64_kernel, dim3((unsigned)ceil_div(MB * KB * 64, 256)),
+                               dim3(256), 0, s, w, b.PR, b.ldpr, wj, KB, MB, Ad);
+            if (opts && opts->ev_begin && gemm_launches == 0) (void)hipEventRecord(opts->ev_begin, s);
+            hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)ceil_div(m, 64), (unsigned)ceil_div(N, 64)),
+                               dim3(kThreads), 0, s, w, col0, N, Ad, Bd, KB, NB, j0, wj);
+            ++gemm_launches;
+        } else if (N > 0) {
             const int32_t KB = (int32_t)ceil_div(wj, 32);
             const int64_t NB = ceil_div(N, 32);
             const int64_t MB = ceil_div(m, 128) * 4;

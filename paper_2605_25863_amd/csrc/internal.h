@@ -76,7 +76,7 @@ hipError_t plain_finish_rref(const PlainArgs& a, uint32_t* A, int64_t lda, int32
 // buffer and the MFMA operand fragments.  `a` carries the field in and the
 // carved bookkeeping out (for the shared extraction kernels).
 size_t blocked_workspace(int64_t m, int64_t n, int64_t k, int32_t panel);
-hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel,
+hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, bool fp64,
                              PlainArgs& a, const linac_opts* opts, hipStream_t s);
 
 // Batched path (batched.hip): workspace = [queue counter | descriptors | one

@@ -144,3 +144,51 @@ def test_c3_full_size_blocked(gpu):
     assert r == 16384 and np.array_equal(piv, np.arange(16384)) and cons.all()
     rows = np.random.default_rng(3).choice(16384, size=512, replace=False)
     assert np.array_equal(oracle.matmul_mod(A[rows], X, p), B[rows].astype(np.uint64))
+
+
+FP64 = lx.PATH_BLOCKED_FP64
+
+
+@pytest.mark.parametrize("m,n,k,bits,panel", [
+    (300, 300, 5, 20, 64),
+    (257, 333, 7, 16, 96),
+    (500, 420, 0, 21, 256),
+    (129, 700, 3, 13, 128),
+    (700, 650, 9, 20, 512),
+])
+def test_fp64_variant(gpu, m, n, k, bits, panel):
+    """The FP64-MFMA trailing product for p < 2^21, bit-exact."""
+    rng = np.random.default_rng(m + n + bits)
+    p = workloads.draw_prime_bits(rng, bits)
+    assert p < (1 << 21)
+    A = workloads.uniform(rng, (m, n), p)
+    B = workloads.uniform(rng, (m, k), p)
+    if m > 10:
+        A[7] = A[3]
+        A[:, 5] = 0
+    tag = f"fp64 m={m} n={n} k={k} p={p} panel={panel}"
+    print(tag, flush=True)
+    got = _solve(A, B, p, panel, path=FP64)
+    ref = oracle.solve(A, B, p)
+    for name, g, r in zip(("X", "rank", "pivots", "consistent"), got, ref):
+        assert np.array_equal(np.asarray(g), np.asarray(r)), f"{tag}: {name}"
+    import torch
+    R, rank, piv = lx.rref(A, p, path=FP64, panel_width=panel)
+    torch.cuda.synchronize()
+    Rr, rr, pr = oracle.rref(A, p)
+    assert int(rank.item()) == rr
+    assert np.array_equal(R.cpu().numpy().astype(np.uint32), Rr)
+
+
+def test_fp64_large_and_rejects_big_primes(gpu):
+    rng = np.random.default_rng(12)
+    p = workloads.draw_prime_bits(rng, 20)
+    n = 4096
+    A = workloads.uniform(rng, (n, n), p)
+    B = workloads.uniform(rng, (n, 8), p)
+    X, r, piv, cons = _solve(A, B, p, 256, path=FP64)
+    assert r == n and cons.all()
+    assert np.array_equal(oracle.matmul_mod(A, X, p), B.astype(np.uint64))
+    with pytest.raises(lx.LinacError) as e:
+        lx.solve(A[:8, :8], B[:8], workloads.MERSENNE31, path=FP64)
+    assert e.value.status == 2

@@ -32,6 +32,7 @@ __all__ = [
     "MERSENNE31",
     "is_prime_u32",
     "draw_prime31",
+    "draw_prime_bits",
     "uniform",
     "dense_system",
     "config",
@@ -79,6 +80,14 @@ def draw_prime31(rng: np.random.Generator) -> int:
     The walk ends because 2^31 - 1 is prime.
     """
     c = int(rng.integers(1 << 30, 1 << 31)) | 1
+    while not is_prime_u32(c):
+        c += 2
+    return c
+
+
+def draw_prime_bits(rng: np.random.Generator, bits: int) -> int:
+    """A prime in [2^(bits-1), 2^bits): an odd seeded candidate, then step by 2."""
+    c = int(rng.integers(1 << (bits - 1), 1 << bits)) | 1
     while not is_prime_u32(c):
         c += 2
     return c
