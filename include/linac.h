@@ -143,8 +143,17 @@ linac_status linac_solve_batched_workspace(const linac_system* sys, int32_t coun
 linac_status linac_solve_batched(const linac_system* sys, int32_t count, void* ws,
                                  size_t ws_bytes, const linac_opts* opts, hipStream_t s);
 
-/* Load tuned parameters (JSON text, as written by the autotuner) for later calls;
- * NULL restores the built-in defaults.  Tuning never changes results. */
+/* Load tuned parameters for later calls (process-wide); NULL restores the
+ * built-in defaults.  Tuning only selects among configurations that give the
+ * same results (paths and panel widths all compute the unique RREF).  The text
+ * is a JSON object, as written by the autotuner (paper_2605_25863_amd/tune.py):
+ *   "blocked_min":    AUTO takes the blocked int8 path once min(m, n) >= this;
+ *   "panel":          array of {"n_max": N, "panel": w}: panel width w for
+ *                     min(m, n) <= N (first match, ascending N; w a multiple of
+ *                     32 in [32, 512]); larger sizes use the last entry;
+ *   "batched_per_cu": resident workgroups per compute unit of the batched launch.
+ * Unknown keys are ignored.  Returns LINAC_E_INVALID_ARG (and keeps the current
+ * table) for malformed text or out-of-range values.  Host only. */
 linac_status linac_load_tuning(const char* json);
 
 /* Host-only primality check used by argument validation: LINAC_OK when p is a

@@ -33,12 +33,14 @@ __all__ = [
     "LinacError", "library_path", "row_reduce", "rref", "solve", "solve_batched",
     "drop_bottom_zero_rows", "pivot_columns_from_row_reduced_echelon_form", "HipTimer",
     "PATH_AUTO", "PATH_PLAIN", "PATH_BLOCKED_INT8", "PATH_BLOCKED_FP64", "check_prime",
+    "load_tuning", "TUNING_FILE",
 ]
 
 PATH_AUTO, PATH_PLAIN, PATH_BLOCKED_INT8, PATH_BLOCKED_FP64 = 0, 1, 2, 3
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBPATH = os.path.join(_HERE, "liblinac_mi355x.so")
+TUNING_FILE = os.path.join(_HERE, "tuning_gfx950.json")
 _lib = None
 
 
@@ -98,12 +100,23 @@ def _load():
                  "linac_check_prime", "linac_version", "linac_last_hip_error"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
+    if os.path.exists(TUNING_FILE):
+        with open(TUNING_FILE) as f:
+            _check(lib.linac_load_tuning(f.read().encode()), "linac_load_tuning")
     return lib
 
 
 def _check(status: int, where: str):
     if status != 0:
         raise LinacError(status, where)
+
+
+def load_tuning(json_text):
+    """Install a tuning table (JSON text, see include/linac.h); None restores the
+    built-in defaults.  Tables only change speed, never results."""
+    lib = _load()
+    _check(lib.linac_load_tuning(None if json_text is None else json_text.encode()),
+           "linac_load_tuning")
 
 
 def check_prime(p: int) -> int:

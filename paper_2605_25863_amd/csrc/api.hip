@@ -6,9 +6,12 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <stdlib.h>
+
 #include <algorithm>
 #include <mutex>
 #include <numeric>
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -70,21 +73,149 @@ linac_status check_field(uint32_t p) {
     return is_prime_u32(p) ? LINAC_OK : LINAC_E_NOT_PRIME;
 }
 
-constexpr int32_t kDefaultPanel = 256;
-constexpr int64_t kBlockedMinSize = 1024;
+// ---------------------------------------------------------------------------
+// Tuning table.  Defaults are built in; linac_load_tuning replaces them with
+// values measured by the autotuner.  Only choices that never change results
+// are tuned: the plain/blocked crossover, the panel width per size bucket and
+// the number of resident batched workgroups per compute unit.
+// ---------------------------------------------------------------------------
+struct PanelRule {
+    int64_t n_max;
+    int32_t panel;
+};
+struct Tuning {
+    int64_t blocked_min = 1024;  // AUTO takes the blocked path from min(m, n) >= this
+    int32_t batched_per_cu = 4;
+    std::vector<PanelRule> panels{{1 << 30, 256}};
+};
+std::mutex g_tune_mu;
+Tuning g_tune;
 
-// AUTO: the plain path for small systems, the int8-MFMA blocked path from
-// min(m, n) >= 1024 on.  Depends only on the shape so that the workspace query
+Tuning tuning() {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    return g_tune;
+}
+
+// A small JSON reader for the tuning file: objects, arrays, numbers, strings,
+// true/false/null.  Values are collected as "path.to.key" -> number; arrays of
+// objects are flattened with an index ("panel.0.n_max").
+struct JsonReader {
+    const char* s;
+    bool ok = true;
+    std::vector<std::pair<std::string, double>> out;
+    void ws() {
+        while (*s == ' ' || *s == '\n' || *s == '\t' || *s == '\r') ++s;
+    }
+    bool str(std::string& v) {
+        ws();
+        if (*s != '"') return false;
+        ++s;
+        v.clear();
+        while (*s && *s != '"') {
+            if (*s == '\\' && s[1]) ++s;
+            v.push_back(*s++);
+        }
+        if (*s != '"') return false;
+        ++s;
+        return true;
+    }
+    bool value(const std::string& key) {
+        ws();
+        if (*s == '{') {
+            ++s;
+            ws();
+            if (*s == '}') return ++s, true;
+            for (;;) {
+                std::string k;
+                if (!str(k)) return false;
+                ws();
+                if (*s != ':') return false;
+                ++s;
+                if (!value(key.empty() ? k : key + "." + k)) return false;
+                ws();
+                if (*s == ',') { ++s; continue; }
+                if (*s == '}') return ++s, true;
+                return false;
+            }
+        }
+        if (*s == '[') {
+            ++s;
+            ws();
+            if (*s == ']') return ++s, true;
+            for (int i = 0;; ++i) {
+                if (!value(key + "." + std::to_string(i))) return false;
+                ws();
+                if (*s == ',') { ++s; continue; }
+                if (*s == ']') return ++s, true;
+                return false;
+            }
+        }
+        if (*s == '"') {
+            std::string v;
+            return str(v);
+        }
+        if (!strncmp(s, "true", 4) || !strncmp(s, "null", 4)) return s += 4, true;
+        if (!strncmp(s, "false", 5)) return s += 5, true;
+        char* end = nullptr;
+        double d = strtod(s, &end);
+        if (end == s) return false;
+        s = end;
+        out.emplace_back(key, d);
+        return true;
+    }
+};
+
+linac_status parse_tuning(const char* json, Tuning* t) {
+    JsonReader r{json};
+    if (!r.value("")) return LINAC_E_INVALID_ARG;
+    r.ws();
+    if (*r.s) return LINAC_E_INVALID_ARG;
+    Tuning nt;
+    std::vector<PanelRule> rules;
+    for (const auto& kv : r.out) {
+        const std::string& k = kv.first;
+        const double v = kv.second;
+        if (k == "blocked_min") nt.blocked_min = (int64_t)v;
+        else if (k == "batched_per_cu") nt.batched_per_cu = (int32_t)v;
+        else if (k.rfind("panel.", 0) == 0) {
+            size_t dot = k.find('.', 6);
+            if (dot == std::string::npos) return LINAC_E_INVALID_ARG;
+            size_t idx = (size_t)atoi(k.c_str() + 6);
+            if (rules.size() <= idx) rules.resize(idx + 1, PanelRule{0, 0});
+            std::string field = k.substr(dot + 1);
+            if (field == "n_max") rules[idx].n_max = (int64_t)v;
+            else if (field == "panel") rules[idx].panel = (int32_t)v;
+        }
+    }
+    for (const PanelRule& pr : rules)
+        if (pr.n_max <= 0 || pr.panel < 32 || pr.panel > 512 || pr.panel % 32) return LINAC_E_INVALID_ARG;
+    if (nt.blocked_min < 1 || nt.batched_per_cu < 1 || nt.batched_per_cu > 16)
+        return LINAC_E_INVALID_ARG;
+    std::sort(rules.begin(), rules.end(),
+              [](const PanelRule& a, const PanelRule& b) { return a.n_max < b.n_max; });
+    if (!rules.empty()) nt.panels = rules;
+    *t = nt;
+    return LINAC_OK;
+}
+
+// AUTO: the plain path for small systems, the int8-MFMA blocked path from the
+// tuned crossover on.  Depends only on the shape so that the workspace query
 // and the call agree.
 int choose_path(const linac_opts* opts, int64_t m, int64_t n) {
     int path = opts ? opts->path : LINAC_PATH_AUTO;
     if (path != LINAC_PATH_AUTO) return path;
-    return (m < n ? m : n) >= kBlockedMinSize ? LINAC_PATH_BLOCKED_INT8 : LINAC_PATH_PLAIN;
+    return (m < n ? m : n) >= tuning().blocked_min ? LINAC_PATH_BLOCKED_INT8 : LINAC_PATH_PLAIN;
 }
 
-int32_t panel_width(const linac_opts* opts) {
-    int32_t w = opts && opts->panel_width > 0 ? opts->panel_width : kDefaultPanel;
-    return w;
+// Panel width: the caller's, else the tuned one for this size (the first rule
+// whose n_max covers min(m, n)), else the last rule.
+int32_t panel_width(const linac_opts* opts, int64_t m = 0, int64_t n = 0) {
+    if (opts && opts->panel_width > 0) return opts->panel_width;
+    const Tuning t = tuning();
+    const int64_t sz = m < n ? m : n;
+    for (const PanelRule& pr : t.panels)
+        if (sz <= pr.n_max) return pr.panel;
+    return t.panels.back().panel;
 }
 
 bool panel_ok(int32_t w) { return w >= 32 && w <= 512 && w % 32 == 0; }
@@ -96,7 +227,7 @@ linac_status path_workspace(int path, int64_t m, int64_t n, int64_t k, const lin
         return LINAC_OK;
     }
     if (path == LINAC_PATH_BLOCKED_INT8 || path == LINAC_PATH_BLOCKED_FP64) {
-        int32_t w = panel_width(opts);
+        int32_t w = panel_width(opts, m, n);
         if (!panel_ok(w)) return LINAC_E_INVALID_ARG;
         *bytes = blocked_workspace(m, n, k, w);
         return LINAC_OK;
@@ -109,8 +240,8 @@ linac_status path_workspace(int path, int64_t m, int64_t n, int64_t k, const lin
 hipError_t run_path(int path, void* ws, int64_t m, int64_t n, int64_t k, PlainArgs& a,
                     const linac_opts* opts, hipStream_t s) {
     if (path == LINAC_PATH_PLAIN) return plain_eliminate(a, opts, s);
-    return blocked_eliminate(ws, m, n, k, panel_width(opts), path == LINAC_PATH_BLOCKED_FP64, a,
-                             opts, s);
+    return blocked_eliminate(ws, m, n, k, panel_width(opts, m, n), path == LINAC_PATH_BLOCKED_FP64,
+                             a, opts, s);
 }
 
 bool size_ok(int64_t m, int64_t n, int64_t k) {
@@ -237,7 +368,7 @@ linac_status linac_rref(uint32_t* A, int64_t m, int64_t n, int64_t lda, uint32_t
     }
     if (opts && opts->verbose)
         fprintf(stderr, "[linac] rref path=%d m=%lld n=%lld p=%u ld=%lld panel=%d\n", path,
-                (long long)m, (long long)n, p, (long long)a.ld, panel_width(opts));
+                (long long)m, (long long)n, p, (long long)a.ld, panel_width(opts, m, n));
     hipError_t e = plain_prepare(a, A, lda, nullptr, 1, (int32_t)n, 0, s);
     if (e == hipSuccess) e = run_path(path, ws, m, n, 0, a, opts, s);
     if (e == hipSuccess) e = plain_finish_rref(a, A, lda, rank, pivots, s);
@@ -285,7 +416,7 @@ linac_status linac_solve(const uint32_t* A, int64_t m, int64_t n, int64_t lda, c
     if (opts && opts->verbose)
         fprintf(stderr, "[linac] solve path=%d m=%lld n=%lld k=%lld p=%u ld=%lld panel=%d\n",
                 path, (long long)m, (long long)n, (long long)k, p, (long long)a.ld,
-                panel_width(opts));
+                panel_width(opts, m, n));
     hipError_t e = plain_prepare(a, A, lda, B, ldb, (int32_t)n, (int32_t)k, s);
     if (e == hipSuccess) e = run_path(path, ws, m, n, k, a, opts, s);
     if (e == hipSuccess) e = plain_finish_solve(a, (int32_t)n, (int32_t)k, X, ldx, rank, pivots,
@@ -354,7 +485,7 @@ linac_status linac_solve_batched(const linac_system* sys, int32_t count, void* w
     int cus = 0;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return hip_fail(e);
-    const int32_t per_cu = 4;
+    const int32_t per_cu = tuning().batched_per_cu;
     const int32_t grid = std::max(1, std::min(count, cus * per_cu));
     hipGraphExec_t exec = nullptr;
     e = batched_graph(dev, ws, count, grid, &exec);
@@ -376,7 +507,13 @@ linac_status linac_solve_batched(const linac_system* sys, int32_t count, void* w
 }
 
 linac_status linac_load_tuning(const char* json) {
-    (void)json;
+    Tuning t;
+    if (json) {
+        linac_status st = parse_tuning(json, &t);
+        if (st != LINAC_OK) return st;
+    }
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune = t;
     return LINAC_OK;
 }
 

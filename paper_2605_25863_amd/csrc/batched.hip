@@ -81,14 +81,14 @@ __device__ void solve_one(const SysDesc& d, uint8_t* s_piv, int32_t* s_pivrow, i
         }
         const int q = block_min(cand, s_red);  // its barriers also publish s_f
         if (q == INT32_MAX) continue;          // free column
+        // every wave takes the (wave-uniform) inverse itself on the scalar unit
+        const uint32_t inv = inv_mod_fermat(__builtin_amdgcn_readfirstlane(s_f[q]), F);
         if (tid == 0) {
-            s_bcast[0] = inv_mod(s_f[q], p);
             s_piv[q] = 1;
             s_pivrow[rank] = q;
             s_pivcol[rank] = j;
         }
         __syncthreads();
-        const uint32_t inv = s_bcast[0];
         const int v0 = j >> 2;  // first 4-column vector touched
         for (int c = 4 * v0 + tid; c < ldw; c += kThreads) {
             const uint32_t v = c < ncols ? mul_mod(d.W[(int64_t)q * ldw + c], inv, F) : 0u;

@@ -56,36 +56,46 @@ __device__ __forceinline__ void digits4(int32_t x, int8_t d[4]) {
     }
 }
 
-// Copy the panel columns into PR (E block zero) and search the first column.
-__global__ __launch_bounds__(kThreads) void panel_extract_kernel(PlainArgs w, uint32_t* PR,
-                                                                 int64_t ldpr, int32_t j0,
-                                                                 int32_t wj) {
+// A row-major matrix view (device pointer and leading dimension).
+struct Mat {
+    uint32_t* M;
+    int64_t ld;
+};
+
+// Copy columns [c0, c0 + width) of src into dst (all of dst's other columns,
+// including the transform block, set to zero).  With gcol >= 0 also record
+// column 0 of dst as the next pivot column's values and post its pivot
+// candidate (smallest non-pivot row with a non-zero entry) to slots[gcol].
+__global__ __launch_bounds__(kThreads) void panel_extract_kernel(PlainArgs w, Mat src, int64_t c0,
+                                                                 Mat dst, int32_t width,
+                                                                 int32_t gcol) {
     __shared__ int s_row[4];
     __shared__ uint32_t s_val[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t c0 = (int64_t)blockIdx.y * 256 + lane * 4;
+    const int64_t d0 = (int64_t)blockIdx.y * 256 + lane * 4;
     const int row0 = blockIdx.x * kTileRows + wave * 8;
+    const bool look = gcol >= 0 && blockIdx.y == 0;
     int best = INT32_MAX;
     uint32_t bestv = 0;
     for (int rr = 0; rr < 8; ++rr) {
         const int r = row0 + rr;
-        if (r >= w.m || c0 >= ldpr) continue;
+        if (r >= w.m || d0 >= dst.ld) continue;
         uint32_t v[4];
         for (int e = 0; e < 4; ++e) {
-            const int64_t c = c0 + e;
-            v[e] = c < wj ? w.W[(int64_t)r * w.ld + j0 + c] : 0u;
+            const int64_t c = d0 + e;
+            v[e] = c < width ? src.M[(int64_t)r * src.ld + c0 + c] : 0u;
         }
-        *(uint4*)(PR + (int64_t)r * ldpr + c0) = make_uint4(v[0], v[1], v[2], v[3]);
-        if (blockIdx.y == 0 && lane == 0) {
-            w.fcol[0][r] = v[0];
-            if (v[0] != 0 && w.is_piv[r] == 0 && r < best) {
+        *(uint4*)(dst.M + (int64_t)r * dst.ld + d0) = make_uint4(v[0], v[1], v[2], v[3]);
+        if (look && lane == 0) {
+            const uint32_t piv = w.is_piv[r];
+            w.fcol[0][r] = v[0] | (piv << 31);
+            if (v[0] != 0 && piv == 0 && r < best) {
                 best = r;
                 bestv = v[0];
             }
         }
     }
-    if (blockIdx.y == 0) {
-        // same reduction as the plain path's look-ahead
+    if (look) {
         best = __shfl(best, 0);
         bestv = __shfl(bestv, 0);
         if (lane == 0) {
@@ -102,8 +112,8 @@ __global__ __launch_bounds__(kThreads) void panel_extract_kernel(PlainArgs w, ui
                     v = s_val[q];
                 }
             if (r != INT32_MAX) {
-                unsigned long long* slot = &w.slots[j0];
-                unsigned long long cur =
+                unsigned long long* slot = &w.slots[gcol];
+                const unsigned long long cur =
                     __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if ((cur >> 32) > (unsigned long long)r)
                     atomicMin(slot, ((unsigned long long)r << 32) | inv_mod(v, w.F.p));
@@ -112,25 +122,39 @@ __global__ __launch_bounds__(kThreads) void panel_extract_kernel(PlainArgs w, ui
     }
 }
 
-// Apply the deferred normalisation of the panel's last pivot row to all of PR.
-__global__ void panel_resolve_kernel(PlainArgs w, uint32_t* PR, int64_t ldpr, int32_t j0,
-                                     int32_t wj) {
-    const unsigned long long s = w.slots[j0 + wj - 1];
+// Apply the deferred normalisation of the last pivot row (slot gcol_last) to
+// columns [0, width) of buf.
+__global__ void panel_resolve_kernel(PlainArgs w, Mat buf, int32_t width, int32_t gcol_last) {
+    const unsigned long long s = w.slots[gcol_last];
     if (s == kNoPivot) return;
     const int q = (int)(s >> 32);
     const uint32_t inv = (uint32_t)s;
-    for (int c = threadIdx.x; c < 2 * wj; c += blockDim.x) {
-        uint32_t* x = PR + (int64_t)q * ldpr + c;
+    for (int c = threadIdx.x; c < width; c += blockDim.x) {
+        uint32_t* x = buf.M + (int64_t)q * buf.ld + c;
         *x = mul_mod(*x, inv, w.F);
     }
 }
 
-// B operand: X_S (pivot rows' trailing parts at the panel start), pre-scaled by
-// 256^l and split into digits, stored in the lane order of the 32x32x32 int8
-// MFMA: fragment (cb, kb, plane = 4*l + l') is 64 lanes x 16 bytes; lane L holds
-// column cb*32 + L%32 and rows k = kb*32 + 16*(L/32) + i, i = 0..15.
-__global__ void build_b_kernel(PlainArgs w, int32_t j0, int32_t wj, int64_t col0, int64_t N,
-                               int32_t KB, int64_t NB, int8_t* Bfrag, uint4 scale) {
+// Row k of X_S: the pivot row of bookkeeping column gslot0 + k, columns
+// [col0, col0 + N) of src, with the implicit 1 of an enclosing transform block
+// at column inj0 + k (inj0 < 0: none); zero for a free column.
+__device__ __forceinline__ uint32_t xs_value(const PlainArgs& w, Mat src, int32_t gslot0,
+                                             int32_t wj, int64_t col0, int64_t N, int64_t inj0,
+                                             int k, int64_t col) {
+    if (k >= wj || col >= N) return 0u;
+    const unsigned long long s = w.slots[gslot0 + k];
+    if (s == kNoPivot) return 0u;
+    if (inj0 >= 0 && col0 + col == inj0 + k) return 1u;
+    return src.M[(int64_t)(s >> 32) * src.ld + col0 + col];
+}
+
+// B operand: X_S pre-scaled by 256^l and split into digits, stored in the lane
+// order of the 32x32x32 int8 MFMA: fragment (cb, kb, plane = 4*l + l') is 64
+// lanes x 16 bytes; lane L holds column cb*32 + L%32 and rows
+// k = kb*32 + 16*(L/32) + i, i = 0..15.
+__global__ void build_b_kernel(PlainArgs w, Mat src, int32_t gslot0, int32_t wj, int64_t col0,
+                               int64_t N, int64_t inj0, int32_t KB, int64_t NB, int8_t* Bfrag,
+                               uint4 scale) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= NB * KB * 64) return;
     const int L = (int)(gid & 63);
@@ -143,11 +167,7 @@ __global__ void build_b_kernel(PlainArgs w, int32_t j0, int32_t wj, int64_t col0
     int8_t out[16][16];  // [plane][i]
     for (int i = 0; i < 16; ++i) {
         const int k = kb * 32 + 16 * (L >> 5) + i;
-        uint32_t y = 0;
-        if (k < wj && col < N) {
-            const unsigned long long s = w.slots[j0 + k];
-            if (s != kNoPivot) y = w.W[(int64_t)(s >> 32) * w.ld + col0 + col];
-        }
+        const uint32_t y = xs_value(w, src, gslot0, wj, col0, N, inj0, k, col);
         for (int l = 0; l < 4; ++l) {
             const uint32_t yl = l == 0 ? y : mul_mod(y, sc[l], w.F);
             int8_t d[4];
@@ -163,11 +183,11 @@ __global__ void build_b_kernel(PlainArgs w, int32_t j0, int32_t wj, int64_t col0
     }
 }
 
-// A operand: E (PR columns [wj, 2wj)), split into digits, in MFMA lane order:
-// fragment (rb, kb, l) is 64 lanes x 16 bytes; lane L holds row rb*32 + L%32 and
-// k = kb*32 + 16*(L/32) + i.
-__global__ void build_a_kernel(PlainArgs w, const uint32_t* PR, int64_t ldpr, int32_t wj,
-                               int32_t KB, int64_t MB, int8_t* Afrag) {
+// A operand: the transform block E = ebuf columns [ecol0, ecol0 + wj), split
+// into digits, in MFMA lane order: fragment (rb, kb, l) is 64 lanes x 16 bytes;
+// lane L holds row rb*32 + L%32 and k = kb*32 + 16*(L/32) + i.
+__global__ void build_a_kernel(PlainArgs w, Mat ebuf, int64_t ecol0, int32_t wj, int32_t KB,
+                               int64_t MB, int8_t* Afrag) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= MB * KB * 64) return;
     const int L = (int)(gid & 63);
@@ -179,7 +199,7 @@ __global__ void build_a_kernel(PlainArgs w, const uint32_t* PR, int64_t ldpr, in
     int8_t out[4][16];
     for (int i = 0; i < 16; ++i) {
         const int k = kb * 32 + 16 * (L >> 5) + i;
-        uint32_t e = (row < w.m && k < wj) ? PR[row * ldpr + wj + k] : 0u;
+        uint32_t e = (row < w.m && k < wj) ? ebuf.M[row * ebuf.ld + ecol0 + k] : 0u;
         int8_t d[4];
         digits4(centre(e, p), d);
         for (int l = 0; l < 4; ++l) out[l][i] = d[l];
@@ -205,47 +225,69 @@ __device__ __forceinline__ uint32_t fold_mod(int32_t s0, int32_t s1, int32_t s2,
     return (uint32_t)r;
 }
 
-// Trailing update C = delta * C + E . X_S (mod p) on int8 MFMA.
+// Product update C = delta * C + E . X_S (mod p) on int8 MFMA (C = dst columns
+// [col0, col0 + N); delta = 0 for the rows that became pivots of this panel).
 // Block: 4 waves; wave v owns rows [(4*bx + v)*32, +32) and the block's 64
-// columns (two 32-column blocks).  The B fragments of one k-block (2 x 16 planes
-// x 1 KB) are staged in LDS and shared by the 4 waves; A fragments are read
-// straight from memory (each wave needs only its own rows).
-__global__ __launch_bounds__(kThreads) void gemm_i8_kernel(PlainArgs w, int64_t col0, int64_t N,
-                                                           const int8_t* Afrag,
-                                                           const int8_t* Bfrag, int32_t KB,
-                                                           int32_t j0, int32_t wj) {
-    __shared__ v4i sB[2 * 16 * 64];  // 32 KB
+// columns (two 32-column blocks).  The B fragments of a k-block (2 x 16 planes
+// x 1 KB) are shared through LDS, double-buffered: the next k-block is loaded
+// into registers while MFMAs run on the current one, then written to the other
+// buffer.  A fragments (each wave needs only its own rows) are prefetched into
+// registers.
+// With grid.x = row tiles and a multiple of 8 of them, all blocks of one row
+// tile run on the same XCD, so each XCD's L2 holds one eighth of the A operand.
+__global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat dst, int64_t col0,
+                                                              int64_t N, const int8_t* Afrag,
+                                                              const int8_t* Bfrag, int32_t KB,
+                                                              int32_t fresh_lo, int32_t fresh_hi) {
+    __shared__ v4i sB[2][2 * 16 * 64];  // 2 x 32 KB
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t rb = (int64_t)blockIdx.x * 4 + wave;
     const int64_t cb0 = (int64_t)blockIdx.y * 2;
+    const int64_t NB = ceil_div(N, 32);
+    // each wave moves 8 of the 32 B fragments of a k-block; column blocks past
+    // the end read a valid block (their output columns are never written)
+    const int8_t* bsrc[8];
+    for (int i = 0; i < 8; ++i) {
+        const int f = wave * 8 + i;
+        int64_t cb = cb0 + f / 16;
+        if (cb >= NB) cb = NB - 1;
+        bsrc[i] = Bfrag + (cb * KB * 16 + (f % 16)) * 1024 + lane * 16;
+    }
+    const int8_t* asrc = Afrag + (rb * KB * 4) * 1024 + lane * 16;
     v16i acc[2][4];
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 4; ++b)
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0;
-    const int64_t NB = ceil_div(N, 32);
+    v4i stage[8], af[4], an[4];
+    for (int i = 0; i < 8; ++i) stage[i] = *(const v4i*)bsrc[i];
+    for (int l = 0; l < 4; ++l) af[l] = *(const v4i*)(asrc + l * 1024);
+    for (int i = 0; i < 8; ++i) sB[0][(wave * 8 + i) * 64 + lane] = stage[i];
+    __builtin_amdgcn_s_waitcnt(0);  // nothing in flight at the loop head
+    __syncthreads();
     for (int kb = 0; kb < KB; ++kb) {
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < 2 * 16 * 64; idx += kThreads) {
-            const int cbi = idx / (16 * 64);
-            const int64_t cb = cb0 + cbi;
-            v4i v = {0, 0, 0, 0};
-            if (cb < NB)
-                v = *(const v4i*)(Bfrag + ((cb * KB + kb) * 16) * 1024 + (idx % (16 * 64)) * 16);
-            sB[idx] = v;
+        const bool more = kb + 1 < KB;
+        if (more) {  // next k-block in flight while this one computes
+            for (int i = 0; i < 8; ++i)
+                stage[i] = *(const v4i*)(bsrc[i] + (int64_t)(kb + 1) * 16 * 1024);
+            for (int l = 0; l < 4; ++l)
+                an[l] = *(const v4i*)(asrc + ((int64_t)(kb + 1) * 4 + l) * 1024);
         }
-        __syncthreads();
-        v4i af[4];
-        for (int l = 0; l < 4; ++l)
-            af[l] = *(const v4i*)(Afrag + ((rb * KB + kb) * 4 + l) * 1024 + lane * 16);
+        const v4i* sb = sB[kb & 1];
         for (int cbi = 0; cbi < 2; ++cbi) {
             for (int l = 0; l < 4; ++l) {
-                for (int lp = 0; lp < 4; ++lp) {
-                    const v4i bf = sB[(cbi * 16 + 4 * l + lp) * 64 + lane];
+                v4i bf[4];
+                for (int lp = 0; lp < 4; ++lp) bf[lp] = sb[(cbi * 16 + 4 * l + lp) * 64 + lane];
+                for (int lp = 0; lp < 4; ++lp)
                     acc[cbi][lp] =
-                        __builtin_amdgcn_mfma_i32_32x32x32_i8(af[l], bf, acc[cbi][lp], 0, 0, 0);
-                }
+                        __builtin_amdgcn_mfma_i32_32x32x32_i8(af[l], bf[lp], acc[cbi][lp], 0, 0, 0);
             }
         }
+        if (more) {
+            v4i* nb = sB[(kb + 1) & 1];
+            for (int i = 0; i < 8; ++i) nb[(wave * 8 + i) * 64 + lane] = stage[i];
+            for (int l = 0; l < 4; ++l) af[l] = an[l];
+        }
+        __syncthreads();
     }
     // epilogue: 32x32 accumulator layout: lane L holds column L%32 and rows
     // 8*(r/4) + 4*(L/32) + r%4 for r = 0..15
@@ -257,9 +299,9 @@ __global__ __launch_bounds__(kThreads) void gemm_i8_kernel(PlainArgs w, int64_t 
             if (row >= w.m) continue;
             const uint32_t t = fold_mod(acc[cbi][0][r], acc[cbi][1][r], acc[cbi][2][r],
                                         acc[cbi][3][r], w.F);
-            uint32_t* c = w.W + row * w.ld + col0 + col;
+            uint32_t* c = dst.M + row * dst.ld + col0 + col;
             const int rc = w.rowcol[row];
-            const bool fresh = rc >= j0 && rc < j0 + wj;  // a pivot row of this panel
+            const bool fresh = rc >= fresh_lo && rc < fresh_hi;  // a pivot row of this panel
             *c = fresh ? t : add_mod(*c, t, w.F.p);
         }
     }
@@ -268,8 +310,8 @@ __global__ __launch_bounds__(kThreads) void gemm_i8_kernel(PlainArgs w, int64_t 
 // FP64 operands for p < 2^21: centred residues as doubles in the lane order of
 // the 16x16x4 FP64 MFMA.  A fragment (rb, kb): lane L holds E[rb*16 + L%16]
 // [kb*4 + L/16]; B fragment (cb, kb): lane L holds X_S[kb*4 + L/16][cb*16 + L%16].
-__global__ void build_a_f64_kernel(PlainArgs w, const uint32_t* PR, int64_t ldpr, int32_t wj,
-                                   int32_t KB, int64_t MB, double* Afrag) {
+__global__ void build_a_f64_kernel(PlainArgs w, Mat ebuf, int64_t ecol0, int32_t wj, int32_t KB,
+                                   int64_t MB, double* Afrag) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= MB * KB * 64) return;
     const int L = (int)(gid & 63);
@@ -278,12 +320,12 @@ __global__ void build_a_f64_kernel(PlainArgs w, const uint32_t* PR, int64_t ldpr
     const int64_t rb = t / KB;
     const int64_t row = rb * 16 + (L & 15);
     const int k = kb * 4 + (L >> 4);
-    const uint32_t e = (row < w.m && k < wj) ? PR[row * ldpr + wj + k] : 0u;
+    const uint32_t e = (row < w.m && k < wj) ? ebuf.M[row * ebuf.ld + ecol0 + k] : 0u;
     Afrag[gid] = (double)centre(e, w.F.p);
 }
 
-__global__ void build_b_f64_kernel(PlainArgs w, int32_t j0, int32_t wj, int64_t col0, int64_t N,
-                                   int32_t KB, int64_t NB, double* Bfrag) {
+__global__ void build_b_f64_kernel(PlainArgs w, Mat src, int32_t gslot0, int32_t wj, int64_t col0,
+                                   int64_t N, int64_t inj0, int32_t KB, int64_t NB, double* Bfrag) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= NB * KB * 64) return;
     const int L = (int)(gid & 63);
@@ -292,11 +334,7 @@ __global__ void build_b_f64_kernel(PlainArgs w, int32_t j0, int32_t wj, int64_t 
     const int64_t cb = t / KB;
     const int64_t col = cb * 16 + (L & 15);
     const int k = kb * 4 + (L >> 4);
-    uint32_t y = 0;
-    if (k < wj && col < N) {
-        const unsigned long long s = w.slots[j0 + k];
-        if (s != kNoPivot) y = w.W[(int64_t)(s >> 32) * w.ld + col0 + col];
-    }
+    const uint32_t y = xs_value(w, src, gslot0, wj, col0, N, inj0, k, col);
     Bfrag[gid] = (double)centre(y, w.F.p);
 }
 
@@ -306,10 +344,11 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // a 32 x 32 quarter (2 x 2 MFMA blocks of 16 x 16).  Accumulator layout of the
 // 16x16x4 FP64 MFMA (checked on gfx950): lane L holds column L%16 and rows
 // L/16 + 4*i, i = 0..3 (interleaved, unlike the int8 and FP32 shapes).
-__global__ __launch_bounds__(kThreads) void gemm_f64_kernel(PlainArgs w, int64_t col0, int64_t N,
-                                                            const double* Afrag,
+__global__ __launch_bounds__(kThreads) void gemm_f64_kernel(PlainArgs w, Mat dst, int64_t col0,
+                                                            int64_t N, const double* Afrag,
                                                             const double* Bfrag, int32_t KB,
-                                                            int64_t NB, int32_t j0, int32_t wj) {
+                                                            int64_t NB, int32_t fresh_lo,
+                                                            int32_t fresh_hi) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t rb0 = (int64_t)blockIdx.x * 4 + (wave >> 1) * 2;
     const int64_t cb0 = (int64_t)blockIdx.y * 4 + (wave & 1) * 2;
@@ -338,62 +377,124 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(PlainArgs w, int64_t
                 if (r < 0.0) r += w.F.dp;
                 if (r >= w.F.dp) r -= w.F.dp;
                 const uint32_t t = (uint32_t)r;
-                uint32_t* c = w.W + row * w.ld + col0 + col;
+                uint32_t* c = dst.M + row * dst.ld + col0 + col;
                 const int rc = w.rowcol[row];
-                const bool fresh = rc >= j0 && rc < j0 + wj;
+                const bool fresh = rc >= fresh_lo && rc < fresh_hi;
                 *c = fresh ? t : add_mod(*c, t, w.F.p);
             }
         }
     }
 }
 
-// Write the reduced panel back into W; pivot columns become unit vectors.
-__global__ void panel_writeback_kernel(PlainArgs w, const uint32_t* PR, int64_t ldpr, int32_t j0,
-                                       int32_t wj) {
+// Write columns [0, width) of src into dst columns [d0, d0 + width); pivot
+// columns (bookkeeping columns gcol0 + js) become unit vectors.
+__global__ void panel_writeback_kernel(PlainArgs w, Mat src, Mat dst, int64_t d0, int32_t width,
+                                       int32_t gcol0) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (int64_t)w.m * wj) return;
-    const int64_t r = gid / wj;
-    const int js = (int)(gid % wj);
-    const int s = w.colpiv[j0 + js];
+    if (gid >= (int64_t)w.m * width) return;
+    const int64_t r = gid / width;
+    const int js = (int)(gid % width);
+    const int s = w.colpiv[gcol0 + js];
     uint32_t v;
     if (s >= 0) v = (w.pivrow[s] == r) ? 1u : 0u;
-    else v = PR[r * ldpr + js];
-    w.W[r * w.ld + j0 + js] = v;
+    else v = src.M[r * src.ld + js];
+    dst.M[r * dst.ld + d0 + js] = v;
 }
 
+constexpr int32_t kLeaf = 32;  // inner panel width of the two-level reduction
+
 struct Blocked {
-    PlainArgs w;   // the working matrix and the bookkeeping (shared with the plain path)
-    uint32_t* PR;
-    int64_t ldpr;
+    PlainArgs w;  // the working matrix and the bookkeeping (shared with the plain path)
+    Mat PR;       // outer panel [panel | E]
+    Mat LR;       // leaf [leaf | E_leaf]
     int8_t* Afrag;
     int8_t* Bfrag;
     int32_t panel;
-    int32_t KB;
 };
 
-// Workspace after the plain layout: PR (m x ldpr) and the operand fragments,
-// sized for the larger of the int8 (A 4 B, B 16 B per element) and FP64 (8 B
-// each) layouts.
+// Workspace after the plain layout: PR (m x ldpr), LR (m x 64) and the operand
+// fragments, sized for the larger of the int8 (A 4 B, B 16 B per element) and
+// FP64 (8 B each) layouts.
 size_t carve_blocked(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, Blocked* b) {
     const size_t base = plain_workspace(m, n, k);
     Carver c(ws ? (char*)ws + base : nullptr);
     const int64_t ldpr = round_up(2 * (int64_t)panel, 64);
+    const int64_t ldlr = round_up(2 * (int64_t)kLeaf, 64);
     const int64_t Kp = round_up(panel, 32);
     const int64_t Mp = round_up(m > 0 ? m : 1, 128);
     const int64_t Np = round_up(n + k > 0 ? n + k : 1, 64);
     uint32_t* PR = c.take<uint32_t>(m * ldpr);
+    uint32_t* LR = c.take<uint32_t>(m * ldlr);
     int8_t* A = c.take<int8_t>(Mp * Kp * 8);
     int8_t* B = c.take<int8_t>(Np * Kp * 16);
     if (b) {
         plain_carve(ws, m, n, k, b->w);
-        b->PR = PR;
-        b->ldpr = ldpr;
+        b->PR = Mat{PR, ldpr};
+        b->LR = Mat{LR, ldlr};
         b->Afrag = A;
         b->Bfrag = B;
         b->panel = panel;
-        b->KB = (int32_t)(Kp / 32);
     }
     return base + c.off + 256;
+}
+
+// dst columns [col0, col0 + N) of every row: delta * C + E . X_S, where E is
+// ebuf columns [ecol0, ecol0 + wj), X_S the pivot rows of bookkeeping columns
+// [gslot0, gslot0 + wj) read from dst (before the update), and delta = 0 for
+// the rows whose pivot column lies in [gslot0, gslot0 + wj).
+hipError_t panel_product(const Blocked& b, const PlainArgs& w, bool fp64, Mat dst, int32_t gslot0,
+                         int32_t wj, int64_t col0, int64_t N, int64_t inj0, Mat ebuf,
+                         int64_t ecol0, hipStream_t s) {
+    const int64_t m = w.m;
+    if (N <= 0) return hipSuccess;
+    if (fp64) {
+        const int32_t KB = (int32_t)ceil_div(wj, 4);
+        const int64_t NB = ceil_div(N, 16);
+        const int64_t MB = ceil_div(m, 64) * 4;
+        double* Ad = (double*)b.Afrag;
+        double* Bd = (double*)b.Bfrag;
+        hipLaunchKernelGGL(build_b_f64_kernel, dim3((unsigned)ceil_div(NB * KB * 64, 256)), dim3(256),
+                           0, s, w, dst, gslot0, wj, col0, N, inj0, KB, NB, Bd);
+        hipLaunchKernelGGL(build_a_f64_kernel, dim3((unsigned)ceil_div(MB * KB * 64, 256)), dim3(256),
+                           0, s, w, ebuf, ecol0, wj, KB, MB, Ad);
+        hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)ceil_div(m, 64), (unsigned)ceil_div(N, 64)),
+                           dim3(kThreads), 0, s, w, dst, col0, N, Ad, Bd, KB, NB, gslot0,
+                           gslot0 + wj);
+    } else {
+        const int32_t KB = (int32_t)ceil_div(wj, 32);
+        const int64_t NB = ceil_div(N, 32);
+        const int64_t MB = ceil_div(m, 128) * 4;
+        uint32_t sc[4] = {1, 0, 0, 0};
+        for (int l = 1; l < 4; ++l) sc[l] = (uint32_t)(((uint64_t)sc[l - 1] * 256u) % w.F.p);
+        const uint4 scale = make_uint4(sc[0], sc[1], sc[2], sc[3]);
+        hipLaunchKernelGGL(build_b_kernel, dim3((unsigned)ceil_div(NB * KB * 64, 256)), dim3(256), 0,
+                           s, w, dst, gslot0, wj, col0, N, inj0, KB, NB, b.Bfrag, scale);
+        hipLaunchKernelGGL(build_a_kernel, dim3((unsigned)ceil_div(MB * KB * 64, 256)), dim3(256), 0,
+                           s, w, ebuf, ecol0, wj, KB, MB, b.Afrag);
+        hipLaunchKernelGGL(gemm_i8_kernel, dim3((unsigned)ceil_div(m, 128), (unsigned)ceil_div(N, 64)),
+                           dim3(kThreads), 0, s, w, dst, col0, N, b.Afrag, b.Bfrag, KB, gslot0,
+                           gslot0 + wj);
+    }
+    return hipGetLastError();
+}
+
+// Gauss-Jordan over bookkeeping columns [g0, g0 + wj) held in buf columns
+// [0, wj), with the transform block at buf columns [wj, 2 wj): one fused step
+// launch per column, then the last pivot row's deferred normalisation.
+hipError_t reduce_columns(const PlainArgs& w, Mat buf, int32_t g0, int32_t wj, hipStream_t s) {
+    PlainArgs pa = w;
+    pa.W = buf.M;
+    pa.ld = buf.ld;
+    pa.ncols = 2 * wj;
+    pa.nsearch = wj;
+    pa.coloff = g0;
+    pa.einject = wj;
+    for (int32_t js = 0; js < wj; ++js) {
+        hipError_t e = launch_gj_step(pa, js, wj + js + 1, s);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(panel_resolve_kernel, dim3(1), dim3(256), 0, s, w, buf, 2 * wj, g0 + wj - 1);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -402,6 +503,13 @@ size_t blocked_workspace(int64_t m, int64_t n, int64_t k, int32_t panel) {
     return carve_blocked(nullptr, m, n, k, panel, nullptr);
 }
 
+// Two-level blocked Gauss-Jordan.  Outer panels of `panel` columns; inside a
+// panel, leaves of kLeaf columns are reduced by the fused step kernel on the
+// small buffer LR, and each leaf's transform updates the rest of the panel
+// buffer PR (remaining panel columns and the outer transform block, where the
+// leaf's pivots carry their implicit 1) by an MFMA product with K = kLeaf.
+// After the last leaf, PR holds the reduced panel and the panel transform, and
+// one MFMA product with K = panel updates all trailing columns of W.
 hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, bool fp64,
                              PlainArgs& out, const linac_opts* opts, hipStream_t s) {
     Blocked b;
@@ -409,65 +517,50 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
     b.w.F = out.F;
     b.w.resolved = 1;
     out = b.w;
-    PlainArgs& w = b.w;
+    const PlainArgs& w = b.w;
     if (m == 0) return hipSuccess;
     const int64_t ncols = n + k;
     const unsigned tiles = (unsigned)ceil_div(m, kTileRows);
-    int64_t gemm_launches = 0;
+    const Mat Wm{w.W, w.ld};
+    int64_t outer_products = 0;
     hipError_t e = hipSuccess;
     for (int32_t j0 = 0; j0 < n && e == hipSuccess; j0 += panel) {
         const int32_t wj = (int32_t)(n - j0 < panel ? n - j0 : panel);
-        const int64_t col0 = j0 + wj;
-        const int64_t N = ncols - col0;
-        hipLaunchKernelGGL(panel_extract_kernel, dim3(tiles, (unsigned)ceil_div(b.ldpr, 256)),
-                           dim3(kThreads), 0, s, w, b.PR, b.ldpr, j0, wj);
-        PlainArgs pa = w;
-        pa.W = b.PR;
-        pa.ld = b.ldpr;
-        pa.ncols = 2 * wj;
-        pa.nsearch = wj;
-        pa.coloff = j0;
-        pa.einject = wj;
-        for (int32_t js = 0; js < wj && e == hipSuccess; ++js)
-            e = launch_gj_step(pa, js, wj + js + 1, s);
-        hipLaunchKernelGGL(panel_resolve_kernel, dim3(1), dim3(256), 0, s, w, b.PR, b.ldpr, j0, wj);
-        if (N > 0 && fp64) {
-            const int32_t KB = (int32_t)ceil_div(wj, 4);
-            const int64_t NB = ceil_div(N, 16);
-            const int64_t MB = ceil_div(m, 64) * 4;
-            double* Ad = (double*)b.Afrag;
-            double* Bd = (double*)b.Bfrag;
-            hipLaunchKernelGGL(build_b_f64_kernel, dim3((unsigned)ceil_div(NB * KB * 64, 256)),
-                               dim3(256), 0, s, w, j0, wj, col0, N, KB, NB, Bd);
-            hipLaunchKernelGGL(build_a_f64_kernel, dim3((unsigned)ceil_div(MB * KB * 64, 256)),
-                               dim3(256), 0, s, w, b.PR, b.ldpr, wj, KB, MB, Ad);
-            if (opts && opts->ev_begin && gemm_launches == 0) (void)hipEventRecord(opts->ev_begin, s);
-            hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)ceil_div(m, 64), (unsigned)ceil_div(N, 64)),
-                               dim3(kThreads), 0, s, w, col0, N, Ad, Bd, KB, NB, j0, wj);
-            ++gemm_launches;
-        } else if (N > 0) {
-            const int32_t KB = (int32_t)ceil_div(wj, 32);
-            const int64_t NB = ceil_div(N, 32);
-            const int64_t MB = ceil_div(m, 128) * 4;
-            uint32_t sc[4] = {1, 0, 0, 0};
-            for (int l = 1; l < 4; ++l) sc[l] = (uint32_t)(((uint64_t)sc[l - 1] * 256u) % w.F.p);
-            uint4 scale = make_uint4(sc[0], sc[1], sc[2], sc[3]);
-            hipLaunchKernelGGL(build_b_kernel, dim3((unsigned)ceil_div(NB * KB * 64, 256)), dim3(256),
-                               0, s, w, j0, wj, col0, N, KB, NB, b.Bfrag, scale);
-            hipLaunchKernelGGL(build_a_kernel, dim3((unsigned)ceil_div(MB * KB * 64, 256)), dim3(256),
-                               0, s, w, b.PR, b.ldpr, wj, KB, MB, b.Afrag);
-            if (opts && opts->ev_begin && gemm_launches == 0) (void)hipEventRecord(opts->ev_begin, s);
-            hipLaunchKernelGGL(gemm_i8_kernel, dim3((unsigned)ceil_div(m, 128), (unsigned)ceil_div(N, 64)),
-                               dim3(kThreads), 0, s, w, col0, N, b.Afrag, b.Bfrag, KB, j0, wj);
-            ++gemm_launches;
+        const bool leaves = wj > kLeaf;
+        hipLaunchKernelGGL(panel_extract_kernel, dim3(tiles, (unsigned)ceil_div(b.PR.ld, 256)),
+                           dim3(kThreads), 0, s, w, Wm, (int64_t)j0, b.PR, wj, leaves ? -1 : j0);
+        if (!leaves) {
+            e = reduce_columns(w, b.PR, j0, wj, s);
+        } else {
+            for (int32_t l0 = 0; l0 < wj && e == hipSuccess; l0 += kLeaf) {
+                const int32_t wl = wj - l0 < kLeaf ? wj - l0 : kLeaf;
+                hipLaunchKernelGGL(panel_extract_kernel,
+                                   dim3(tiles, (unsigned)ceil_div(b.LR.ld, 256)), dim3(kThreads), 0,
+                                   s, w, b.PR, (int64_t)l0, b.LR, wl, j0 + l0);
+                e = reduce_columns(w, b.LR, j0 + l0, wl, s);
+                // rest of PR: panel columns after the leaf and the outer transform
+                // block up to this leaf's pivots (beyond it every row is still zero)
+                if (e == hipSuccess)
+                    e = panel_product(b, w, fp64, b.PR, j0 + l0, wl, (int64_t)l0 + wl, wj,
+                                      (int64_t)wj + l0, b.LR, wl, s);
+                hipLaunchKernelGGL(panel_writeback_kernel, dim3((unsigned)ceil_div(m * wl, 256)),
+                                   dim3(256), 0, s, w, b.LR, b.PR, (int64_t)l0, wl, j0 + l0);
+            }
+        }
+        if (e != hipSuccess) break;
+        const int64_t N = ncols - (j0 + wj);
+        if (N > 0) {
+            if (opts && opts->ev_begin && outer_products == 0) (void)hipEventRecord(opts->ev_begin, s);
+            e = panel_product(b, w, fp64, Wm, j0, wj, (int64_t)j0 + wj, N, -1, b.PR, wj, s);
+            ++outer_products;
         }
         hipLaunchKernelGGL(panel_writeback_kernel, dim3((unsigned)ceil_div(m * wj, 256)), dim3(256),
-                           0, s, w, b.PR, b.ldpr, j0, wj);
+                           0, s, w, b.PR, Wm, (int64_t)j0, wj, j0);
         if (e == hipSuccess) e = hipGetLastError();
     }
-    if (opts && opts->ev_end && gemm_launches > 0) (void)hipEventRecord(opts->ev_end, s);
-    if (opts && opts->dominant_launches) *opts->dominant_launches = gemm_launches;
-    return e == hipSuccess ? hipGetLastError() : e;
+    if (opts && opts->ev_end && outer_products > 0) (void)hipEventRecord(opts->ev_end, s);
+    if (opts && opts->dominant_launches) *opts->dominant_launches = outer_products;
+    return e;
 }
 
 }  // namespace linac

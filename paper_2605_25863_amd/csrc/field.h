@@ -24,15 +24,23 @@ static constexpr uint32_t kMersenne31 = 0x7fffffffu;
 
 struct FieldConst {
     uint32_t p;
+    uint32_t pprime;  // -p^-1 mod 2^32 (Montgomery; p odd)
+    uint32_t r2;      // 2^64 mod p
     uint32_t pad;
-    double dp;      // (double)p
-    double pinv;    // fl(1 / p)
-    double two32_p; // fl(2^32 / p)
+    double dp;        // (double)p
+    double pinv;      // fl(1 / p)
+    double two32_p;   // fl(2^32 / p)
 };
 
 __host__ inline FieldConst make_field(uint32_t p) {
     FieldConst f;
     f.p = p;
+    // p^-1 mod 2^32 by Newton's iteration x <- x (2 - p x), exact bits doubling
+    uint32_t x = p;
+    for (int i = 0; i < 5; ++i) x *= 2u - p * x;
+    f.pprime = (uint32_t)(0u - x);
+    const uint64_t r1 = (uint64_t)(((uint64_t)1 << 32) % p);
+    f.r2 = (uint32_t)(r1 * r1 % p);
     f.pad = 0;
     f.dp = (double)p;
     f.pinv = 1.0 / (double)p;
@@ -95,6 +103,32 @@ __device__ __forceinline__ uint32_t mersenne_reduce(uint64_t z) {
     uint32_t hi = (uint32_t)(z >> 31);
     uint32_t s = lo + hi;  // < 2^32
     return reduce_2p(s, kMersenne31);
+}
+
+// Montgomery reduction (P. Montgomery, "Modular multiplication without trial
+// division", 1985) with R = 2^32: for T < p * 2^32 returns T / R mod p.  For
+// p < 2^31, T + m p < 2^64 and the quotient is below 2p.
+__device__ __forceinline__ uint32_t redc(uint64_t T, uint32_t p, uint32_t pprime) {
+    const uint32_t m = (uint32_t)T * pprime;
+    const uint64_t t = (T + (uint64_t)m * p) >> 32;
+    return t >= p ? (uint32_t)(t - p) : (uint32_t)t;
+}
+
+// a^-1 = a^(p-2) mod p (Fermat) by square-and-multiply in Montgomery form.  It
+// uses 32-bit integer multiplies only, so for a wave-uniform argument the
+// compiler keeps it on the scalar unit, off the vector pipeline and short in
+// latency.  p = 2 (even, no Montgomery form) has the single unit 1.
+__device__ inline uint32_t inv_mod_fermat(uint32_t a, const FieldConst& F) {
+    const uint32_t p = F.p;
+    if (p == 2) return a;
+    const uint32_t pp = F.pprime;
+    uint32_t x = redc((uint64_t)a * F.r2, p, pp);  // a R mod p
+    uint32_t r = redc((uint64_t)F.r2, p, pp);      // R mod p (Montgomery form of 1)
+    for (uint32_t e = p - 2; e != 0; e >>= 1) {
+        if (e & 1) r = redc((uint64_t)r * x, p, pp);
+        x = redc((uint64_t)x * x, p, pp);
+    }
+    return redc((uint64_t)r, p, pp);
 }
 
 // Modular inverse of a != 0 by the extended Euclidean algorithm.  Returns 0 for

@@ -45,7 +45,7 @@ struct PlainArgs {
     int32_t einject;  // >= 0: local column where the transform block E starts; the pivot
                       // row of local column j carries an implicit 1 at einject + j
     int32_t resolved; // 1: no deferred normalisation is left in W at the end
-    uint32_t* fcol[2];           // column j of the working matrix as of step j (ping-pong)
+    uint32_t* fcol[2];           // column j as of step j (ping-pong); bit 31 marks pivot rows
     uint32_t* is_piv;            // 1 for rows already chosen as pivots
     unsigned long long* slots;   // per column: (pivot row << 32) | inverse of its head
     int32_t* pivrow;             // s-th pivot row

@@ -8,11 +8,12 @@
 // lets this design fold all of them into a single kernel per column:
 //
 //  * Look-ahead pivot search.  Step j writes column j+1 anyway, so the blocks
-//    that own it also record its values (fcol) and post the smallest
-//    non-pivot row with a non-zero entry, packed with the inverse of that
-//    entry, through one 64-bit atomicMin into slot[j+1].  Step j+1 reads the
-//    slot at launch: the pivot row and its inverse are known with no extra
-//    launch and no host round trip (the host stays blind, as in the paper).
+//    that own it also record its values (fcol, with bit 31 marking rows that
+//    are already pivots) and post the smallest non-pivot row with a non-zero
+//    entry, packed with the inverse of that entry, through one 64-bit
+//    atomicMin into slot[j+1].  Step j+1 reads the slot at launch: the pivot
+//    row and its inverse are known with no extra launch and no host round trip
+//    (the host stays blind, as in the paper).
 //  * Virtual row swap.  Rows never move.  The pivot row q of step j is only
 //    read during step j, so every block can form its normalised values
 //    inv * W[q][c] on the fly; writing it back is deferred to step j+1, which
@@ -53,16 +54,9 @@ __device__ __forceinline__ uint32_t pick(const uint4& v, int e) {
     return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
 }
 
-// Post a pivot candidate (row, head value) for column `col`: the smallest row
-// wins; its inverse travels with it.  Called by one thread per block.
-__device__ void post_candidate(unsigned long long* slot, int row, uint32_t value, uint32_t p) {
-    unsigned long long cur = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((cur >> 32) <= (unsigned long long)row) return;  // a smaller row is already posted
-    uint32_t inv = inv_mod(value, p);
-    atomicMin(slot, ((unsigned long long)row << 32) | inv);
-}
-
-// Block-wide minimum of per-wave candidates (row, value); returns in thread 0.
+// Block-wide minimum of per-wave pivot candidates (row, head value), posted to
+// `slot` as (row << 32) | inverse of the head: the smallest row wins.  The
+// inverse is skipped when a smaller row has already been posted.
 __device__ void block_candidate(int wave, int lane, int src_lane, int best, uint32_t bestv,
                                 int* s_row, uint32_t* s_val, unsigned long long* slot,
                                 uint32_t p) {
@@ -81,7 +75,12 @@ __device__ void block_candidate(int wave, int lane, int src_lane, int best, uint
                 r = s_row[w];
                 v = s_val[w];
             }
-        if (r != INT32_MAX) post_candidate(slot, r, v, p);
+        if (r != INT32_MAX) {
+            const unsigned long long cur =
+                __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((cur >> 32) > (unsigned long long)r)
+                atomicMin(slot, ((unsigned long long)r << 32) | inv_mod(v, p));
+        }
     }
 }
 
@@ -191,11 +190,14 @@ __global__ __launch_bounds__(kThreads) void plain_step_kernel(PlainArgs a, int32
     uint4 x[kRowsPerWave];
     uint32_t f[kRowsPerWave];
     bool act[kRowsPerWave];
+    uint32_t pivmask = 0;  // bit rr: row row0 + rr is already a pivot row
 #pragma unroll
     for (int rr = 0; rr < kRowsPerWave; ++rr) {
         const int r = row0 + rr;
         const bool valid = r < a.m;
-        f[rr] = valid ? fcur[r] : 0u;
+        const uint32_t fr = valid ? fcur[r] : 0u;
+        pivmask |= (fr >> 31) << rr;
+        f[rr] = fr & 0x7fffffffu;
         const bool pend = r == qpend;
         bool on = valid && r != q;
         if (blockIdx.y != 0) on = on && (pend || (have_piv && f[rr] != 0));
@@ -242,8 +244,9 @@ __global__ __launch_bounds__(kThreads) void plain_step_kernel(PlainArgs a, int32
                 if (r >= a.m) break;
                 const uint32_t v = r == q ? pick(make_uint4(pn[0], pn[1], pn[2], pn[3]), e)
                                           : pick(x[rr], e);
-                fnext[r] = v;
-                if (v != 0 && r != q && a.is_piv[r] == 0 && r < best) {
+                const bool piv = ((pivmask >> rr) & 1u) || r == q;
+                fnext[r] = v | ((uint32_t)piv << 31);
+                if (v != 0 && !piv && r < best) {
                     best = r;
                     bestv = v;
                 }

@@ -1,0 +1,118 @@
+"""Autotuner: measure the result-neutral choices of the library on this GPU and
+write them as the JSON tuning table read by linac_load_tuning.
+
+    python -m paper_2605_25863_amd.tune [--quick] [--out PATH]
+
+It times, on seeded dense systems (entries uniform in [0, p), a seeded 31-bit
+prime, 16 right-hand sides):
+  * the plain path against the blocked int8 path at growing n, to find the
+    crossover "blocked_min";
+  * the blocked path at each candidate panel width, per size bucket ("panel");
+  * the batched launch at 1, 2, 4 and 8 resident workgroups per compute unit on
+    a batch of uneven systems ("batched_per_cu").
+Every candidate configuration computes the same unique RREF, so the table only
+changes speed.  The written file (default: tuning_gfx950.json next to this
+module) is loaded by the Python binding at import.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_OUT = os.path.join(HERE, "tuning_gfx950.json")
+PANELS = (64, 96, 128, 192, 256, 384, 512)
+
+
+def _time_solve(lx, torch, At, Bt, p, path, panel, reps):
+    m, n = At.shape
+    k = Bt.shape[1]
+    ws = torch.empty(lx.solve_workspace_bytes(m, n, k, path, panel), dtype=torch.uint8,
+                     device="cuda")
+    out = (torch.empty((n, k), dtype=torch.int32, device="cuda"),
+           torch.zeros(1, dtype=torch.int32, device="cuda"),
+           torch.empty(min(m, n), dtype=torch.int32, device="cuda"),
+           torch.empty(k, dtype=torch.uint8, device="cuda"))
+    lx.solve(At, Bt, p, path=path, panel_width=panel, out=out, workspace=ws)  # warm-up
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        lx.solve(At, Bt, p, path=path, panel_width=panel, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def tune(quick: bool = False):
+    import torch
+    import paper_2605_25863_amd as lx
+    import workloads
+
+    lx.load_tuning(None)  # measure from the built-in defaults
+    sizes = (512, 1024, 2048, 4096) if quick else (512, 1024, 2048, 4096, 8192)
+    reps = 2 if quick else 3
+    report = {"crossover": {}, "panels": {}}
+    blocked_min = None
+    rules = []
+    for n in sizes:
+        A, B, p = workloads.dense_system(seed=1000 + n, n=n, k=16)
+        At = torch.from_numpy(A.astype(np.int32)).cuda()
+        Bt = torch.from_numpy(B.astype(np.int32)).cuda()
+        t_plain = _time_solve(lx, torch, At, Bt, p, lx.PATH_PLAIN, 0, reps)
+        per_panel = {}
+        for w in PANELS:
+            if w > n:
+                continue
+            per_panel[w] = _time_solve(lx, torch, At, Bt, p, lx.PATH_BLOCKED_INT8, w, reps)
+        best_w = min(per_panel, key=per_panel.get)
+        report["crossover"][n] = {"plain_s": t_plain, "blocked_s": per_panel[best_w]}
+        report["panels"][n] = per_panel
+        if blocked_min is None and per_panel[best_w] < t_plain:
+            blocked_min = n
+        rules.append({"n_max": n, "panel": best_w})
+        print(f"n={n}: plain {t_plain * 1e3:.2f} ms, best panel {best_w}: "
+              f"{per_panel[best_w] * 1e3:.2f} ms", flush=True)
+    # the largest measured size covers everything above it
+    rules[-1]["n_max"] = 1 << 30
+    # batched: resident workgroups per CU
+    systems = workloads.batched_systems(seed=4, count=512 if quick else 1024)
+    prep = lx.prepare_batched(systems)
+    per_cu = {}
+    for c in (1, 2, 4, 8):
+        lx.load_tuning(json.dumps({"batched_per_cu": c}))
+        lx.solve_batched(systems, prepared=prep)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            lx.solve_batched(systems, prepared=prep)
+        torch.cuda.synchronize()
+        per_cu[c] = (time.perf_counter() - t0) / reps
+        print(f"batched per_cu={c}: {per_cu[c] * 1e3:.2f} ms", flush=True)
+    best_cu = min(per_cu, key=per_cu.get)
+    table = {"arch": "gfx950", "blocked_min": blocked_min or sizes[-1] * 2,
+             "panel": rules, "batched_per_cu": best_cu,
+             "measured": {"crossover_s": report["crossover"], "panel_s": report["panels"],
+                          "batched_s": per_cu}}
+    lx.load_tuning(None)
+    return table
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--out", default=DEFAULT_OUT)
+    args = ap.parse_args()
+    table = tune(args.quick)
+    with open(args.out, "w") as f:
+        json.dump(table, f, indent=1)
+    print(json.dumps({k: table[k] for k in ("blocked_min", "panel", "batched_per_cu")}))
+
+
+if __name__ == "__main__":
+    main()

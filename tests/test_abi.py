@@ -131,3 +131,33 @@ def test_binding_fails_loudly_without_gpu():
         pytest.skip("a GPU is visible")
     with pytest.raises(RuntimeError):
         lx.solve(np.eye(3, dtype=np.uint32), np.ones((3, 1), dtype=np.uint32), 7)
+
+
+def test_tuning_table_parsing(lib):
+    """linac_load_tuning: valid tables change the panel choice (seen through the
+    workspace size), malformed ones are rejected and leave the table alone."""
+    import json
+    sz_default, sz = ctypes.c_size_t(), ctypes.c_size_t()
+    opts = lx._opts(lx.PATH_BLOCKED_INT8)
+    assert lib.linac_load_tuning(None) == OK
+    assert lib.linac_solve_workspace(4096, 4096, 16, ctypes.byref(opts), ctypes.byref(sz_default)) == OK
+    table = {"blocked_min": 2048, "panel": [{"n_max": 1024, "panel": 64},
+                                            {"n_max": 1 << 30, "panel": 512}],
+             "batched_per_cu": 2, "arch": "gfx950", "measured": {"x": [1, 2.5, None, True]}}
+    assert lib.linac_load_tuning(json.dumps(table).encode()) == OK
+    assert lib.linac_solve_workspace(4096, 4096, 16, ctypes.byref(opts), ctypes.byref(sz)) == OK
+    assert sz.value > sz_default.value  # panel 512 needs larger panel buffers than 256
+    # AUTO below the crossover is the plain path (smallest workspace)
+    auto = lx._opts(lx.PATH_AUTO)
+    plain = lx._opts(lx.PATH_PLAIN)
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    lib.linac_solve_workspace(1500, 1500, 4, ctypes.byref(auto), ctypes.byref(a))
+    lib.linac_solve_workspace(1500, 1500, 4, ctypes.byref(plain), ctypes.byref(b))
+    assert a.value == b.value
+    for bad in (b"{", b"[1,2", b'{"panel": [{"n_max": 10, "panel": 33}]}',
+                b'{"batched_per_cu": 0}', b"{} trailing"):
+        assert lib.linac_load_tuning(bad) == INVALID
+    # the previous valid table is still in force
+    assert lib.linac_solve_workspace(4096, 4096, 16, ctypes.byref(opts), ctypes.byref(a)) == OK
+    assert a.value == sz.value
+    assert lib.linac_load_tuning(None) == OK
