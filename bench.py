@@ -2,21 +2,33 @@
 
 Default workload (the one the metric is quoted on): one dense n = 8192 system
 with 16 right-hand sides over a seeded 31-bit prime field, entries uniform in
-[0, p), solved by the plain Gauss-Jordan path (one fused step kernel per
-pivot column).  A step is one full linac_solve: pack [A | B], 8192
-elimination launches, extraction of X / rank / pivots / consistency.  Inputs
-are resident in HBM before the timed region.
+[0, p).  A step is one full linac_solve on inputs already resident in HBM:
+pack [A | B], eliminate, extract X / rank / pivots / consistency.  The
+reported path is the library's AUTO choice (the blocked int8-MFMA path at this
+size); the plain path (one fused step kernel per pivot column) is timed on the
+same input and reported beside it.
 
-Prints one JSON line.  The metric counts 2 n^3 / 3 operations per square
-system (the LINPACK convention, right-hand sides excluded).
+The metric counts 2 n^3 / 3 operations per square system (right-hand sides
+excluded).  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--config c2] [--no-cpu-baseline]
+    python bench.py [--config c2|c1|c3|c4|c5] [--path auto|plain|int8|fp64]
+                    [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Per-kernel rooflines come from one extra instrumented solve in which the
+library records a HIP event pair around every hot-kernel launch on its stream
+(outside the timed steps, so event recording does not slow them):
+  step          HBM-bound: 8 algorithmic bytes per element update (int32 read +
+                write), peak 8000 GB/s;
+  leaf/trail    int8 MFMA: 32 int8 operations per mod-p multiply-add (16 limb
+  products      products, 2 ops each), peak 5000 TOP/s;
+  batched       vector ALU: one Shoup mulmod-subtract = 17 VALU issue slots
+                (3 quarter-rate 32-bit multiplies + 5 simple ops), so the chip
+                peak is 256 CU x 64 lanes x 2.4 GHz / 17 = 2.31e12 updates/s.
 """
 
 from __future__ import annotations
 
 import argparse
-import ctypes
 import hashlib
 import json
 import os
@@ -29,6 +41,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+I8_PEAK_TOPS = 5000.0
+FP64_PEAK_TFLOPS = 78.6
+VALU_UPDATES_PEAK = 256 * 64 * 2.4e9 / 17.0  # updates/s
+LEAF = 32
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -41,6 +57,31 @@ def gj_updates(m: int, n: int, ncols: int) -> int:
 
 def metric_ops(n: int) -> float:
     return 2.0 * n ** 3 / 3.0
+
+
+def rect_metric_ops(m: int, n: int, r: int) -> float:
+    """2(mnr - (m+n) r^2 / 2 + r^3 / 3): the square formula for rank-r m x n."""
+    return 2.0 * (m * n * r - (m + n) * r * r / 2.0 + r ** 3 / 3.0)
+
+
+def blocked_work(m: int, n: int, ncols: int, panel: int):
+    """Algorithmic work of the two-level blocked path, per launch kind:
+    step element updates, and mod-p multiply-adds of the leaf and trailing
+    products (K x M x N per product)."""
+    steps_upd = 0
+    leaf_macs = 0
+    trail_macs = 0
+    for j0 in range(0, n, panel):
+        wj = min(panel, n - j0)
+        if wj > LEAF:
+            for l0 in range(0, wj, LEAF):
+                wl = min(LEAF, wj - l0)
+                steps_upd += (m - 1) * wl * (wl + 1)
+                leaf_macs += m * wj * wl
+        else:
+            steps_upd += (m - 1) * wj * (wj + 1)
+        trail_macs += m * (ncols - j0 - wj) * wj
+    return steps_upd, leaf_macs, trail_macs
 
 
 def kernel_source_hash(names) -> str:
@@ -84,10 +125,64 @@ def cpu_baseline(target_s: float = 15.0):
         if gj_updates(cand, cand, cand + 16) / rate <= target_s:
             n = cand
     t = run(n) if n != 1024 else t1
-    return {"value": metric_ops(n) / t / 1e9, "unit": "GOP/s", "cores": threads, "kind": "oracle",
+    return {"value": round(metric_ops(n) / t / 1e9, 3), "unit": "GOP/s", "cores": threads,
+            "kind": "oracle",
             "sample": f"C oracle Gauss-Jordan (uint64, %, OpenMP over rows) on the same seeded "
                       f"distribution at n={n} with 16 right-hand sides; {t:.2f} s",
             "seconds": round(t, 3), "n": n}
+
+
+PATHS = {"auto": 0, "plain": 1, "int8": 2, "fp64": 3}
+
+
+def _resolved_path(lx, m, n, path_name):
+    """The path AUTO takes for this shape (the library decides by size)."""
+    if path_name != "auto":
+        return path_name
+    auto = lx.solve_workspace_bytes(m, n, 0, lx.PATH_AUTO)
+    plain = lx.solve_workspace_bytes(m, n, 0, lx.PATH_PLAIN)
+    return "plain" if auto == plain else "int8"
+
+
+def _rooflines(kinds, m, n, ncols, path_name, panel, src_hash, workload):
+    out = {}
+    if path_name == "plain":
+        upd = gj_updates(m, n, ncols)
+        if "step" in kinds:
+            nl, ms = kinds["step"]
+            out["step"] = {"bound": "hbm", "kernel": "plain_step_kernel", "launches": nl,
+                           "avg_launch_us": ms * 1e3 / nl,
+                           "algorithmic_bytes_per_launch": 8.0 * upd / nl,
+                           "achieved": 8.0 * upd / (ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s"}
+    else:
+        steps_upd, leaf_macs, trail_macs = blocked_work(m, n, ncols, panel)
+        per_mac_ops, peak, unit = (32.0, I8_PEAK_TOPS, "TOP/s") if path_name == "int8" else \
+            (2.0, FP64_PEAK_TFLOPS, "TFLOP/s")
+        if "step" in kinds:
+            nl, ms = kinds["step"]
+            out["step"] = {"bound": "hbm", "kernel": "plain_step_kernel (panel leaves)",
+                           "launches": nl, "avg_launch_us": ms * 1e3 / nl,
+                           "algorithmic_bytes_per_launch": 8.0 * steps_upd / nl,
+                           "achieved": 8.0 * steps_upd / (ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s"}
+        for kind, macs, kname in (("leaf_product", leaf_macs, "gemm (leaf transform)"),
+                                  ("trail_product", trail_macs, "gemm (trailing update)")):
+            if kind in kinds:
+                nl, ms = kinds[kind]
+                out[kind] = {"bound": "mfma", "kernel": ("gemm_i8_kernel " if path_name == "int8"
+                                                         else "gemm_f64_kernel ") + kname,
+                             "launches": nl, "avg_launch_us": ms * 1e3 / nl,
+                             "algorithmic_ops_per_launch": per_mac_ops * macs / nl,
+                             "achieved": per_mac_ops * macs / (ms / 1e3) / 1e12, "peak": peak,
+                             "unit": unit}
+    for name, r in out.items():
+        r["frac"] = round(r["achieved"] / r["peak"], 4)
+        r["achieved"] = round(r["achieved"], 1)
+        r["avg_launch_us"] = round(r["avg_launch_us"], 3)
+        r["total_ms"] = round(kinds[name][1], 3)
+        r["traffic"] = measured_traffic(r["kernel"].split()[0], workload, src_hash)
+    return out
 
 
 def bench_dense(args):
@@ -95,9 +190,7 @@ def bench_dense(args):
     import paper_2605_25863_amd as lx
     import workloads
 
-    cfg = {"c1": 256, "c2": 8192, "c3": 16384}[args.config]
-    n_override = args.n
-    A, B, p = workloads.config(args.config, n=n_override)
+    A, B, p = workloads.config(args.config, n=args.n)
     m, n = A.shape
     k = B.shape[1]
     dev = torch.device("cuda:0")
@@ -108,47 +201,40 @@ def bench_dense(args):
            torch.zeros(1, dtype=torch.int32, device=dev),
            torch.empty(min(m, n), dtype=torch.int32, device=dev),
            torch.empty(k, dtype=torch.uint8, device=dev))
-    path = {"plain": lx.PATH_PLAIN, "int8": lx.PATH_BLOCKED_INT8, "auto": lx.PATH_AUTO}[args.path]
+    stream = torch.cuda.current_stream()
+    path_name = _resolved_path(lx, m, n, args.path)
+    path = PATHS[path_name]
     ws = torch.empty(lx.solve_workspace_bytes(m, n, k, path, args.panel), dtype=torch.uint8,
                      device=dev)
-    stream = torch.cuda.current_stream()
-    timer = lx.HipTimer()
-    launches = ctypes.c_int64(0)
 
-    def step(timed):
-        lx.solve(At, Bt, p, path=path, out=out, workspace=ws, stream=stream,
-                 events=timer if timed else None, launches=launches if timed else None,
-                 panel_width=args.panel)
+    def timed_solves(path, ws, steps, warmup):
+        for _ in range(warmup):
+            lx.solve(At, Bt, p, path=path, out=out, workspace=ws, stream=stream,
+                     panel_width=args.panel)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            lx.solve(At, Bt, p, path=path, out=out, workspace=ws, stream=stream,
+                     panel_width=args.panel)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
 
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    kernel_ms = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(True)
-        kernel_ms.append(timer.elapsed_ms())  # waits for this step's last step kernel
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = wall * 1e3 / args.steps
-    value = metric_ops(n) / (ms_per_step / 1e3) / 1e9
-
+    t_step = timed_solves(path, ws, args.steps, args.warmup)
     rank = int(out[1].item())
     assert rank == min(m, n), f"unexpected rank {rank}"
+    value = metric_ops(n) / t_step / 1e9
 
-    nl = int(launches.value)
-    upd = gj_updates(m, n, n + k)
-    alg_bytes_per_launch = 8.0 * upd / max(nl, 1)
-    avg_launch_s = (float(np.median(kernel_ms)) / 1e3) / max(nl, 1)
-    achieved = alg_bytes_per_launch / avg_launch_s / 1e9
-    src_hash = kernel_source_hash(["plain.hip", "field.h"])
-    traffic = measured_traffic("plain_step_kernel", args.config, src_hash)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": "plain_step_kernel",
-                "launches_per_step": nl, "avg_launch_us": round(avg_launch_s * 1e6, 3),
-                "algorithmic_bytes_per_launch": round(alg_bytes_per_launch),
-                "source_hash": src_hash}
+    # instrumented pass: one event pair around every hot-kernel launch
+    cap = n + 4 * (n // 32 + 8) + 64
+    lt = lx.LaunchTimes(cap)
+    lx.solve(At, Bt, p, path=path, out=out, workspace=ws, stream=stream, panel_width=args.panel,
+             per_launch=lt)
+    kinds = lt.by_kind()
+    panel = args.panel or 256
+    src_hash = kernel_source_hash(["plain.hip", "blocked.hip", "field.h"])
+    roofs = _rooflines(kinds, m, n, n + k, path_name, panel, src_hash, args.config)
+    dominant = max(roofs, key=lambda name: roofs[name]["total_ms"]) if roofs else None
+
     rec = {
         "metric": "mod-p elim GOP/s (2n^3/3 mulmod-add)",
         "value": round(value, 3),
@@ -156,19 +242,27 @@ def bench_dense(args):
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(t_step * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        "dtype": "u32" if path_name == "plain" else ("i8-mfma/u32" if path_name == "int8"
+                                                      else "f64-mfma/u32"),
         "data": "synthetic (seeded uniform residues)",
         "config": {"workload": f"{args.config}: one dense n={n} system, {k} right-hand sides, "
-                               f"p={p}, {args.path} Gauss-Jordan",
-                   "n": n, "k": k, "p": p, "path": args.path, "seed": {"c1": 1, "c2": 2,
-                                                                      "c3": 3}[args.config]},
-        "roofline": roofline,
-        "kernel_ms_per_step": round(float(np.median(kernel_ms)), 3),
+                               f"p={p}, {path_name} path", "n": n, "k": k, "p": p,
+                   "path": path_name, "seed": {"c1": 1, "c2": 2, "c3": 3}[args.config]},
+        "roofline": roofs.get(dominant),
+        "rooflines": roofs,
+        "kernel_ms_by_kind": {kk: round(v[1], 3) for kk, v in kinds.items()},
     }
+    if path_name != "plain" and not args.no_plain_compare:
+        wsp = torch.empty(lx.solve_workspace_bytes(m, n, k, lx.PATH_PLAIN), dtype=torch.uint8,
+                          device=dev)
+        tp = timed_solves(lx.PATH_PLAIN, wsp, max(1, min(args.steps, 3)), 1)
+        rec["plain"] = {"value": round(metric_ops(n) / tp / 1e9, 3), "unit": "GOP/s",
+                        "ms_per_step": round(tp * 1e3, 3),
+                        "speedup_of_reported_path": round(tp / t_step, 2)}
     return rec
 
 
@@ -183,21 +277,23 @@ def bench_batched(args):
     systems = workloads.batched_systems()
     prep = lx.prepare_batched(systems)
     stream = torch.cuda.current_stream()
-    timer = lx.HipTimer()
     for _ in range(args.warmup):
         lx.solve_batched(systems, prepared=prep, stream=stream)
     torch.cuda.synchronize()
-    kernel_ms = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        lx.solve_batched(systems, prepared=prep, stream=stream, events=timer)
-        kernel_ms.append(timer.elapsed_ms())
+        lx.solve_batched(systems, prepared=prep, stream=stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
     sps = len(systems) / (ms_per_step / 1e3)
     ops = sum(metric_ops(s["n"]) for s in systems)
     upd = sum(gj_updates(s["n"], s["n"], s["n"] + s["k"]) for s in systems)
+    lt = lx.LaunchTimes(4)
+    lx.solve_batched(systems, prepared=prep, stream=stream, per_launch=lt)
+    kinds = lt.by_kind()
+    nl, kms = kinds["batched"]
+    achieved = upd / (kms / 1e3)
     rec = {"metric": "systems/s batched (4096 uneven systems, one persistent launch)",
            "value": round(sps, 1), "unit": "systems/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
@@ -206,15 +302,18 @@ def bench_batched(args):
            "config": {"workload": "c4: 4096 systems, n~U{32..512}, k~U{1..8}, a seeded 31-bit "
                                   "prime each, 205 rank deficient"},
            "gop_per_s": round(ops / (ms_per_step / 1e3) / 1e9, 2),
-           "kernel_ms_per_step": round(float(np.median(kernel_ms)), 3),
-           "updates_per_s": round(upd / (float(np.median(kernel_ms)) / 1e3) / 1e12, 4)}
+           "roofline": {"bound": "alu", "kernel": "batched_kernel", "launches": nl,
+                        "avg_launch_us": round(kms * 1e3 / nl, 3),
+                        "achieved": round(achieved / 1e9, 2),
+                        "peak": round(VALU_UPDATES_PEAK / 1e9, 1), "unit": "Gupdates/s",
+                        "frac": round(achieved / VALU_UPDATES_PEAK, 4), "traffic": None}}
     if not args.no_plain_compare:
         # the same systems, one linac_solve each on the plain path
-        outs, wss = [], []
+        wss = []
         for it in prep["items"]:
-            m, n = it["A"].shape
-            k = it["B"].shape[1]
-            wss.append(torch.empty(lx.solve_workspace_bytes(m, n, k, lx.PATH_PLAIN),
+            mm, nn = it["A"].shape
+            kk = it["B"].shape[1]
+            wss.append(torch.empty(lx.solve_workspace_bytes(mm, nn, kk, lx.PATH_PLAIN),
                                    dtype=torch.uint8, device="cuda:0"))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -226,6 +325,58 @@ def bench_batched(args):
         rec["plain_systems_per_s"] = round(len(systems) / tp, 1)
         rec["speedup_vs_plain"] = round(sps / (len(systems) / tp), 2)
     return rec
+
+
+def bench_sparse_pattern(args):
+    """c5: instances of a 12000 x 10000 sparse-pattern matrix (rank about 9500),
+    full RREF with pivot columns, p = 2^31 - 1, one linac_rref per instance on
+    one stream (all inputs resident in HBM)."""
+    import torch
+    import paper_2605_25863_amd as lx
+    import workloads
+
+    count = args.instances
+    mats = []
+    for _, A in workloads.sparse_pattern_instances(instances=range(count)):
+        mats.append(torch.from_numpy(A.view(np.int32)).to("cuda:0"))
+    m, n = mats[0].shape
+    p = workloads.MERSENNE31
+    path_name = "plain" if args.path == "plain" else ("fp64" if args.path == "fp64" else "int8")
+    path = PATHS[path_name]
+    work = [torch.empty_like(A) for A in mats]
+    ws = torch.empty(lx.rref_workspace_bytes(m, n, path, args.panel), dtype=torch.uint8,
+                     device="cuda:0")
+    stream = torch.cuda.current_stream()
+    ranks = []
+
+    def one_pass(collect=False):
+        for A, Wk in zip(mats, work):
+            Wk.copy_(A)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs = [lx.rref(Wk, p, inplace=True, path=path, panel_width=args.panel, stream=stream,
+                        workspace=ws) for Wk in work]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if collect:
+            ranks.extend(int(o[1].item()) for o in outs)
+        return dt
+
+    for _ in range(args.warmup):
+        one_pass()
+    ts = [one_pass(collect=(i == 0)) for i in range(args.steps)]
+    t = float(np.median(ts))
+    ops = sum(rect_metric_ops(m, n, rr) for rr in ranks)
+    return {"metric": "mod-p elim GOP/s (2n^3/3 convention, rank-r rectangular)",
+            "value": round(ops / t / 1e9, 3), "unit": "GOP/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(t * 1e3, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "i8-mfma/u32",
+            "data": "synthetic (seeded shared sparsity pattern, stand-in for sample-point systems)",
+            "config": {"workload": f"c5: {count} instances of {m}x{n}, 200 nnz per independent "
+                                   f"row, 2500 dependent rows, p=2^31-1, full RREF, "
+                                   f"{path_name} path",
+                       "instances": count, "ranks": sorted(set(ranks))},
+            "ms_per_instance": round(t * 1e3 / count, 3)}
 
 
 def copy_calibration(mib: int = 1024, reps: int = 3):
@@ -247,10 +398,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--n", type=int, default=None, help="resize the dense workload")
-    ap.add_argument("--path", default="plain", choices=["plain", "int8", "auto"])
-    ap.add_argument("--panel", type=int, default=0, help="blocked panel width (0 = default)")
+    ap.add_argument("--path", default="auto", choices=list(PATHS))
+    ap.add_argument("--panel", type=int, default=0, help="blocked panel width (0 = tuned)")
+    ap.add_argument("--instances", type=int, default=64, help="c5 instances")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain-compare", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -264,6 +416,9 @@ def main():
         sys.exit(2)
     if args.config == "c4":
         print(json.dumps(bench_batched(args)), flush=True)
+        return
+    if args.config == "c5":
+        print(json.dumps(bench_sparse_pattern(args)), flush=True)
         return
     rec = bench_dense(args)
     if not args.no_cpu_baseline:

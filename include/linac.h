@@ -71,7 +71,23 @@ typedef struct {
     hipEvent_t ev_end;   /* optional: recorded immediately after its last launch */
     int64_t* dominant_launches; /* optional HOST pointer: receives the number of
                                    launches of the dominant kernel */
+    /* Optional per-launch timing (for profiling; adds an event record around
+     * every hot-kernel launch).  launch_events: HOST array of 2 * launch_cap
+     * caller-created events; pair i brackets the i-th recorded launch, whose
+     * kind (LINAC_KERNEL_*) goes to launch_kinds[i] (HOST array of launch_cap).
+     * *launch_used (HOST) receives the number of pairs recorded. */
+    hipEvent_t* launch_events;
+    int32_t* launch_kinds;
+    int32_t launch_cap;
+    int32_t* launch_used;
 } linac_opts;
+
+enum {
+    LINAC_KERNEL_STEP = 1,          /* fused Gauss-Jordan step (plain path and panel leaves) */
+    LINAC_KERNEL_LEAF_PRODUCT = 2,  /* blocked: leaf transform applied to the panel buffer */
+    LINAC_KERNEL_TRAIL_PRODUCT = 3, /* blocked: panel transform applied to the trailing columns */
+    LINAC_KERNEL_BATCHED = 4        /* batched persistent launch */
+};
 
 /* Workspace (bytes) needed by linac_rref for an m x n matrix. */
 linac_status linac_rref_workspace(int64_t m, int64_t n, const linac_opts* opts, size_t* bytes);

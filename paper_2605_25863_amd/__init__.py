@@ -33,7 +33,7 @@ __all__ = [
     "LinacError", "library_path", "row_reduce", "rref", "solve", "solve_batched",
     "drop_bottom_zero_rows", "pivot_columns_from_row_reduced_echelon_form", "HipTimer",
     "PATH_AUTO", "PATH_PLAIN", "PATH_BLOCKED_INT8", "PATH_BLOCKED_FP64", "check_prime",
-    "load_tuning", "TUNING_FILE",
+    "load_tuning", "TUNING_FILE", "LaunchTimes", "rref_workspace_bytes",
 ]
 
 PATH_AUTO, PATH_PLAIN, PATH_BLOCKED_INT8, PATH_BLOCKED_FP64 = 0, 1, 2, 3
@@ -58,7 +58,14 @@ class _Opts(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int), ("panel_width", ctypes.c_int),
                 ("validate", ctypes.c_int), ("verbose", ctypes.c_int),
                 ("ev_begin", ctypes.c_void_p), ("ev_end", ctypes.c_void_p),
-                ("dominant_launches", ctypes.POINTER(ctypes.c_int64))]
+                ("dominant_launches", ctypes.POINTER(ctypes.c_int64)),
+                ("launch_events", ctypes.POINTER(ctypes.c_void_p)),
+                ("launch_kinds", ctypes.POINTER(ctypes.c_int32)),
+                ("launch_cap", ctypes.c_int32),
+                ("launch_used", ctypes.POINTER(ctypes.c_int32))]
+
+
+KERNEL_KINDS = {1: "step", 2: "leaf_product", 3: "trail_product", 4: "batched"}
 
 
 class _System(ctypes.Structure):
@@ -125,7 +132,7 @@ def check_prime(p: int) -> int:
 
 
 def _opts(path=PATH_AUTO, panel_width=0, validate=False, verbose=False, events=None,
-          launches=None):
+          launches=None, per_launch=None):
     o = _Opts()
     o.path, o.panel_width = int(path), int(panel_width)
     o.validate, o.verbose = int(bool(validate)), int(bool(verbose))
@@ -133,7 +140,47 @@ def _opts(path=PATH_AUTO, panel_width=0, validate=False, verbose=False, events=N
         o.ev_begin, o.ev_end = events.begin, events.end
     if launches is not None:
         o.dominant_launches = ctypes.pointer(launches)
+    if per_launch is not None:
+        o.launch_events = per_launch.events
+        o.launch_kinds = per_launch.kinds
+        o.launch_cap = per_launch.cap
+        o.launch_used = ctypes.pointer(per_launch.used)
     return o
+
+
+class LaunchTimes:
+    """Events for the library's per-launch timing hook: after a call,
+    by_kind() returns {kind: (launches, total_ms)}."""
+
+    def __init__(self, cap: int):
+        self._hip = ctypes.CDLL("libamdhip64.so")
+        self.cap = int(cap)
+        self.events = (ctypes.c_void_p * (2 * self.cap))()
+        for i in range(2 * self.cap):
+            ev = ctypes.c_void_p()
+            assert self._hip.hipEventCreate(ctypes.byref(ev)) == 0
+            self.events[i] = ev.value
+        self.kinds = (ctypes.c_int32 * self.cap)()
+        self.used = ctypes.c_int32(0)
+
+    def by_kind(self):
+        self._hip.hipEventSynchronize(ctypes.c_void_p(self.events[2 * self.used.value - 1]))
+        out = {}
+        ms = ctypes.c_float()
+        for i in range(self.used.value):
+            assert self._hip.hipEventElapsedTime(ctypes.byref(ms), ctypes.c_void_p(self.events[2 * i]),
+                                                 ctypes.c_void_p(self.events[2 * i + 1])) == 0
+            name = KERNEL_KINDS.get(self.kinds[i], str(self.kinds[i]))
+            n, t = out.get(name, (0, 0.0))
+            out[name] = (n + 1, t + ms.value)
+        return out
+
+    def __del__(self):
+        try:
+            for i in range(2 * self.cap):
+                self._hip.hipEventDestroy(ctypes.c_void_p(self.events[i]))
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------------------
@@ -214,7 +261,7 @@ class HipTimer:
 
 def rref(A, p: int, *, inplace: bool = False, path: int = PATH_AUTO, validate: bool = False,
          verbose: bool = False, stream=None, events: HipTimer | None = None, launches=None,
-         panel_width: int = 0):
+         panel_width: int = 0, per_launch: "LaunchTimes | None" = None, workspace=None):
     """RREF of A over F_p.  Returns (R, rank, pivots) as device tensors (R int32
     m x n, rank int32[1], pivots int32[min(m, n)], ascending, -1 padded)."""
     torch = _torch()
@@ -226,12 +273,12 @@ def rref(A, p: int, *, inplace: bool = False, path: int = PATH_AUTO, validate: b
     m, n = At.shape
     rank = torch.zeros(1, dtype=torch.int32, device=dev)
     pivots = torch.empty(min(m, n), dtype=torch.int32, device=dev)
-    o = _opts(path, panel_width, validate, verbose, events, launches)
+    o = _opts(path, panel_width, validate, verbose, events, launches, per_launch)
     need = ctypes.c_size_t()
     _check(lib.linac_rref_workspace(m, n, ctypes.byref(o), ctypes.byref(need)), "rref_workspace")
-    ws = _workspace(torch, need.value, dev)
+    ws = workspace if workspace is not None else _workspace(torch, need.value, dev)
     _check(lib.linac_rref(_ptr(At), m, n, max(n, 1), int(p), _ptr(rank), _ptr(pivots), _ptr(ws),
-                          need.value, ctypes.byref(o), _stream(torch, stream)), "linac_rref")
+                          ws.numel(), ctypes.byref(o), _stream(torch, stream)), "linac_rref")
     return At, rank, pivots
 
 
@@ -251,7 +298,7 @@ def row_reduce(matrix, field_characteristic: int = 0, verbose: bool = False, **k
 
 def solve(A, B, p: int, *, path: int = PATH_AUTO, validate: bool = False, verbose: bool = False,
           stream=None, events: HipTimer | None = None, launches=None, out=None, workspace=None,
-          panel_width: int = 0):
+          panel_width: int = 0, per_launch: "LaunchTimes | None" = None):
     """Solve A X = B over F_p (Sec. 5.2).  Returns (X, rank, pivots, consistent).
 
     numpy in -> numpy out (rank as int); torch in -> device tensors out.
@@ -275,7 +322,7 @@ def solve(A, B, p: int, *, path: int = PATH_AUTO, validate: bool = False, verbos
         cons = torch.empty(k, dtype=torch.uint8, device=dev)
     else:
         X, rank, pivots, cons = out
-    o = _opts(path, panel_width, validate, verbose, events, launches)
+    o = _opts(path, panel_width, validate, verbose, events, launches, per_launch)
     need = ctypes.c_size_t()
     _check(lib.linac_solve_workspace(m, n, k, ctypes.byref(o), ctypes.byref(need)),
            "solve_workspace")
@@ -291,6 +338,14 @@ def solve(A, B, p: int, *, path: int = PATH_AUTO, validate: bool = False, verbos
     return X, rank, pivots, cons
 
 
+def rref_workspace_bytes(m: int, n: int, path: int = PATH_AUTO, panel_width: int = 0) -> int:
+    lib = _load()
+    o = _opts(path, panel_width)
+    need = ctypes.c_size_t()
+    _check(lib.linac_rref_workspace(m, n, ctypes.byref(o), ctypes.byref(need)), "rref_workspace")
+    return int(need.value)
+
+
 def solve_workspace_bytes(m: int, n: int, k: int, path: int = PATH_AUTO,
                           panel_width: int = 0) -> int:
     lib = _load()
@@ -302,7 +357,7 @@ def solve_workspace_bytes(m: int, n: int, k: int, path: int = PATH_AUTO,
 
 
 def solve_batched(systems, *, path: int = PATH_AUTO, verbose: bool = False, stream=None,
-                  events: HipTimer | None = None, launches=None, prepared=None):
+                  events: HipTimer | None = None, launches=None, prepared=None, per_launch=None):
     """Solve many independent systems in one launch.
 
     ``systems``: list of dicts {A, B, p} (numpy or device int32 tensors).
@@ -313,7 +368,7 @@ def solve_batched(systems, *, path: int = PATH_AUTO, verbose: bool = False, stre
     torch = _torch()
     prep = prepared if prepared is not None else prepare_batched(systems)
     lib = _load()
-    o = _opts(path, 0, False, verbose, events, launches)
+    o = _opts(path, 0, False, verbose, events, launches, per_launch)
     _check(lib.linac_solve_batched(prep["desc"], len(prep["items"]), _ptr(prep["ws"]),
                                    prep["ws"].numel(), ctypes.byref(o), _stream(torch, stream)),
            "linac_solve_batched")

@@ -496,7 +496,10 @@ linac_status linac_solve_batched(const linac_system* sys, int32_t count, void* w
         e = hipEventRecord(opts->ev_begin, s);
         if (e != hipSuccess) return hip_fail(e);
     }
+    LaunchTimer lt(opts, s);
+    lt.before(LINAC_KERNEL_BATCHED);
     e = hipGraphLaunch(exec, s);
+    lt.after();
     if (e != hipSuccess) return hip_fail(e);
     if (opts && opts->ev_end) {
         e = hipEventRecord(opts->ev_end, s);

@@ -444,7 +444,7 @@ size_t carve_blocked(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, B
 // the rows whose pivot column lies in [gslot0, gslot0 + wj).
 hipError_t panel_product(const Blocked& b, const PlainArgs& w, bool fp64, Mat dst, int32_t gslot0,
                          int32_t wj, int64_t col0, int64_t N, int64_t inj0, Mat ebuf,
-                         int64_t ecol0, hipStream_t s) {
+                         int64_t ecol0, hipStream_t s, LaunchTimer& lt, int kind) {
     const int64_t m = w.m;
     if (N <= 0) return hipSuccess;
     if (fp64) {
@@ -457,9 +457,11 @@ hipError_t panel_product(const Blocked& b, const PlainArgs& w, bool fp64, Mat ds
                            0, s, w, dst, gslot0, wj, col0, N, inj0, KB, NB, Bd);
         hipLaunchKernelGGL(build_a_f64_kernel, dim3((unsigned)ceil_div(MB * KB * 64, 256)), dim3(256),
                            0, s, w, ebuf, ecol0, wj, KB, MB, Ad);
+        lt.before(kind);
         hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)ceil_div(m, 64), (unsigned)ceil_div(N, 64)),
                            dim3(kThreads), 0, s, w, dst, col0, N, Ad, Bd, KB, NB, gslot0,
                            gslot0 + wj);
+        lt.after();
     } else {
         const int32_t KB = (int32_t)ceil_div(wj, 32);
         const int64_t NB = ceil_div(N, 32);
@@ -471,9 +473,11 @@ hipError_t panel_product(const Blocked& b, const PlainArgs& w, bool fp64, Mat ds
                            s, w, dst, gslot0, wj, col0, N, inj0, KB, NB, b.Bfrag, scale);
         hipLaunchKernelGGL(build_a_kernel, dim3((unsigned)ceil_div(MB * KB * 64, 256)), dim3(256), 0,
                            s, w, ebuf, ecol0, wj, KB, MB, b.Afrag);
+        lt.before(kind);
         hipLaunchKernelGGL(gemm_i8_kernel, dim3((unsigned)ceil_div(m, 128), (unsigned)ceil_div(N, 64)),
                            dim3(kThreads), 0, s, w, dst, col0, N, b.Afrag, b.Bfrag, KB, gslot0,
                            gslot0 + wj);
+        lt.after();
     }
     return hipGetLastError();
 }
@@ -481,7 +485,8 @@ hipError_t panel_product(const Blocked& b, const PlainArgs& w, bool fp64, Mat ds
 // Gauss-Jordan over bookkeeping columns [g0, g0 + wj) held in buf columns
 // [0, wj), with the transform block at buf columns [wj, 2 wj): one fused step
 // launch per column, then the last pivot row's deferred normalisation.
-hipError_t reduce_columns(const PlainArgs& w, Mat buf, int32_t g0, int32_t wj, hipStream_t s) {
+hipError_t reduce_columns(const PlainArgs& w, Mat buf, int32_t g0, int32_t wj, hipStream_t s,
+                          LaunchTimer& lt) {
     PlainArgs pa = w;
     pa.W = buf.M;
     pa.ld = buf.ld;
@@ -490,7 +495,9 @@ hipError_t reduce_columns(const PlainArgs& w, Mat buf, int32_t g0, int32_t wj, h
     pa.coloff = g0;
     pa.einject = wj;
     for (int32_t js = 0; js < wj; ++js) {
+        lt.before(LINAC_KERNEL_STEP);
         hipError_t e = launch_gj_step(pa, js, wj + js + 1, s);
+        lt.after();
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(panel_resolve_kernel, dim3(1), dim3(256), 0, s, w, buf, 2 * wj, g0 + wj - 1);
@@ -523,6 +530,7 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
     const unsigned tiles = (unsigned)ceil_div(m, kTileRows);
     const Mat Wm{w.W, w.ld};
     int64_t outer_products = 0;
+    LaunchTimer lt(opts, s);
     hipError_t e = hipSuccess;
     for (int32_t j0 = 0; j0 < n && e == hipSuccess; j0 += panel) {
         const int32_t wj = (int32_t)(n - j0 < panel ? n - j0 : panel);
@@ -530,19 +538,19 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
         hipLaunchKernelGGL(panel_extract_kernel, dim3(tiles, (unsigned)ceil_div(b.PR.ld, 256)),
                            dim3(kThreads), 0, s, w, Wm, (int64_t)j0, b.PR, wj, leaves ? -1 : j0);
         if (!leaves) {
-            e = reduce_columns(w, b.PR, j0, wj, s);
+            e = reduce_columns(w, b.PR, j0, wj, s, lt);
         } else {
             for (int32_t l0 = 0; l0 < wj && e == hipSuccess; l0 += kLeaf) {
                 const int32_t wl = wj - l0 < kLeaf ? wj - l0 : kLeaf;
                 hipLaunchKernelGGL(panel_extract_kernel,
                                    dim3(tiles, (unsigned)ceil_div(b.LR.ld, 256)), dim3(kThreads), 0,
                                    s, w, b.PR, (int64_t)l0, b.LR, wl, j0 + l0);
-                e = reduce_columns(w, b.LR, j0 + l0, wl, s);
+                e = reduce_columns(w, b.LR, j0 + l0, wl, s, lt);
                 // rest of PR: panel columns after the leaf and the outer transform
                 // block up to this leaf's pivots (beyond it every row is still zero)
                 if (e == hipSuccess)
                     e = panel_product(b, w, fp64, b.PR, j0 + l0, wl, (int64_t)l0 + wl, wj,
-                                      (int64_t)wj + l0, b.LR, wl, s);
+                                      (int64_t)wj + l0, b.LR, wl, s, lt, LINAC_KERNEL_LEAF_PRODUCT);
                 hipLaunchKernelGGL(panel_writeback_kernel, dim3((unsigned)ceil_div(m * wl, 256)),
                                    dim3(256), 0, s, w, b.LR, b.PR, (int64_t)l0, wl, j0 + l0);
             }
@@ -551,7 +559,8 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
         const int64_t N = ncols - (j0 + wj);
         if (N > 0) {
             if (opts && opts->ev_begin && outer_products == 0) (void)hipEventRecord(opts->ev_begin, s);
-            e = panel_product(b, w, fp64, Wm, j0, wj, (int64_t)j0 + wj, N, -1, b.PR, wj, s);
+            e = panel_product(b, w, fp64, Wm, j0, wj, (int64_t)j0 + wj, N, -1, b.PR, wj, s, lt,
+                              LINAC_KERNEL_TRAIL_PRODUCT);
             ++outer_products;
         }
         hipLaunchKernelGGL(panel_writeback_kernel, dim3((unsigned)ceil_div(m * wj, 256)), dim3(256),

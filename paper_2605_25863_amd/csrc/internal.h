@@ -60,6 +60,26 @@ struct PlainArgs {
 size_t plain_workspace(int64_t m, int64_t n, int64_t k);
 void plain_carve(void* ws, int64_t m, int64_t n, int64_t k, PlainArgs& a);
 
+// Optional per-launch timing through linac_opts (see include/linac.h).
+struct LaunchTimer {
+    const linac_opts* o;
+    hipStream_t s;
+    int32_t used = 0;
+    LaunchTimer(const linac_opts* opts, hipStream_t st) : o(opts), s(st) {}
+    bool on() const { return o && o->launch_events && o->launch_cap > 0 && used < o->launch_cap; }
+    void before(int kind) {
+        if (!on()) return;
+        (void)hipEventRecord(o->launch_events[2 * used], s);
+        if (o->launch_kinds) o->launch_kinds[used] = kind;
+    }
+    void after() {
+        if (!on()) return;
+        (void)hipEventRecord(o->launch_events[2 * used + 1], s);
+        ++used;
+        if (o->launch_used) *o->launch_used = used;
+    }
+};
+
 // One Gauss-Jordan step for local pivot column j over local columns [.., ncols_eff).
 hipError_t launch_gj_step(const PlainArgs& a, int32_t j, int32_t ncols_eff, hipStream_t s);
 

@@ -420,8 +420,11 @@ hipError_t plain_eliminate(const PlainArgs& a, const linac_opts* opts, hipStream
         if (e != hipSuccess) return e;
     }
     if (a.m > 0) {
+        LaunchTimer lt(opts, s);
         for (int32_t j = 0; j < a.nsearch; ++j) {
+            lt.before(LINAC_KERNEL_STEP);
             hipError_t e = launch_gj_step(a, j, a.ncols, s);
+            lt.after();
             if (e != hipSuccess) return e;
         }
     }
