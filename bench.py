@@ -17,10 +17,12 @@ excluded).  Prints one JSON line.
 Per-kernel rooflines come from one extra instrumented solve in which the
 library records a HIP event pair around every hot-kernel launch on its stream
 (outside the timed steps, so event recording does not slow them):
-  step          HBM-bound: 8 algorithmic bytes per element update (int32 read +
-                write), peak 8000 GB/s;
-  leaf/trail    int8 MFMA: 32 int8 operations per mod-p multiply-add (16 limb
-  products      products, 2 ops each), peak 5000 TOP/s;
+  step          plain path, HBM-bound: 8 algorithmic bytes per element update
+                (int32 read + write), peak 8000 GB/s;
+  leaf/trail    blocked path, int8 MFMA: 32 int8 operations per mod-p
+  products      multiply-add (16 limb products, 2 ops each), peak 5000 TOP/s
+                (the leaves' pivot selections and operand builds are listed
+                by time only);
   batched       vector ALU: one Shoup mulmod-subtract = 17 VALU issue slots
                 (3 quarter-rate 32-bit multiplies + 5 simple ops), so the chip
                 peak is 256 CU x 64 lanes x 2.4 GHz / 17 = 2.31e12 updates/s.
@@ -65,23 +67,20 @@ def rect_metric_ops(m: int, n: int, r: int) -> float:
 
 
 def blocked_work(m: int, n: int, ncols: int, panel: int):
-    """Algorithmic work of the two-level blocked path, per launch kind:
-    step element updates, and mod-p multiply-adds of the leaf and trailing
-    products (K x M x N per product)."""
-    steps_upd = 0
+    """Algorithmic work of the two-level blocked path: mod-p multiply-adds of
+    the leaf products (K = leaf width, M = m, N = panel width + leaf width: the
+    leaf's own columns, the panel columns after it and the transform block up
+    to it) and of the trailing products (K = panel width, N = trailing
+    columns)."""
     leaf_macs = 0
     trail_macs = 0
     for j0 in range(0, n, panel):
         wj = min(panel, n - j0)
-        if wj > LEAF:
-            for l0 in range(0, wj, LEAF):
-                wl = min(LEAF, wj - l0)
-                steps_upd += (m - 1) * wl * (wl + 1)
-                leaf_macs += m * wj * wl
-        else:
-            steps_upd += (m - 1) * wj * (wj + 1)
+        for l0 in range(0, wj, LEAF):
+            wl = min(LEAF, wj - l0)
+            leaf_macs += m * (wj + wl) * wl
         trail_macs += m * (ncols - j0 - wj) * wj
-    return steps_upd, leaf_macs, trail_macs
+    return leaf_macs, trail_macs
 
 
 def kernel_source_hash(names) -> str:
@@ -156,16 +155,9 @@ def _rooflines(kinds, m, n, ncols, path_name, panel, src_hash, workload):
                            "achieved": 8.0 * upd / (ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s"}
     else:
-        steps_upd, leaf_macs, trail_macs = blocked_work(m, n, ncols, panel)
+        leaf_macs, trail_macs = blocked_work(m, n, ncols, panel)
         per_mac_ops, peak, unit = (32.0, I8_PEAK_TOPS, "TOP/s") if path_name == "int8" else \
             (2.0, FP64_PEAK_TFLOPS, "TFLOP/s")
-        if "step" in kinds:
-            nl, ms = kinds["step"]
-            out["step"] = {"bound": "hbm", "kernel": "plain_step_kernel (panel leaves)",
-                           "launches": nl, "avg_launch_us": ms * 1e3 / nl,
-                           "algorithmic_bytes_per_launch": 8.0 * steps_upd / nl,
-                           "achieved": 8.0 * steps_upd / (ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s"}
         for kind, macs, kname in (("leaf_product", leaf_macs, "gemm (leaf transform)"),
                                   ("trail_product", trail_macs, "gemm (trailing update)")):
             if kind in kinds:
@@ -231,7 +223,7 @@ def bench_dense(args):
              per_launch=lt)
     kinds = lt.by_kind()
     panel = args.panel or 256
-    src_hash = kernel_source_hash(["plain.hip", "blocked.hip", "field.h"])
+    src_hash = kernel_source_hash(["plain.hip", "blocked.hip", "leaf.hip", "field.h"])
     roofs = _rooflines(kinds, m, n, n + k, path_name, panel, src_hash, args.config)
     dominant = max(roofs, key=lambda name: roofs[name]["total_ms"]) if roofs else None
 

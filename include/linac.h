@@ -86,7 +86,9 @@ enum {
     LINAC_KERNEL_STEP = 1,          /* fused Gauss-Jordan step (plain path and panel leaves) */
     LINAC_KERNEL_LEAF_PRODUCT = 2,  /* blocked: leaf transform applied to the panel buffer */
     LINAC_KERNEL_TRAIL_PRODUCT = 3, /* blocked: panel transform applied to the trailing columns */
-    LINAC_KERNEL_BATCHED = 4        /* batched persistent launch */
+    LINAC_KERNEL_BATCHED = 4,       /* batched persistent launch */
+    LINAC_KERNEL_SELECT = 5,        /* blocked: pivot selection of a leaf */
+    LINAC_KERNEL_OPERANDS = 6       /* blocked: building the MFMA operands of a product */
 };
 
 /* Workspace (bytes) needed by linac_rref for an m x n matrix. */

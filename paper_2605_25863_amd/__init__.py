@@ -65,7 +65,8 @@ class _Opts(ctypes.Structure):
                 ("launch_used", ctypes.POINTER(ctypes.c_int32))]
 
 
-KERNEL_KINDS = {1: "step", 2: "leaf_product", 3: "trail_product", 4: "batched"}
+KERNEL_KINDS = {1: "step", 2: "leaf_product", 3: "trail_product", 4: "batched", 5: "select",
+                6: "operands"}
 
 
 class _System(ctypes.Structure):

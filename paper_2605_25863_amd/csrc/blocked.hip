@@ -7,8 +7,9 @@
 // Panel step for pivot columns [j0, j0 + w):
 //  1. The panel columns of every row are copied to a side buffer PR next to a
 //     w-column block E that starts at zero.
-//  2. The fused step kernel of the plain path reduces PR column by column (all
-//     rows, Gauss-Jordan).  When row q becomes the pivot of local column s it
+//  2. PR is reduced in leaves of 32 columns (leaf.hip): a pivot selection
+//     picks the leaf's pivot rows and P^-1, and one MFMA product applies the
+//     leaf to the rest of PR.  When row q becomes the pivot of local column s it
 //     carries an implicit 1 in E[q][s], so the row operations applied to E
 //     record, for every row r, the coefficients of its final value in terms of
 //     the panel's pivot rows as they were at the panel start:
@@ -63,75 +64,21 @@ struct Mat {
 };
 
 // Copy columns [c0, c0 + width) of src into dst (all of dst's other columns,
-// including the transform block, set to zero).  With gcol >= 0 also record
-// column 0 of dst as the next pivot column's values and post its pivot
-// candidate (smallest non-pivot row with a non-zero entry) to slots[gcol].
-__global__ __launch_bounds__(kThreads) void panel_extract_kernel(PlainArgs w, Mat src, int64_t c0,
-                                                                 Mat dst, int32_t width,
-                                                                 int32_t gcol) {
-    __shared__ int s_row[4];
-    __shared__ uint32_t s_val[4];
+// including the transform block, set to zero).
+__global__ __launch_bounds__(kThreads) void panel_extract_kernel(int32_t m, Mat src, int64_t c0,
+                                                                 Mat dst, int32_t width) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t d0 = (int64_t)blockIdx.y * 256 + lane * 4;
     const int row0 = blockIdx.x * kTileRows + wave * 8;
-    const bool look = gcol >= 0 && blockIdx.y == 0;
-    int best = INT32_MAX;
-    uint32_t bestv = 0;
     for (int rr = 0; rr < 8; ++rr) {
         const int r = row0 + rr;
-        if (r >= w.m || d0 >= dst.ld) continue;
+        if (r >= m || d0 >= dst.ld) continue;
         uint32_t v[4];
         for (int e = 0; e < 4; ++e) {
             const int64_t c = d0 + e;
             v[e] = c < width ? src.M[(int64_t)r * src.ld + c0 + c] : 0u;
         }
         *(uint4*)(dst.M + (int64_t)r * dst.ld + d0) = make_uint4(v[0], v[1], v[2], v[3]);
-        if (look && lane == 0) {
-            const uint32_t piv = w.is_piv[r];
-            w.fcol[0][r] = v[0] | (piv << 31);
-            if (v[0] != 0 && piv == 0 && r < best) {
-                best = r;
-                bestv = v[0];
-            }
-        }
-    }
-    if (look) {
-        best = __shfl(best, 0);
-        bestv = __shfl(bestv, 0);
-        if (lane == 0) {
-            s_row[wave] = best;
-            s_val[wave] = bestv;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int r = s_row[0];
-            uint32_t v = s_val[0];
-            for (int q = 1; q < 4; ++q)
-                if (s_row[q] < r) {
-                    r = s_row[q];
-                    v = s_val[q];
-                }
-            if (r != INT32_MAX) {
-                unsigned long long* slot = &w.slots[gcol];
-                const unsigned long long cur =
-                    __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if ((cur >> 32) > (unsigned long long)r)
-                    atomicMin(slot, ((unsigned long long)r << 32) | inv_mod(v, w.F.p));
-            }
-        }
-    }
-}
-
-// Apply the deferred normalisation of the last pivot row (slot gcol_last) to
-// columns [0, width) of buf.
-__global__ void panel_resolve_kernel(PlainArgs w, Mat buf, int32_t width, int32_t gcol_last) {
-    const unsigned long long s = w.slots[gcol_last];
-    if (s == kNoPivot) return;
-    const int q = (int)(s >> 32);
-    const uint32_t inv = (uint32_t)s;
-    for (int c = threadIdx.x; c < width; c += blockDim.x) {
-        uint32_t* x = buf.M + (int64_t)q * buf.ld + c;
-        *x = mul_mod(*x, inv, w.F);
     }
 }
 
@@ -290,7 +237,24 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
         __syncthreads();
     }
     // epilogue: 32x32 accumulator layout: lane L holds column L%32 and rows
-    // 8*(r/4) + 4*(L/32) + r%4 for r = 0..15
+    // 8*(r/4) + 4*(L/32) + r%4 for r = 0..15.  All loads are issued before the
+    // first store so their latencies overlap.
+    bool fresh[16];
+    for (int r = 0; r < 16; ++r) {
+        const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int rc = row < w.m ? w.rowcol[row] : -1;
+        fresh[r] = rc >= fresh_lo && rc < fresh_hi;  // a pivot row of this panel
+    }
+    uint32_t cur[2][16];
+    for (int cbi = 0; cbi < 2; ++cbi) {
+        const int64_t col = (cb0 + cbi) * 32 + (lane & 31);
+        for (int r = 0; r < 16; ++r) {
+            const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            cur[cbi][r] = (col < N && row < w.m && !fresh[r])
+                              ? __builtin_nontemporal_load(dst.M + row * dst.ld + col0 + col)
+                              : 0u;
+        }
+    }
     for (int cbi = 0; cbi < 2; ++cbi) {
         const int64_t col = (cb0 + cbi) * 32 + (lane & 31);
         if (col >= N) continue;
@@ -299,10 +263,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
             if (row >= w.m) continue;
             const uint32_t t = fold_mod(acc[cbi][0][r], acc[cbi][1][r], acc[cbi][2][r],
                                         acc[cbi][3][r], w.F);
-            uint32_t* c = dst.M + row * dst.ld + col0 + col;
-            const int rc = w.rowcol[row];
-            const bool fresh = rc >= fresh_lo && rc < fresh_hi;  // a pivot row of this panel
-            *c = fresh ? t : add_mod(*c, t, w.F.p);
+            dst.M[row * dst.ld + col0 + col] = fresh[r] ? t : add_mod(cur[cbi][r], t, w.F.p);
         }
     }
 }
@@ -364,6 +325,24 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(PlainArgs w, Mat dst
             for (int b = 0; b < 2; ++b)
                 acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
     }
+    uint32_t cur[2][2][4];
+    bool fresh[2][4];
+    for (int a = 0; a < 2; ++a)
+        for (int i = 0; i < 4; ++i) {
+            const int64_t row = (rb0 + a) * 16 + (lane >> 4) + 4 * i;
+            const int rc = row < w.m ? w.rowcol[row] : -1;
+            fresh[a][i] = rc >= fresh_lo && rc < fresh_hi;
+        }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            const int64_t col = (cb0 + b) * 16 + (lane & 15);
+            for (int i = 0; i < 4; ++i) {
+                const int64_t row = (rb0 + a) * 16 + (lane >> 4) + 4 * i;
+                cur[a][b][i] = (col < N && row < w.m && !fresh[a][i])
+                                   ? dst.M[row * dst.ld + col0 + col]
+                                   : 0u;
+            }
+        }
     for (int a = 0; a < 2; ++a) {
         for (int b = 0; b < 2; ++b) {
             const int64_t col = (cb0 + b) * 16 + (lane & 15);
@@ -377,10 +356,8 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(PlainArgs w, Mat dst
                 if (r < 0.0) r += w.F.dp;
                 if (r >= w.F.dp) r -= w.F.dp;
                 const uint32_t t = (uint32_t)r;
-                uint32_t* c = dst.M + row * dst.ld + col0 + col;
-                const int rc = w.rowcol[row];
-                const bool fresh = rc >= fresh_lo && rc < fresh_hi;
-                *c = fresh ? t : add_mod(*c, t, w.F.p);
+                dst.M[row * dst.ld + col0 + col] =
+                    fresh[a][i] ? t : add_mod(cur[a][b][i], t, w.F.p);
             }
         }
     }
@@ -406,102 +383,98 @@ constexpr int32_t kLeaf = 32;  // inner panel width of the two-level reduction
 struct Blocked {
     PlainArgs w;  // the working matrix and the bookkeeping (shared with the plain path)
     Mat PR;       // outer panel [panel | E]
-    Mat LR;       // leaf [leaf | E_leaf]
     int8_t* Afrag;
     int8_t* Bfrag;
+    LeafState leaf;
     int32_t panel;
 };
 
-// Workspace after the plain layout: PR (m x ldpr), LR (m x 64) and the operand
-// fragments, sized for the larger of the int8 (A 4 B, B 16 B per element) and
-// FP64 (8 B each) layouts.
+// Workspace after the plain layout: PR (m x ldpr), the operand fragments (sized
+// for the larger of the int8 layouts, A 4 B and B 16 B per element, and the
+// FP64 ones, 8 B each, for both the trailing product and the leaf products) and
+// the leaf selection state.
 size_t carve_blocked(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, Blocked* b) {
     const size_t base = plain_workspace(m, n, k);
     Carver c(ws ? (char*)ws + base : nullptr);
     const int64_t ldpr = round_up(2 * (int64_t)panel, 64);
-    const int64_t ldlr = round_up(2 * (int64_t)kLeaf, 64);
     const int64_t Kp = round_up(panel, 32);
     const int64_t Mp = round_up(m > 0 ? m : 1, 128);
     const int64_t Np = round_up(n + k > 0 ? n + k : 1, 64);
+    const int64_t Nl = round_up(2 * (int64_t)panel + kLeaf, 64);  // leaf product columns
+    const int64_t abytes = Mp * (Kp > kLeaf ? Kp : kLeaf) * 8;
+    const int64_t bbytes = (Np * Kp > Nl * kLeaf ? Np * Kp : Nl * kLeaf) * 16;
     uint32_t* PR = c.take<uint32_t>(m * ldpr);
-    uint32_t* LR = c.take<uint32_t>(m * ldlr);
-    int8_t* A = c.take<int8_t>(Mp * Kp * 8);
-    int8_t* B = c.take<int8_t>(Np * Kp * 16);
+    int8_t* A = c.take<int8_t>(abytes);
+    int8_t* B = c.take<int8_t>(bbytes);
+    LeafState ls;
+    leaf_carve(c, m, &ls);
     if (b) {
         plain_carve(ws, m, n, k, b->w);
         b->PR = Mat{PR, ldpr};
-        b->LR = Mat{LR, ldlr};
         b->Afrag = A;
         b->Bfrag = B;
+        b->leaf = ls;
         b->panel = panel;
     }
     return base + c.off + 256;
 }
 
-// dst columns [col0, col0 + N) of every row: delta * C + E . X_S, where E is
-// ebuf columns [ecol0, ecol0 + wj), X_S the pivot rows of bookkeeping columns
-// [gslot0, gslot0 + wj) read from dst (before the update), and delta = 0 for
-// the rows whose pivot column lies in [gslot0, gslot0 + wj).
-hipError_t panel_product(const Blocked& b, const PlainArgs& w, bool fp64, Mat dst, int32_t gslot0,
-                         int32_t wj, int64_t col0, int64_t N, int64_t inj0, Mat ebuf,
-                         int64_t ecol0, hipStream_t s, LaunchTimer& lt, int kind) {
+// The product kernel: dst columns [col0, col0 + N) of every row become
+// delta * C + A . B from the prepared fragments (K = 32 KB for int8, 4 KB for
+// FP64); delta = 0 for the rows whose pivot column lies in [fresh_lo, fresh_hi).
+hipError_t run_product(const Blocked& b, const PlainArgs& w, bool fp64, Mat dst, int64_t col0,
+                       int64_t N, int32_t KB, int32_t fresh_lo, int32_t fresh_hi, hipStream_t s,
+                       LaunchTimer& lt, int kind) {
+    const int64_t m = w.m;
+    lt.before(kind);
+    if (fp64) {
+        hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)ceil_div(m, 64), (unsigned)ceil_div(N, 64)),
+                           dim3(kThreads), 0, s, w, dst, col0, N, (const double*)b.Afrag,
+                           (const double*)b.Bfrag, KB, ceil_div(N, 16), fresh_lo, fresh_hi);
+    } else {
+        hipLaunchKernelGGL(gemm_i8_kernel, dim3((unsigned)ceil_div(m, 128), (unsigned)ceil_div(N, 64)),
+                           dim3(kThreads), 0, s, w, dst, col0, N, b.Afrag, b.Bfrag, KB, fresh_lo,
+                           fresh_hi);
+    }
+    lt.after();
+    return hipGetLastError();
+}
+
+// Trailing update: dst columns [col0, col0 + N) of every row become
+// delta * C + E . X_S, where E is PR's transform block (columns [wj, 2 wj)) and
+// X_S the pivot rows of bookkeeping columns [j0, j0 + wj) read from dst (before
+// the update), with delta = 0 for the panel's pivot rows.
+hipError_t trailing_product(const Blocked& b, const PlainArgs& w, bool fp64, Mat dst, int32_t j0,
+                            int32_t wj, int64_t col0, int64_t N, hipStream_t s, LaunchTimer& lt) {
     const int64_t m = w.m;
     if (N <= 0) return hipSuccess;
+    lt.before(LINAC_KERNEL_OPERANDS);
+    int32_t KB;
     if (fp64) {
-        const int32_t KB = (int32_t)ceil_div(wj, 4);
+        KB = (int32_t)ceil_div(wj, 4);
         const int64_t NB = ceil_div(N, 16);
         const int64_t MB = ceil_div(m, 64) * 4;
-        double* Ad = (double*)b.Afrag;
-        double* Bd = (double*)b.Bfrag;
         hipLaunchKernelGGL(build_b_f64_kernel, dim3((unsigned)ceil_div(NB * KB * 64, 256)), dim3(256),
-                           0, s, w, dst, gslot0, wj, col0, N, inj0, KB, NB, Bd);
+                           0, s, w, dst, j0, wj, col0, N, (int64_t)-1, KB, NB, (double*)b.Bfrag);
         hipLaunchKernelGGL(build_a_f64_kernel, dim3((unsigned)ceil_div(MB * KB * 64, 256)), dim3(256),
-                           0, s, w, ebuf, ecol0, wj, KB, MB, Ad);
-        lt.before(kind);
-        hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)ceil_div(m, 64), (unsigned)ceil_div(N, 64)),
-                           dim3(kThreads), 0, s, w, dst, col0, N, Ad, Bd, KB, NB, gslot0,
-                           gslot0 + wj);
-        lt.after();
+                           0, s, w, b.PR, (int64_t)wj, wj, KB, MB, (double*)b.Afrag);
     } else {
-        const int32_t KB = (int32_t)ceil_div(wj, 32);
+        KB = (int32_t)ceil_div(wj, 32);
         const int64_t NB = ceil_div(N, 32);
         const int64_t MB = ceil_div(m, 128) * 4;
         uint32_t sc[4] = {1, 0, 0, 0};
         for (int l = 1; l < 4; ++l) sc[l] = (uint32_t)(((uint64_t)sc[l - 1] * 256u) % w.F.p);
         const uint4 scale = make_uint4(sc[0], sc[1], sc[2], sc[3]);
         hipLaunchKernelGGL(build_b_kernel, dim3((unsigned)ceil_div(NB * KB * 64, 256)), dim3(256), 0,
-                           s, w, dst, gslot0, wj, col0, N, inj0, KB, NB, b.Bfrag, scale);
+                           s, w, dst, j0, wj, col0, N, (int64_t)-1, KB, NB, b.Bfrag, scale);
         hipLaunchKernelGGL(build_a_kernel, dim3((unsigned)ceil_div(MB * KB * 64, 256)), dim3(256), 0,
-                           s, w, ebuf, ecol0, wj, KB, MB, b.Afrag);
-        lt.before(kind);
-        hipLaunchKernelGGL(gemm_i8_kernel, dim3((unsigned)ceil_div(m, 128), (unsigned)ceil_div(N, 64)),
-                           dim3(kThreads), 0, s, w, dst, col0, N, b.Afrag, b.Bfrag, KB, gslot0,
-                           gslot0 + wj);
-        lt.after();
+                           s, w, b.PR, (int64_t)wj, wj, KB, MB, b.Afrag);
     }
-    return hipGetLastError();
-}
-
-// Gauss-Jordan over bookkeeping columns [g0, g0 + wj) held in buf columns
-// [0, wj), with the transform block at buf columns [wj, 2 wj): one fused step
-// launch per column, then the last pivot row's deferred normalisation.
-hipError_t reduce_columns(const PlainArgs& w, Mat buf, int32_t g0, int32_t wj, hipStream_t s,
-                          LaunchTimer& lt) {
-    PlainArgs pa = w;
-    pa.W = buf.M;
-    pa.ld = buf.ld;
-    pa.ncols = 2 * wj;
-    pa.nsearch = wj;
-    pa.coloff = g0;
-    pa.einject = wj;
-    for (int32_t js = 0; js < wj; ++js) {
-        lt.before(LINAC_KERNEL_STEP);
-        hipError_t e = launch_gj_step(pa, js, wj + js + 1, s);
-        lt.after();
-        if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(panel_resolve_kernel, dim3(1), dim3(256), 0, s, w, buf, 2 * wj, g0 + wj - 1);
-    return hipGetLastError();
+    lt.after();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return run_product(b, w, fp64, dst, col0, N, KB, j0, j0 + wj, s, lt,
+                       LINAC_KERNEL_TRAIL_PRODUCT);
 }
 
 }  // namespace
@@ -511,12 +484,12 @@ size_t blocked_workspace(int64_t m, int64_t n, int64_t k, int32_t panel) {
 }
 
 // Two-level blocked Gauss-Jordan.  Outer panels of `panel` columns; inside a
-// panel, leaves of kLeaf columns are reduced by the fused step kernel on the
-// small buffer LR, and each leaf's transform updates the rest of the panel
-// buffer PR (remaining panel columns and the outer transform block, where the
-// leaf's pivots carry their implicit 1) by an MFMA product with K = kLeaf.
-// After the last leaf, PR holds the reduced panel and the panel transform, and
-// one MFMA product with K = panel updates all trailing columns of W.
+// panel, leaves of kLeaf columns: a pivot selection (leaf.hip) and one MFMA
+// product with K = kLeaf that applies the leaf to the rest of the panel buffer
+// PR (the leaf's own columns, the panel columns after it and the outer
+// transform block, where the leaf's pivots carry their implicit 1).  After the
+// last leaf, PR holds the reduced panel and the panel transform, and one MFMA
+// product with K = panel updates all trailing columns of W.
 hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, bool fp64,
                              PlainArgs& out, const linac_opts* opts, hipStream_t s) {
     Blocked b;
@@ -531,36 +504,36 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
     const Mat Wm{w.W, w.ld};
     int64_t outer_products = 0;
     LaunchTimer lt(opts, s);
-    hipError_t e = hipSuccess;
+    hipError_t e = leaf_init(b.leaf, (int32_t)m, s);
+    int32_t leaf_index = 0;
     for (int32_t j0 = 0; j0 < n && e == hipSuccess; j0 += panel) {
         const int32_t wj = (int32_t)(n - j0 < panel ? n - j0 : panel);
-        const bool leaves = wj > kLeaf;
         hipLaunchKernelGGL(panel_extract_kernel, dim3(tiles, (unsigned)ceil_div(b.PR.ld, 256)),
-                           dim3(kThreads), 0, s, w, Wm, (int64_t)j0, b.PR, wj, leaves ? -1 : j0);
-        if (!leaves) {
-            e = reduce_columns(w, b.PR, j0, wj, s, lt);
-        } else {
-            for (int32_t l0 = 0; l0 < wj && e == hipSuccess; l0 += kLeaf) {
-                const int32_t wl = wj - l0 < kLeaf ? wj - l0 : kLeaf;
-                hipLaunchKernelGGL(panel_extract_kernel,
-                                   dim3(tiles, (unsigned)ceil_div(b.LR.ld, 256)), dim3(kThreads), 0,
-                                   s, w, b.PR, (int64_t)l0, b.LR, wl, j0 + l0);
-                e = reduce_columns(w, b.LR, j0 + l0, wl, s, lt);
-                // rest of PR: panel columns after the leaf and the outer transform
-                // block up to this leaf's pivots (beyond it every row is still zero)
-                if (e == hipSuccess)
-                    e = panel_product(b, w, fp64, b.PR, j0 + l0, wl, (int64_t)l0 + wl, wj,
-                                      (int64_t)wj + l0, b.LR, wl, s, lt, LINAC_KERNEL_LEAF_PRODUCT);
-                hipLaunchKernelGGL(panel_writeback_kernel, dim3((unsigned)ceil_div(m * wl, 256)),
-                                   dim3(256), 0, s, w, b.LR, b.PR, (int64_t)l0, wl, j0 + l0);
-            }
+                           dim3(kThreads), 0, s, w.m, Wm, (int64_t)j0, b.PR, wj);
+        for (int32_t l0 = 0; l0 < wj && e == hipSuccess; l0 += kLeaf) {
+            const int32_t wl = wj - l0 < kLeaf ? wj - l0 : kLeaf;
+            const int32_t parity = leaf_index & 1;
+            // the leaf's own columns, the panel columns after it and the transform
+            // block up to this leaf's pivots (beyond it every row is still zero)
+            const int64_t N = (int64_t)wj + wl;
+            lt.before(LINAC_KERNEL_SELECT);
+            e = leaf_select(w, b.leaf, b.PR.M, b.PR.ld, l0, wl, j0 + l0, parity, s);
+            lt.after();
+            if (e != hipSuccess) break;
+            lt.before(LINAC_KERNEL_OPERANDS);
+            e = leaf_operands(w, b.leaf, b.PR.M, b.PR.ld, l0, wl, wj, j0 + l0, N, parity, fp64,
+                              b.Afrag, b.Bfrag, s);
+            lt.after();
+            if (e != hipSuccess) break;
+            e = run_product(b, w, fp64, b.PR, (int64_t)l0, N, fp64 ? kLeaf / 4 : 1, j0 + l0,
+                            j0 + l0 + wl, s, lt, LINAC_KERNEL_LEAF_PRODUCT);
+            ++leaf_index;
         }
         if (e != hipSuccess) break;
         const int64_t N = ncols - (j0 + wj);
         if (N > 0) {
             if (opts && opts->ev_begin && outer_products == 0) (void)hipEventRecord(opts->ev_begin, s);
-            e = panel_product(b, w, fp64, Wm, j0, wj, (int64_t)j0 + wj, N, -1, b.PR, wj, s, lt,
-                              LINAC_KERNEL_TRAIL_PRODUCT);
+            e = trailing_product(b, w, fp64, Wm, j0, wj, (int64_t)j0 + wj, N, s, lt);
             ++outer_products;
         }
         hipLaunchKernelGGL(panel_writeback_kernel, dim3((unsigned)ceil_div(m * wj, 256)), dim3(256),

@@ -92,6 +92,45 @@ hipError_t plain_finish_solve(const PlainArgs& a, int32_t n, int32_t k, uint32_t
 hipError_t plain_finish_rref(const PlainArgs& a, uint32_t* A, int64_t lda, int32_t* rank,
                              int32_t* pivots, hipStream_t s);
 
+// Leaf pivot selection and leaf operands (leaf.hip).  The selection's result
+// for the current leaf: t pivots, their candidate-list positions, row ids and
+// leaf-local columns (ascending), and P^-1 for P = the pivot rows' values at
+// the pivot columns (row-major, stride 32).
+struct LeafOut {
+    int32_t t;
+    int32_t pad[63];
+    int32_t pos[32];
+    int32_t row[32];
+    int32_t col[32];
+    uint32_t pinv[32 * 32];
+};
+
+// Candidate lists (rows that are not pivots yet, ascending; ping-pong by leaf
+// parity), their lengths, the selection tree's arrival counters (one set per
+// parity) and node results.
+struct LeafState {
+    int32_t* cand[2];
+    int32_t* count;  // count[parity]
+    int32_t* cnt[2];
+    int32_t* res;
+    LeafOut* out;
+    int32_t nodes;
+    int32_t gmax;
+};
+
+int32_t leaf_nodes(int64_t m);
+void leaf_carve(Carver& c, int64_t m, LeafState* ls);
+hipError_t leaf_init(const LeafState& ls, int32_t m, hipStream_t s);
+hipError_t leaf_select(const PlainArgs& w, const LeafState& ls, const uint32_t* PR, int64_t ldpr,
+                       int32_t l0, int32_t wl, int32_t gcol0, int32_t parity, hipStream_t s);
+// Operands of the leaf product over PR columns [l0, l0 + N): the B operand
+// Y = P^-1 R and the A operand (multipliers), in the layouts of the blocked
+// path's product kernels (int8: 32 x 32 blocks with one k-block of 32; FP64:
+// 16 x 16 blocks with 8 k-blocks of 4); also compacts the candidate list.
+hipError_t leaf_operands(const PlainArgs& w, const LeafState& ls, const uint32_t* PR, int64_t ldpr,
+                         int32_t l0, int32_t wl, int32_t wj, int32_t gcol0, int64_t N,
+                         int32_t parity, bool fp64, void* Afrag, void* Bfrag, hipStream_t s);
+
 // Blocked path (blocked.hip): workspace = the plain layout followed by the panel
 // buffer and the MFMA operand fragments.  `a` carries the field in and the
 // carved bookkeeping out (for the shared extraction kernels).

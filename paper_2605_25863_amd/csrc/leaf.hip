@@ -1,0 +1,609 @@
+// Pivot selection for a leaf of at most 32 pivot columns, and the operands of
+// the leaf's product update (the blocked path's inner level).
+//
+// Over a field every non-zero entry is an acceptable pivot (Sec. 3.2,
+// "Pivoting"), and the reduced row-echelon form does not depend on which rows
+// serve as pivots.  The pivot columns of a leaf are fixed by the span of its
+// eligible rows (rows that are not pivots yet): column c is a pivot column iff
+// it raises the rank of the columns before it.  So any row basis of the leaf
+// gives its pivot columns, and the leaf is reduced as one block:
+//
+//   select    the candidate rows (eligible rows in row order) are cut into
+//             chunks of 64.  One workgroup per chunk runs Gauss-Jordan on its
+//             rows' leaf values (registers + LDS) and keeps a basis of at most
+//             32 rows.  Bases merge pairwise up a binary tree; the second of two
+//             siblings to finish does the merge.  A node that covers a prefix of
+//             the candidates and has full rank, or the root, is final.  With
+//             dense data the first chunk already has full rank.
+//   operands  Y = P^-1 R, where P is the pivot rows' values at the pivot
+//             columns and R those rows over the columns to update (with the
+//             implicit 1 of each new pivot in the panel's transform block), and
+//             the multipliers -L[i, C] of every other row, both in the MFMA
+//             operand layouts; the candidate list drops the new pivot rows.
+//   product   C <- C + A Y for the other rows, C <- Y for the pivot rows (the
+//             blocked path's MFMA product).
+//
+// The selection's Gauss-Jordan is fraction free (row_i <- d row_i - f_i row_q,
+// no inverse on the critical path) and also tracks, for every row, the
+// coefficients T of its current value in terms of the original pivot rows.  At
+// the end pivot row s equals D_s e_s on the pivot columns, so
+// P^-1 = diag(D)^-1 T.  D_s is the product of the pivot values d from step s
+// on (each later step scales row s by its d), so with c_s the product before
+// step s, D_s^-1 = c_s / (product of all d): one inverse per leaf.  Residues are held lazily in FP64, in (-3p, 3p): a product
+// a b - floor(fl(ab)/p) p is exact by FMA and lies in [-p, 2p).
+#include "internal.h"
+
+namespace linac {
+
+namespace {
+
+constexpr int kSelWaves = 16;
+constexpr int kSelThreads = 64 * kSelWaves;
+constexpr int kChunk = 64;     // candidate rows per tree node
+constexpr int kNodeInts = 64;  // per node: basis size, then its list positions
+
+struct Lazy {
+    double p, pinv;
+};
+
+// a b - q p, q = floor(fl(a b) / p): exact and in [-p, 2p) for |a|, |b| < 2^33.
+__device__ __forceinline__ double lz_mul(double a, double b, const Lazy& L) {
+    const double h = a * b;
+    const double l = __fma_rn(a, b, -h);
+    const double q = floor(h * L.pinv);
+    return __fma_rn(-q, L.p, h) + l;
+}
+
+// d v - f u, in (-3p, 3p).
+__device__ __forceinline__ double lz_ff(double d, double v, double f, double u, const Lazy& L) {
+    return lz_mul(d, v, L) - lz_mul(f, u, L);
+}
+
+// The residue in [0, p) of an integer x with |x| < 2^34.
+__device__ __forceinline__ double lz_canon(double x, const Lazy& L) {
+    const double q = floor(x * L.pinv);
+    double r = __fma_rn(-q, L.p, x);
+    if (r < 0.0) r += L.p;
+    if (r >= L.p) r -= L.p;
+    return r;
+}
+
+// The residue in [0, p) of an integer x with |x| < 2^53 (for tiny p the first
+// quotient may be off by more than one; the second pass starts below 3p).
+__device__ __forceinline__ double lz_canon_wide(double x, const Lazy& L) {
+    const double q = floor(x * L.pinv);
+    return lz_canon(__fma_rn(-q, L.p, x), L);
+}
+
+// a^-1 = a^(p-2) for a canonical non-zero a (lane-parallel square-and-multiply).
+__device__ double lz_inverse(double a, uint32_t p, const Lazy& L) {
+    double r = 1.0, x = a;
+    for (uint32_t e = p - 2; e != 0; e >>= 1) {
+        if (e & 1) r = lz_mul(r, x, L);
+        x = lz_mul(x, x, L);
+    }
+    return lz_canon(r, L);
+}
+
+__device__ __forceinline__ double readlane_d(double x, int lane) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+struct SelArgs {
+    PlainArgs w;
+    const uint32_t* PR;
+    int64_t ldpr;
+    int32_t l0;     // leaf start column in PR
+    int32_t wl;     // leaf width (1..32)
+    int32_t gcol0;  // global column of leaf column 0
+    int32_t gmax;   // level-0 nodes the grid covers
+    int32_t ncnt;   // arrival counters per launch
+    const int32_t* cand;
+    const int32_t* count;
+    int32_t* cnt_cur;
+    int32_t* cnt_next;
+    int32_t* res;
+    LeafOut* out;
+};
+
+// Shared memory of the selection kernel.
+struct Sel {
+    double f[2][64];              // the current pivot column (double-buffered by step)
+    unsigned long long mask[2];   // its eligible non-zero rows
+    double cp[32];                // product of the pivot values before pivot s
+    int32_t pos[64];              // list positions of this node's rows (lane order)
+    int32_t sidx[64];             // lane -> pivot index, -1
+    int32_t pl[32];               // pivot index -> lane
+    int32_t pc[32];               // pivot index -> leaf column
+    double total;                 // product of all pivot values
+    int32_t nrows;
+    int32_t t;
+    int32_t bcast;
+};
+
+__device__ int node_id(int level, int k, int gmax) {
+    int base = 0, n = gmax;
+    for (int l = 0; l < level; ++l) {
+        base += n;
+        n = (n + 1) >> 1;
+    }
+    return base + k;
+}
+
+// Gauss-Jordan over the leaf columns of the node's rows (lane = row).  Wave v
+// holds leaf columns v and v + 16 (v[]) and transform columns v and v + 16 (T[]).
+__device__ __forceinline__ void node_gj(const SelArgs& a, Sel& S, double v[2], double T[2], const Lazy& L) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int R = S.nrows;
+    const int32_t row = lane < R ? a.cand[S.pos[lane]] : -1;
+    for (int r = 0; r < 2; ++r) {
+        const int c = wave + 16 * r;
+        v[r] = (row >= 0 && c < a.wl) ? (double)a.PR[(int64_t)row * a.ldpr + a.l0 + c] : 0.0;
+        T[r] = 0.0;
+    }
+    if (threadIdx.x < 64) S.sidx[threadIdx.x] = -1;
+    const unsigned long long valid = R >= 64 ? ~0ull : ((1ull << R) - 1ull);
+    unsigned long long chosen = 0;
+    int t = 0;
+    double cprod = 1.0;  // common scale of the non-pivot rows' own coefficient
+    __syncthreads();
+    for (int j = 0; j < a.wl; ++j) {
+        const int buf = j & 1;
+        if (wave == (j & 15)) {
+            const double x = j < 16 ? v[0] : v[1];
+            const unsigned long long nz = __ballot(lz_canon(x, L) != 0.0);
+            S.f[buf][lane] = x;
+            if (lane == 0) S.mask[buf] = nz & valid & ~chosen;
+        }
+        __syncthreads();
+        const unsigned long long m = S.mask[buf];
+        const int mlo = uniform((int)(uint32_t)m), mhi = uniform((int)(uint32_t)(m >> 32));
+        if ((mlo | mhi) == 0) continue;  // free column
+        const int q = mlo != 0 ? __builtin_ctz((uint32_t)mlo) : 32 + __builtin_ctz((uint32_t)mhi);
+        const double fi = S.f[buf][lane];
+        const double d = S.f[buf][q];
+        const int s = t;
+        if (threadIdx.x == 0) {
+            S.pl[s] = q;
+            S.pc[s] = j;
+            S.sidx[q] = s;
+            S.cp[s] = cprod;
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int c = wave + 16 * r;
+            if (c > j && c < a.wl) {
+                const double u = readlane_d(v[r], q);
+                if (lane != q) v[r] = lz_ff(d, v[r], fi, u, L);
+            }
+            if (c < s) {
+                const double u = readlane_d(T[r], q);
+                if (lane != q) T[r] = lz_ff(d, T[r], fi, u, L);
+            } else if (c == s) {
+                T[r] = lane == q ? cprod : -lz_mul(fi, cprod, L);
+            }
+        }
+        cprod = lz_mul(cprod, d, L);
+        chosen |= 1ull << q;
+        t = s + 1;
+    }
+    if (threadIdx.x == 0) {
+        S.t = t;
+        S.total = cprod;
+    }
+    __syncthreads();
+}
+
+// Final node: P^-1, the leaf result and the pivot bookkeeping.
+__device__ __forceinline__ void publish(const SelArgs& a, Sel& S, const double T[2], const Lazy& L) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int t = S.t;
+    if (threadIdx.x == 0) {
+        S.bcast = a.w.state[0];
+        if (t > 0) S.total = lz_inverse(lz_canon(S.total, L), a.w.F.p, L);
+    }
+    __syncthreads();
+    const int s = lane < S.nrows ? S.sidx[lane] : -1;
+    if (s >= 0) {
+        const double dinv = lz_mul(S.cp[s], S.total, L);
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int c = wave + 16 * r;
+            if (c < t) a.out->pinv[s * 32 + c] = (uint32_t)lz_canon(lz_mul(dinv, T[r], L), L);
+        }
+    }
+    const int r0 = S.bcast;
+    if (threadIdx.x < t) {
+        const int i = threadIdx.x;
+        const int pos = S.pos[S.pl[i]];
+        const int row = a.cand[pos];
+        const int gcol = a.gcol0 + S.pc[i];
+        a.out->pos[i] = pos;
+        a.out->row[i] = row;
+        a.out->col[i] = S.pc[i];
+        a.w.pivrow[r0 + i] = row;
+        a.w.pivcol[r0 + i] = gcol;
+        a.w.colpiv[gcol] = r0 + i;
+        a.w.rowcol[row] = gcol;
+        a.w.is_piv[row] = 1u;
+        a.w.slots[gcol] = ((unsigned long long)row << 32) | 1ull;
+    }
+    if (threadIdx.x == 0) {
+        a.out->t = t;
+        a.w.state[0] = r0 + t;
+    }
+}
+
+__global__ __launch_bounds__(kSelThreads) void leaf_select_kernel(SelArgs a) {
+    __shared__ Sel S;
+    const Lazy L{(double)a.w.F.p, a.w.F.pinv};
+    for (int i = blockIdx.x * kSelThreads + threadIdx.x; i < a.ncnt; i += gridDim.x * kSelThreads)
+        a.cnt_next[i] = 0;
+    const int E = *a.count;
+    const int G = (E + kChunk - 1) / kChunk;
+    const int g = blockIdx.x;
+    if (E == 0) {
+        if (g == 0 && threadIdx.x == 0) a.out->t = 0;
+        return;
+    }
+    if (g >= G) return;
+    if (threadIdx.x < 64) S.pos[threadIdx.x] = g * kChunk + threadIdx.x;
+    if (threadIdx.x == 0) S.nrows = min(kChunk, E - g * kChunk);
+    __syncthreads();
+    int level = 0, k = g, nodes = G;
+    bool need_gj = true;
+    double v[2], T[2];
+    while (true) {
+        if (need_gj) node_gj(a, S, v, T, L);
+        const int t = S.t;
+        if ((k == 0 && t == a.wl) || nodes == 1) {
+            publish(a, S, T, L);
+            return;
+        }
+        const int up = (nodes + 1) >> 1;
+        if ((k ^ 1) >= nodes) {  // no sibling: the node passes up unchanged
+            ++level;
+            k >>= 1;
+            nodes = up;
+            need_gj = false;
+            continue;
+        }
+        int32_t* mine = a.res + (int64_t)node_id(level, k, a.gmax) * kNodeInts;
+        if (threadIdx.x < t) mine[1 + threadIdx.x] = S.pos[S.pl[threadIdx.x]];
+        if (threadIdx.x == 0) mine[0] = t;
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0)
+            S.bcast = atomicAdd(&a.cnt_cur[node_id(level + 1, k >> 1, a.gmax)], 1);
+        __syncthreads();
+        if (S.bcast == 0) return;  // the sibling finishes later and merges
+        __threadfence();
+        const int32_t* lres = a.res + (int64_t)node_id(level, k & ~1, a.gmax) * kNodeInts;
+        const int32_t* rres = a.res + (int64_t)node_id(level, k | 1, a.gmax) * kNodeInts;
+        const int tl = __hip_atomic_load(lres, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int tr = __hip_atomic_load(rres, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int take = tl == a.wl ? tl : tl + tr;  // a full left basis spans everything
+        if (threadIdx.x < tl)
+            S.pos[threadIdx.x] =
+                __hip_atomic_load(lres + 1 + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else if (threadIdx.x < take)
+            S.pos[threadIdx.x] = __hip_atomic_load(rres + 1 + threadIdx.x - tl, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0) S.nrows = take;
+        __syncthreads();
+        ++level;
+        k >>= 1;
+        nodes = up;
+        need_gj = true;
+    }
+}
+
+__global__ void leaf_init_kernel(int32_t* cand, int32_t* count, int32_t* cnt, int32_t ncnt2,
+                                 int32_t m) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = tid; i < m; i += stride) cand[i] = (int32_t)i;
+    for (int64_t i = tid; i < ncnt2; i += stride) cnt[i] = 0;
+    if (tid == 0) count[0] = m;
+}
+
+__device__ __forceinline__ int32_t centre(uint32_t v, uint32_t p) {
+    return v > (p - 1) / 2 ? (int32_t)v - (int32_t)p : (int32_t)v;
+}
+
+__device__ __forceinline__ void digits4(int32_t x, int8_t d[4]) {
+    for (int l = 0; l < 4; ++l) {
+        const int8_t lo = (int8_t)(x & 0xff);
+        d[l] = lo;
+        x = (x - lo) >> 8;
+    }
+}
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+struct OpArgs {
+    PlainArgs w;
+    const uint32_t* PR;
+    int64_t ldpr;
+    int32_t l0, wl, wj, gcol0;
+    int64_t N;  // PR columns [l0, l0 + N) are updated
+    const int32_t* cand;
+    int32_t* cand_next;
+    const int32_t* count;
+    int32_t* count_next;
+    const LeafOut* out;
+    void* Afrag;
+    void* Bfrag;
+    int32_t nyb, nab;  // blocks of the Y and A parts (the rest compact the list)
+    int32_t fp64;
+    uint4 scale;  // 256^l mod p, l = 0..3
+};
+
+// Y part: one block per 32 update columns.  Y[s][c] = sum_s' Pinv[s][s'] R[s'][c]
+// with Pinv split into 15- and 16-bit halves, so both partial sums stay below
+// 2^53 and accumulate exactly in FP64.
+__device__ void operands_y(const OpArgs& a, int b) {
+    __shared__ uint32_t sR[32][33];
+    __shared__ uint32_t sP[32][33];
+    __shared__ uint32_t sY[32][33];
+    const int tid = threadIdx.x;
+    const int t = a.out->t;
+    const FieldConst& F = a.w.F;
+    const int64_t c0 = (int64_t)b * 32;
+    for (int i = tid; i < 32 * 32; i += 256) {
+        const int s = i >> 5, c = i & 31;
+        uint32_t r = 0, pv = 0;
+        if (s < t) {
+            const int64_t col = c0 + c;
+            if (col < a.N) {
+                r = a.PR[(int64_t)a.out->row[s] * a.ldpr + a.l0 + col];
+                if (col == (int64_t)a.wj + a.out->col[s]) r = 1u;  // the new pivot's implicit 1
+            }
+            if (c < t) pv = a.out->pinv[s * 32 + c];
+        }
+        sR[s][c] = r;
+        sP[s][c] = pv;
+    }
+    __syncthreads();
+    {
+        const int s = tid >> 3, cb = (tid & 7) * 4;
+        double s1[4] = {0.0, 0.0, 0.0, 0.0}, s0[4] = {0.0, 0.0, 0.0, 0.0};
+        if (s < t) {
+            for (int k = 0; k < t; ++k) {
+                const uint32_t pv = sP[s][k];
+                const double hi = (double)(pv >> 16), lo = (double)(pv & 0xffffu);
+                for (int e = 0; e < 4; ++e) {
+                    const double r = (double)sR[k][cb + e];
+                    s1[e] = __fma_rn(hi, r, s1[e]);
+                    s0[e] = __fma_rn(lo, r, s0[e]);
+                }
+            }
+        }
+        const Lazy L{F.dp, F.pinv};
+        for (int e = 0; e < 4; ++e) {
+            const double h = lz_canon_wide(s1[e], L);
+            sY[s][cb + e] = (uint32_t)lz_canon_wide(__fma_rn(h, 65536.0, s0[e]), L);
+        }
+    }
+    __syncthreads();
+    if (!a.fp64) {
+        // int8 B fragment (cb = b, one k-block): plane 4l + l', lane L holds column
+        // L % 32 and rows 16 (L / 32) + i; row y pre-scaled by 256^l mod p
+        const int L = tid & 63, l = tid >> 6;
+        const uint32_t sc = l == 0 ? a.scale.x : l == 1 ? a.scale.y : l == 2 ? a.scale.z : a.scale.w;
+        int8_t outb[4][16];
+        for (int i = 0; i < 16; ++i) {
+            const uint32_t y = sY[16 * (L >> 5) + i][L & 31];
+            const uint32_t yl = l == 0 ? y : mul_mod(y, sc, F);
+            int8_t d[4];
+            digits4(centre(yl, F.p), d);
+            for (int lp = 0; lp < 4; ++lp) outb[lp][i] = d[lp];
+        }
+        int8_t* base = (int8_t*)a.Bfrag + ((int64_t)b * 16 + 4 * l) * 1024 + L * 16;
+        for (int lp = 0; lp < 4; ++lp) {
+            v4i vv;
+            __builtin_memcpy(&vv, outb[lp], 16);
+            *(v4i*)(base + lp * 1024) = vv;
+        }
+    } else {
+        // FP64 B fragments (cb16 = 2b, 2b + 1; 8 k-blocks of 4): lane L holds
+        // row 4 kb + L / 16, column 16 cb16 + L % 16
+        double* Bd = (double*)a.Bfrag;
+        for (int i = tid; i < 2 * 8 * 64; i += 256) {
+            const int half = i >> 9, kb = (i >> 6) & 7, L = i & 63;
+            const uint32_t y = sY[kb * 4 + (L >> 4)][half * 16 + (L & 15)];
+            Bd[(((int64_t)(2 * b + half)) * 8 + kb) * 64 + L] = (double)centre(y, F.p);
+        }
+    }
+}
+
+// Multiplier of row `row` for leaf pivot k: -L[row, C_k], or the unit vector e_s
+// for the leaf's own pivot row s.
+__device__ __forceinline__ uint32_t a_value(const OpArgs& a, int64_t row, int k, int t, int sel,
+                                            const int32_t* cols) {
+    if (row >= a.w.m || k >= t) return 0u;
+    if (sel >= 0) return k == sel ? 1u : 0u;
+    const uint32_t x = a.PR[row * a.ldpr + a.l0 + cols[k]];
+    return x == 0 ? 0u : a.w.F.p - x;
+}
+
+__device__ __forceinline__ int leaf_sel(const OpArgs& a, int64_t row, const int32_t* cols, int t) {
+    if (row >= a.w.m) return -1;
+    const int rc = a.w.rowcol[row] - a.gcol0;
+    if (rc < 0 || rc >= a.wl) return -1;
+    for (int s = 0; s < t; ++s)
+        if (cols[s] == rc) return s;
+    return -1;
+}
+
+__device__ void operands_a(const OpArgs& a, int b) {
+    __shared__ int32_t cols[32];
+    const int tid = threadIdx.x;
+    const int t = a.out->t;
+    if (tid < 32) cols[tid] = tid < t ? a.out->col[tid] : 0;
+    __syncthreads();
+    const uint32_t p = a.w.F.p;
+    if (!a.fp64) {
+        // int8 A fragment (rb, one k-block, limb l): lane L holds row 32 rb + L % 32
+        // and k = 16 (L / 32) + i
+        const int L = tid & 63;
+        const int64_t rb = (int64_t)b * 4 + (tid >> 6);
+        const int64_t row = rb * 32 + (L & 31);
+        const int sel = leaf_sel(a, row, cols, t);
+        int8_t outb[4][16];
+        for (int i = 0; i < 16; ++i) {
+            const int k = 16 * (L >> 5) + i;
+            int8_t d[4];
+            digits4(centre(a_value(a, row, k, t, sel, cols), p), d);
+            for (int l = 0; l < 4; ++l) outb[l][i] = d[l];
+        }
+        int8_t* base = (int8_t*)a.Afrag + rb * 4 * 1024 + L * 16;
+        for (int l = 0; l < 4; ++l) {
+            v4i vv;
+            __builtin_memcpy(&vv, outb[l], 16);
+            *(v4i*)(base + l * 1024) = vv;
+        }
+    } else {
+        // FP64 A fragment (rb of 16 rows, kb of 4): lane L holds row 16 rb + L % 16,
+        // k = 4 kb + L / 16; a block covers 2 row blocks x 8 k-blocks x 64 lanes
+        double* Ad = (double*)a.Afrag;
+        for (int i = tid; i < 2 * 8 * 64; i += 256) {
+            const int64_t rb = (int64_t)b * 2 + (i >> 9);
+            const int kb = (i >> 6) & 7, L = i & 63;
+            const int64_t row = rb * 16 + (L & 15);
+            const int sel = leaf_sel(a, row, cols, t);
+            Ad[(rb * 8 + kb) * 64 + L] =
+                (double)centre(a_value(a, row, kb * 4 + (L >> 4), t, sel, cols), p);
+        }
+    }
+}
+
+// Drop the leaf's pivot rows from the candidate list (order kept).
+__device__ void operands_compact(const OpArgs& a, int b) {
+    __shared__ int32_t pos[32];
+    const int tid = threadIdx.x;
+    const int t = a.out->t;
+    if (tid < 32) pos[tid] = tid < t ? a.out->pos[tid] : INT32_MAX;
+    __syncthreads();
+    const int E = *a.count;
+    const int64_t i = (int64_t)b * 256 + tid;
+    if (b == 0 && tid == 0) *a.count_next = E - t;
+    if (i >= E) return;
+    int shift = 0;
+    bool gone = false;
+    for (int s = 0; s < t; ++s) {
+        shift += pos[s] < i;
+        gone |= pos[s] == i;
+    }
+    if (!gone) a.cand_next[i - shift] = a.cand[i];
+}
+
+__global__ __launch_bounds__(256) void leaf_operands_kernel(OpArgs a) {
+    const int b = blockIdx.x;
+    if (b < a.nyb) operands_y(a, b);
+    else if (b < a.nyb + a.nab) operands_a(a, b - a.nyb);
+    else operands_compact(a, b - a.nyb - a.nab);
+}
+
+}  // namespace
+
+int32_t leaf_nodes(int64_t m) {
+    int64_t n = ceil_div(m > 0 ? m : 1, kChunk), tot = 0;
+    while (true) {
+        tot += n;
+        if (n == 1) break;
+        n = (n + 1) / 2;
+    }
+    return (int32_t)(tot + 1);
+}
+
+void leaf_carve(Carver& c, int64_t m, LeafState* ls) {
+    const int32_t nodes = leaf_nodes(m);
+    int32_t* cand0 = c.take<int32_t>(m > 0 ? m : 1);
+    int32_t* cand1 = c.take<int32_t>(m > 0 ? m : 1);
+    int32_t* count = c.take<int32_t>(64);
+    int32_t* cnt = c.take<int32_t>(2 * (int64_t)nodes);
+    int32_t* res = c.take<int32_t>((int64_t)nodes * kNodeInts);
+    LeafOut* out = c.take<LeafOut>(1);
+    if (ls) {
+        ls->cand[0] = cand0;
+        ls->cand[1] = cand1;
+        ls->count = count;
+        ls->cnt[0] = cnt;
+        ls->cnt[1] = cnt + nodes;
+        ls->res = res;
+        ls->out = out;
+        ls->nodes = nodes;
+        ls->gmax = (int32_t)ceil_div(m > 0 ? m : 1, kChunk);
+    }
+}
+
+hipError_t leaf_init(const LeafState& ls, int32_t m, hipStream_t s) {
+    const int64_t work = m > 2 * ls.nodes ? m : 2 * ls.nodes;
+    const unsigned blocks = (unsigned)(ceil_div(work, 256) < 1024 ? ceil_div(work, 256) : 1024);
+    hipLaunchKernelGGL(leaf_init_kernel, dim3(blocks), dim3(256), 0, s, ls.cand[0], ls.count,
+                       ls.cnt[0], 2 * ls.nodes, m);
+    return hipGetLastError();
+}
+
+hipError_t leaf_select(const PlainArgs& w, const LeafState& ls, const uint32_t* PR, int64_t ldpr,
+                       int32_t l0, int32_t wl, int32_t gcol0, int32_t parity, hipStream_t s) {
+    SelArgs a;
+    a.w = w;
+    a.PR = PR;
+    a.ldpr = ldpr;
+    a.l0 = l0;
+    a.wl = wl;
+    a.gcol0 = gcol0;
+    a.gmax = ls.gmax;
+    a.ncnt = ls.nodes;
+    a.cand = ls.cand[parity];
+    a.count = ls.count + parity;
+    a.cnt_cur = ls.cnt[parity];
+    a.cnt_next = ls.cnt[parity ^ 1];
+    a.res = ls.res;
+    a.out = ls.out;
+    hipLaunchKernelGGL(leaf_select_kernel, dim3((unsigned)ls.gmax), dim3(kSelThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t leaf_operands(const PlainArgs& w, const LeafState& ls, const uint32_t* PR, int64_t ldpr,
+                         int32_t l0, int32_t wl, int32_t wj, int32_t gcol0, int64_t N,
+                         int32_t parity, bool fp64, void* Afrag, void* Bfrag, hipStream_t s) {
+    OpArgs a;
+    a.w = w;
+    a.PR = PR;
+    a.ldpr = ldpr;
+    a.l0 = l0;
+    a.wl = wl;
+    a.wj = wj;
+    a.gcol0 = gcol0;
+    a.N = N;
+    a.cand = ls.cand[parity];
+    a.cand_next = ls.cand[parity ^ 1];
+    a.count = ls.count + parity;
+    a.count_next = ls.count + (parity ^ 1);
+    a.out = ls.out;
+    a.Afrag = Afrag;
+    a.Bfrag = Bfrag;
+    a.fp64 = fp64 ? 1 : 0;
+    a.nyb = (int32_t)ceil_div(N, 32);
+    // A fragments for every row block the product kernel reads: int8 128-row
+    // tiles of four 32-row blocks (4 per operand block); FP64 64-row tiles of
+    // four 16-row blocks (2 per operand block)
+    a.nab = fp64 ? (int32_t)(ceil_div(w.m, 64) * 2) : (int32_t)ceil_div(w.m, 128);
+    uint32_t sc[4] = {1, 0, 0, 0};
+    for (int l = 1; l < 4; ++l) sc[l] = (uint32_t)(((uint64_t)sc[l - 1] * 256u) % w.F.p);
+    a.scale = make_uint4(sc[0], sc[1], sc[2], sc[3]);
+    const int64_t ncb = ceil_div(w.m > 0 ? w.m : 1, 256);
+    hipLaunchKernelGGL(leaf_operands_kernel, dim3((unsigned)(a.nyb + a.nab + ncb)), dim3(256), 0,
+                       s, a);
+    return hipGetLastError();
+}
+
+}  // namespace linac

@@ -192,3 +192,44 @@ def test_fp64_large_and_rejects_big_primes(gpu):
     with pytest.raises(lx.LinacError) as e:
         lx.solve(A[:8, :8], B[:8], workloads.MERSENNE31, path=FP64)
     assert e.value.status == 2
+
+
+@pytest.mark.parametrize("m,n,panel,kind", [
+    (3000, 200, 64, "late"),       # each leaf's only pivot candidates sit in the last rows
+    (2500, 300, 256, "zero_leaves"),  # whole leaves of zero columns (no pivot at all)
+    (4200, 160, 128, "tall_lowrank"),  # rank 100 spread over 4200 rows: deep merge trees
+    (700, 900, 96, "scattered"),   # pivots of every leaf spread over many chunks
+])
+def test_selection_trees(gpu, m, n, panel, kind):
+    """Leaves whose basis is not inside the first chunk of candidate rows, so the
+    selection merges bases up the tree (and reaches the root)."""
+    rng = np.random.default_rng(m + n + panel)
+    p = workloads.draw_prime31(rng)
+    if kind == "late":
+        A = np.zeros((m, n), dtype=np.uint32)
+        A[m - n:, :] = workloads.uniform(rng, (n, n), p)
+        A[:m - n, ::7] = workloads.uniform(rng, (m - n, len(range(0, n, 7))), p)
+    elif kind == "zero_leaves":
+        A = workloads.uniform(rng, (m, n), p)
+        A[:, 32:96] = 0
+        A[:, 200:232] = 0
+    elif kind == "tall_lowrank":
+        L = workloads.uniform(rng, (m, 100), p).astype(np.uint64)
+        L[rng.random(m) < 0.97] = 0
+        U = workloads.uniform(rng, (100, n), p).astype(np.uint64)
+        A = oracle.matmul_mod(L, U, p).astype(np.uint32)
+    else:
+        A = workloads.uniform(rng, (m, n), p)
+        A[rng.random((m, n)) < 0.995] = 0
+    B = workloads.uniform(rng, (m, 3), p)
+    B[:, 0] = oracle.matmul_mod(A, workloads.uniform(rng, (n, 1), p), p)[:, 0]
+    tag = f"trees {kind} m={m} n={n} panel={panel} p={p}"
+    print(tag, flush=True)
+    _cmp(A, B, p, panel, tag)
+    _cmp_rref(A, p, panel, tag)
+    q = workloads.draw_prime_bits(rng, 20)
+    Aq, Bq = A % q, B % q
+    ref = oracle.solve(Aq, Bq, q)
+    got = _solve(Aq, Bq, q, panel, path=FP64)
+    for name, g, r in zip(("X", "rank", "pivots", "consistent"), got, ref):
+        assert np.array_equal(np.asarray(g), np.asarray(r)), f"{tag} fp64: {name}"
