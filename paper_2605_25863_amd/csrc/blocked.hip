@@ -21,15 +21,17 @@
 //
 // Exactness of the product on int8 MFMA.  Every residue is first centred,
 // x -> x - p when x > (p-1)/2, so |x| <= 2^30, then split into four signed
-// base-256 digits in [-128, 127].  For y = X_S[k][c] the operand is
-// pre-scaled: y_l = 256^l * y mod p for l = 0..3, each centred and split into
-// digits b_{l,l'}.  With a_l the digits of E[r][k],
-//    E[r][k] * y == sum_l a_l * y_l == sum_{l'} 256^{l'} sum_l a_l * b_{l,l'}  (mod p),
-// so four int32 accumulators S_{l'} = sum_k sum_l a_l b_{l,l'} suffice (16
-// int8 products per mod-p product).  |S_{l'}| <= 4 * K * 2^14 = K * 2^16 < 2^31
-// for K < 2^15, and T = S_0 + 2^8 S_1 + 2^16 S_2 + 2^24 S_3 stays below 2^50 in
-// magnitude for K <= 512, so it is exact in FP64 and one reduction mod p ends
-// the panel.  For p < 2^21 the centred residues are below 2^20 and the product
+// base-256 digits in [-128, 127]: x = sum_l 256^l x_l.  For an A entry a and
+// a B entry b,
+//    a * b = sum_{s=0..6} 256^s sum_{l + l' = s} a_l * b_l',
+// so seven int32 accumulators S_s = sum_k sum_{l+l'=s} a_l b_l' (16 int8 MFMA
+// products per mod-p product, at most four per group) give the product sum.
+// |S_s| <= 4 * K * 2^14 < 2^31 for K < 2^15.  T_lo = S_0 + 2^8 S_1 + 2^16 S_2
+// + 2^24 S_3 and T_hi = S_4 + 2^8 S_5 + 2^16 S_6 stay below 2^50 and 2^40 in
+// magnitude for K <= 512, so both are exact in FP64, and the result is
+// T_lo + (2^32 mod p) T_hi reduced mod p.  Both operands keep four digit
+// planes, so the B operand (read by every block of a column) is no larger
+// than A.  For p < 2^21 the centred residues are below 2^20 and the product
 // can instead run on FP64 MFMA directly: every partial sum is below K * 2^40,
 // exact while K <= 8192.
 #include "internal.h"
@@ -95,13 +97,11 @@ __device__ __forceinline__ uint32_t xs_value(const PlainArgs& w, Mat src, int32_
     return src.M[(int64_t)(s >> 32) * src.ld + col0 + col];
 }
 
-// B operand: X_S pre-scaled by 256^l and split into digits, stored in the lane
-// order of the 32x32x32 int8 MFMA: fragment (cb, kb, plane = 4*l + l') is 64
-// lanes x 16 bytes; lane L holds column cb*32 + L%32 and rows
-// k = kb*32 + 16*(L/32) + i, i = 0..15.
+// B operand: X_S split into digits, stored in the lane order of the 32x32x32
+// int8 MFMA: fragment (cb, kb, l') is 64 lanes x 16 bytes; lane L holds digit
+// l' of column cb*32 + L%32 and rows k = kb*32 + 16*(L/32) + i, i = 0..15.
 __global__ void build_b_kernel(PlainArgs w, Mat src, int32_t gslot0, int32_t wj, int64_t col0,
-                               int64_t N, int64_t inj0, int32_t KB, int64_t NB, int8_t* Bfrag,
-                               uint4 scale) {
+                               int64_t N, int64_t inj0, int32_t KB, int64_t NB, int8_t* Bfrag) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= NB * KB * 64) return;
     const int L = (int)(gid & 63);
@@ -110,23 +110,18 @@ __global__ void build_b_kernel(PlainArgs w, Mat src, int32_t gslot0, int32_t wj,
     const int64_t cb = t / KB;
     const int64_t col = cb * 32 + (L & 31);
     const uint32_t p = w.F.p;
-    const uint32_t sc[4] = {scale.x, scale.y, scale.z, scale.w};
-    int8_t out[16][16];  // [plane][i]
+    int8_t out[4][16];  // [digit][i]
     for (int i = 0; i < 16; ++i) {
         const int k = kb * 32 + 16 * (L >> 5) + i;
-        const uint32_t y = xs_value(w, src, gslot0, wj, col0, N, inj0, k, col);
-        for (int l = 0; l < 4; ++l) {
-            const uint32_t yl = l == 0 ? y : mul_mod(y, sc[l], w.F);
-            int8_t d[4];
-            digits4(centre(yl, p), d);
-            for (int lp = 0; lp < 4; ++lp) out[4 * l + lp][i] = d[lp];
-        }
+        int8_t d[4];
+        digits4(centre(xs_value(w, src, gslot0, wj, col0, N, inj0, k, col), p), d);
+        for (int l = 0; l < 4; ++l) out[l][i] = d[l];
     }
-    int8_t* base = Bfrag + ((cb * KB + kb) * 16) * 1024 + L * 16;
-    for (int pl = 0; pl < 16; ++pl) {
+    int8_t* base = Bfrag + ((cb * KB + kb) * 4) * 1024 + L * 16;
+    for (int l = 0; l < 4; ++l) {
         v4i v;
-        __builtin_memcpy(&v, out[pl], 16);
-        *(v4i*)(base + pl * 1024) = v;
+        __builtin_memcpy(&v, out[l], 16);
+        *(v4i*)(base + l * 1024) = v;
     }
 }
 
@@ -159,79 +154,73 @@ __global__ void build_a_kernel(PlainArgs w, Mat ebuf, int64_t ecol0, int32_t wj,
     }
 }
 
-// T = S0 + 2^8 S1 + 2^16 S2 + 2^24 S3 (exact in FP64) reduced mod p.
-__device__ __forceinline__ uint32_t fold_mod(int32_t s0, int32_t s1, int32_t s2, int32_t s3,
-                                             const FieldConst& F) {
-    double T = __fma_rn(16777216.0, (double)s3,
-                        __fma_rn(65536.0, (double)s2, __fma_rn(256.0, (double)s1, (double)s0)));
-    double q = floor(T * F.pinv);
-    double r = __fma_rn(-q, F.dp, T);
-    if (r < 0.0) r += F.dp;
-    if (r >= F.dp) r -= F.dp;
-    if (r < 0.0) r += F.dp;
-    return (uint32_t)r;
+// sum_s 256^s S_s reduced mod p, plus `add` (a residue, or 0): T_lo and T_hi
+// are exact in FP64; each is folded into [-p, 2p), T_hi is multiplied by
+// c32 = 2^32 mod p exactly (FMA split), and the sum is reduced once more.
+__device__ __forceinline__ uint32_t fold7(const v16i* acc, int r, uint32_t add, double c32,
+                                          const FieldConst& F) {
+    const double lo = __fma_rn(16777216.0, (double)acc[3][r],
+                               __fma_rn(65536.0, (double)acc[2][r],
+                                        __fma_rn(256.0, (double)acc[1][r], (double)acc[0][r])));
+    const double hi =
+        __fma_rn(65536.0, (double)acc[6][r], __fma_rn(256.0, (double)acc[5][r], (double)acc[4][r]));
+    const double rlo = __fma_rn(-floor(lo * F.pinv), F.dp, lo);
+    const double rhi = __fma_rn(-floor(hi * F.pinv), F.dp, hi);
+    const double h = rhi * c32;
+    const double l = __fma_rn(rhi, c32, -h);
+    const double t = __fma_rn(-floor(h * F.pinv), F.dp, h) + l + rlo + (double)add;  // (-3p, 5p)
+    double r2 = __fma_rn(-floor(t * F.pinv), F.dp, t);
+    if (r2 < 0.0) r2 += F.dp;
+    if (r2 >= F.dp) r2 -= F.dp;
+    return (uint32_t)r2;
 }
 
-// Product update C = delta * C + E . X_S (mod p) on int8 MFMA (C = dst columns
-// [col0, col0 + N); delta = 0 for the rows that became pivots of this panel).
-// Block: 4 waves; wave v owns rows [(4*bx + v)*32, +32) and the block's 64
-// columns (two 32-column blocks).  The B fragments of a k-block (2 x 16 planes
-// x 1 KB) are shared through LDS, double-buffered: the next k-block is loaded
-// into registers while MFMAs run on the current one, then written to the other
-// buffer.  A fragments (each wave needs only its own rows) are prefetched into
-// registers.
-// With grid.x = row tiles and a multiple of 8 of them, all blocks of one row
-// tile run on the same XCD, so each XCD's L2 holds one eighth of the A operand.
+// Product update C = delta * C + A . B (mod p) on int8 MFMA (C = dst columns
+// [col0, col0 + N); delta = 0 for the rows whose pivot column lies in
+// [fresh_lo, fresh_hi)).  Block: 4 waves over a 128 x 32 tile; wave v owns rows
+// [(4*bx + v)*32, +32) and the block's 32 columns, with the seven group
+// accumulators of one 32x32 MFMA block.  The B fragments of a k-block (4 digit
+// planes x 1 KB) are shared through LDS, double-buffered: the next k-block is
+// loaded into registers while the MFMAs run on the current one, then written
+// to the other buffer.  A fragments (each wave needs only its own rows) are
+// prefetched into registers.  With grid.x = row tiles and a multiple of 8 of
+// them, all blocks of one row tile run on the same XCD, so each XCD's L2 holds
+// one eighth of the A operand.
 __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat dst, int64_t col0,
                                                               int64_t N, const int8_t* Afrag,
                                                               const int8_t* Bfrag, int32_t KB,
-                                                              int32_t fresh_lo, int32_t fresh_hi) {
-    __shared__ v4i sB[2][2 * 16 * 64];  // 2 x 32 KB
+                                                              int32_t fresh_lo, int32_t fresh_hi,
+                                                              double c32) {
+    __shared__ v4i sB[2][4 * 64];  // 2 x 4 KB
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t rb = (int64_t)blockIdx.x * 4 + wave;
-    const int64_t cb0 = (int64_t)blockIdx.y * 2;
-    const int64_t NB = ceil_div(N, 32);
-    // each wave moves 8 of the 32 B fragments of a k-block; column blocks past
-    // the end read a valid block (their output columns are never written)
-    const int8_t* bsrc[8];
-    for (int i = 0; i < 8; ++i) {
-        const int f = wave * 8 + i;
-        int64_t cb = cb0 + f / 16;
-        if (cb >= NB) cb = NB - 1;
-        bsrc[i] = Bfrag + (cb * KB * 16 + (f % 16)) * 1024 + lane * 16;
-    }
+    const int64_t cb = blockIdx.y;
+    const int8_t* bsrc = Bfrag + (cb * KB * 4 + wave) * 1024 + lane * 16;  // wave v moves plane v
     const int8_t* asrc = Afrag + (rb * KB * 4) * 1024 + lane * 16;
-    v16i acc[2][4];
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 4; ++b)
-            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0;
-    v4i stage[8], af[4], an[4];
-    for (int i = 0; i < 8; ++i) stage[i] = *(const v4i*)bsrc[i];
+    v16i acc[7];
+    for (int g = 0; g < 7; ++g)
+        for (int r = 0; r < 16; ++r) acc[g][r] = 0;
+    v4i stage, af[4], an[4];
+    stage = *(const v4i*)bsrc;
     for (int l = 0; l < 4; ++l) af[l] = *(const v4i*)(asrc + l * 1024);
-    for (int i = 0; i < 8; ++i) sB[0][(wave * 8 + i) * 64 + lane] = stage[i];
+    sB[0][wave * 64 + lane] = stage;
     __builtin_amdgcn_s_waitcnt(0);  // nothing in flight at the loop head
     __syncthreads();
     for (int kb = 0; kb < KB; ++kb) {
         const bool more = kb + 1 < KB;
         if (more) {  // next k-block in flight while this one computes
-            for (int i = 0; i < 8; ++i)
-                stage[i] = *(const v4i*)(bsrc[i] + (int64_t)(kb + 1) * 16 * 1024);
+            stage = *(const v4i*)(bsrc + (int64_t)(kb + 1) * 4 * 1024);
             for (int l = 0; l < 4; ++l)
                 an[l] = *(const v4i*)(asrc + ((int64_t)(kb + 1) * 4 + l) * 1024);
         }
         const v4i* sb = sB[kb & 1];
-        for (int cbi = 0; cbi < 2; ++cbi) {
-            for (int l = 0; l < 4; ++l) {
-                v4i bf[4];
-                for (int lp = 0; lp < 4; ++lp) bf[lp] = sb[(cbi * 16 + 4 * l + lp) * 64 + lane];
-                for (int lp = 0; lp < 4; ++lp)
-                    acc[cbi][lp] =
-                        __builtin_amdgcn_mfma_i32_32x32x32_i8(af[l], bf[lp], acc[cbi][lp], 0, 0, 0);
-            }
-        }
+        v4i bf[4];
+        for (int lp = 0; lp < 4; ++lp) bf[lp] = sb[lp * 64 + lane];
+        for (int l = 0; l < 4; ++l)
+            for (int lp = 0; lp < 4; ++lp)
+                acc[l + lp] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[l], bf[lp], acc[l + lp], 0, 0, 0);
         if (more) {
-            v4i* nb = sB[(kb + 1) & 1];
-            for (int i = 0; i < 8; ++i) nb[(wave * 8 + i) * 64 + lane] = stage[i];
+            sB[(kb + 1) & 1][wave * 64 + lane] = stage;
             for (int l = 0; l < 4; ++l) af[l] = an[l];
         }
         __syncthreads();
@@ -239,32 +228,25 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
     // epilogue: 32x32 accumulator layout: lane L holds column L%32 and rows
     // 8*(r/4) + 4*(L/32) + r%4 for r = 0..15.  All loads are issued before the
     // first store so their latencies overlap.
+    const int64_t col = cb * 32 + (lane & 31);
     bool fresh[16];
+    uint32_t cur[16];
     for (int r = 0; r < 16; ++r) {
         const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         const int rc = row < w.m ? w.rowcol[row] : -1;
         fresh[r] = rc >= fresh_lo && rc < fresh_hi;  // a pivot row of this panel
     }
-    uint32_t cur[2][16];
-    for (int cbi = 0; cbi < 2; ++cbi) {
-        const int64_t col = (cb0 + cbi) * 32 + (lane & 31);
-        for (int r = 0; r < 16; ++r) {
-            const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            cur[cbi][r] = (col < N && row < w.m && !fresh[r])
-                              ? __builtin_nontemporal_load(dst.M + row * dst.ld + col0 + col)
-                              : 0u;
-        }
+    for (int r = 0; r < 16; ++r) {
+        const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        cur[r] = (col < N && row < w.m && !fresh[r])
+                     ? __builtin_nontemporal_load(dst.M + row * dst.ld + col0 + col)
+                     : 0u;
     }
-    for (int cbi = 0; cbi < 2; ++cbi) {
-        const int64_t col = (cb0 + cbi) * 32 + (lane & 31);
-        if (col >= N) continue;
-        for (int r = 0; r < 16; ++r) {
-            const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            if (row >= w.m) continue;
-            const uint32_t t = fold_mod(acc[cbi][0][r], acc[cbi][1][r], acc[cbi][2][r],
-                                        acc[cbi][3][r], w.F);
-            dst.M[row * dst.ld + col0 + col] = fresh[r] ? t : add_mod(cur[cbi][r], t, w.F.p);
-        }
+    if (col >= N) return;
+    for (int r = 0; r < 16; ++r) {
+        const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (row >= w.m) continue;
+        dst.M[row * dst.ld + col0 + col] = fold7(acc, r, cur[r], c32, w.F);
     }
 }
 
@@ -390,9 +372,9 @@ struct Blocked {
 };
 
 // Workspace after the plain layout: PR (m x ldpr), the operand fragments (sized
-// for the larger of the int8 layouts, A 4 B and B 16 B per element, and the
-// FP64 ones, 8 B each, for both the trailing product and the leaf products) and
-// the leaf selection state.
+// for the larger of the int8 layouts, 4 B per element, and the FP64 ones, 8 B,
+// for both the trailing product and the leaf products) and the leaf selection
+// state.
 size_t carve_blocked(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, Blocked* b) {
     const size_t base = plain_workspace(m, n, k);
     Carver c(ws ? (char*)ws + base : nullptr);
@@ -402,7 +384,7 @@ size_t carve_blocked(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, B
     const int64_t Np = round_up(n + k > 0 ? n + k : 1, 64);
     const int64_t Nl = round_up(2 * (int64_t)panel + kLeaf, 64);  // leaf product columns
     const int64_t abytes = Mp * (Kp > kLeaf ? Kp : kLeaf) * 8;
-    const int64_t bbytes = (Np * Kp > Nl * kLeaf ? Np * Kp : Nl * kLeaf) * 16;
+    const int64_t bbytes = (Np * Kp > Nl * kLeaf ? Np * Kp : Nl * kLeaf) * 8;
     uint32_t* PR = c.take<uint32_t>(m * ldpr);
     int8_t* A = c.take<int8_t>(abytes);
     int8_t* B = c.take<int8_t>(bbytes);
@@ -432,9 +414,10 @@ hipError_t run_product(const Blocked& b, const PlainArgs& w, bool fp64, Mat dst,
                            dim3(kThreads), 0, s, w, dst, col0, N, (const double*)b.Afrag,
                            (const double*)b.Bfrag, KB, ceil_div(N, 16), fresh_lo, fresh_hi);
     } else {
-        hipLaunchKernelGGL(gemm_i8_kernel, dim3((unsigned)ceil_div(m, 128), (unsigned)ceil_div(N, 64)),
+        const double c32 = (double)((((uint64_t)1) << 32) % w.F.p);
+        hipLaunchKernelGGL(gemm_i8_kernel, dim3((unsigned)ceil_div(m, 128), (unsigned)ceil_div(N, 32)),
                            dim3(kThreads), 0, s, w, dst, col0, N, b.Afrag, b.Bfrag, KB, fresh_lo,
-                           fresh_hi);
+                           fresh_hi, c32);
     }
     lt.after();
     return hipGetLastError();
@@ -462,11 +445,8 @@ hipError_t trailing_product(const Blocked& b, const PlainArgs& w, bool fp64, Mat
         KB = (int32_t)ceil_div(wj, 32);
         const int64_t NB = ceil_div(N, 32);
         const int64_t MB = ceil_div(m, 128) * 4;
-        uint32_t sc[4] = {1, 0, 0, 0};
-        for (int l = 1; l < 4; ++l) sc[l] = (uint32_t)(((uint64_t)sc[l - 1] * 256u) % w.F.p);
-        const uint4 scale = make_uint4(sc[0], sc[1], sc[2], sc[3]);
         hipLaunchKernelGGL(build_b_kernel, dim3((unsigned)ceil_div(NB * KB * 64, 256)), dim3(256), 0,
-                           s, w, dst, j0, wj, col0, N, (int64_t)-1, KB, NB, b.Bfrag, scale);
+                           s, w, dst, j0, wj, col0, N, (int64_t)-1, KB, NB, b.Bfrag);
         hipLaunchKernelGGL(build_a_kernel, dim3((unsigned)ceil_div(MB * KB * 64, 256)), dim3(256), 0,
                            s, w, b.PR, (int64_t)wj, wj, KB, MB, b.Afrag);
     }

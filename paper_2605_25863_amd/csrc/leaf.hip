@@ -117,6 +117,7 @@ struct Sel {
     unsigned long long mask[2];   // its eligible non-zero rows
     double cp[32];                // product of the pivot values before pivot s
     int32_t pos[64];              // list positions of this node's rows (lane order)
+    int32_t basis[32];            // list positions of the node's basis rows (pivot order)
     int32_t sidx[64];             // lane -> pivot index, -1
     int32_t pl[32];               // pivot index -> lane
     int32_t pc[32];               // pivot index -> leaf column
@@ -197,6 +198,8 @@ __device__ __forceinline__ void node_gj(const SelArgs& a, Sel& S, double v[2], d
         S.total = cprod;
     }
     __syncthreads();
+    if (threadIdx.x < t) S.basis[threadIdx.x] = S.pos[S.pl[threadIdx.x]];
+    __syncthreads();
 }
 
 // Final node: P^-1, the leaf result and the pivot bookkeeping.
@@ -204,6 +207,7 @@ __device__ __forceinline__ void publish(const SelArgs& a, Sel& S, const double T
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int t = S.t;
     if (threadIdx.x == 0) {
+        __hip_atomic_store(a.cnt_cur + (a.ncnt - 1), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         S.bcast = a.w.state[0];
         if (t > 0) S.total = lz_inverse(lz_canon(S.total, L), a.w.F.p, L);
     }
@@ -220,7 +224,7 @@ __device__ __forceinline__ void publish(const SelArgs& a, Sel& S, const double T
     const int r0 = S.bcast;
     if (threadIdx.x < t) {
         const int i = threadIdx.x;
-        const int pos = S.pos[S.pl[i]];
+        const int pos = S.basis[i];
         const int row = a.cand[pos];
         const int gcol = a.gcol0 + S.pc[i];
         a.out->pos[i] = pos;
@@ -239,9 +243,12 @@ __device__ __forceinline__ void publish(const SelArgs& a, Sel& S, const double T
     }
 }
 
+// The last arrival counter of each set is the "published" flag: once the final
+// node is known, workgroups still merging stop at their next tree level.
 __global__ __launch_bounds__(kSelThreads) void leaf_select_kernel(SelArgs a) {
     __shared__ Sel S;
     const Lazy L{(double)a.w.F.p, a.w.F.pinv};
+    int32_t* published = a.cnt_cur + (a.ncnt - 1);
     for (int i = blockIdx.x * kSelThreads + threadIdx.x; i < a.ncnt; i += gridDim.x * kSelThreads)
         a.cnt_next[i] = 0;
     const int E = *a.count;
@@ -252,16 +259,25 @@ __global__ __launch_bounds__(kSelThreads) void leaf_select_kernel(SelArgs a) {
         return;
     }
     if (g >= G) return;
+    if (threadIdx.x == 0)
+        S.bcast = g > 0 ? __hip_atomic_load(published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
     if (threadIdx.x < 64) S.pos[threadIdx.x] = g * kChunk + threadIdx.x;
     if (threadIdx.x == 0) S.nrows = min(kChunk, E - g * kChunk);
     __syncthreads();
+    if (S.bcast != 0) return;
     int level = 0, k = g, nodes = G;
-    bool need_gj = true;
     double v[2], T[2];
+    node_gj(a, S, v, T, L);
+    bool regs = true;  // v, T hold the Gauss-Jordan of the node's basis rows
     while (true) {
-        if (need_gj) node_gj(a, S, v, T, L);
         const int t = S.t;
         if ((k == 0 && t == a.wl) || nodes == 1) {
+            if (!regs) {  // a basis passed up without elimination: reduce it now
+                if (threadIdx.x < t) S.pos[threadIdx.x] = S.basis[threadIdx.x];
+                if (threadIdx.x == 0) S.nrows = t;
+                __syncthreads();
+                node_gj(a, S, v, T, L);
+            }
             publish(a, S, T, L);
             return;
         }
@@ -270,36 +286,53 @@ __global__ __launch_bounds__(kSelThreads) void leaf_select_kernel(SelArgs a) {
             ++level;
             k >>= 1;
             nodes = up;
-            need_gj = false;
             continue;
         }
         int32_t* mine = a.res + (int64_t)node_id(level, k, a.gmax) * kNodeInts;
-        if (threadIdx.x < t) mine[1 + threadIdx.x] = S.pos[S.pl[threadIdx.x]];
+        if (threadIdx.x < t) mine[1 + threadIdx.x] = S.basis[threadIdx.x];
         if (threadIdx.x == 0) mine[0] = t;
         __threadfence();
         __syncthreads();
-        if (threadIdx.x == 0)
-            S.bcast = atomicAdd(&a.cnt_cur[node_id(level + 1, k >> 1, a.gmax)], 1);
+        if (threadIdx.x == 0) {
+            const int old = atomicAdd(&a.cnt_cur[node_id(level + 1, k >> 1, a.gmax)], 1);
+            S.bcast = old == 0 ? 1
+                               : __hip_atomic_load(published, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
         __syncthreads();
-        if (S.bcast == 0) return;  // the sibling finishes later and merges
+        // first of the two siblings (the other merges later), or already published
+        if (S.bcast != 0) return;
         __threadfence();
         const int32_t* lres = a.res + (int64_t)node_id(level, k & ~1, a.gmax) * kNodeInts;
         const int32_t* rres = a.res + (int64_t)node_id(level, k | 1, a.gmax) * kNodeInts;
         const int tl = __hip_atomic_load(lres, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int tr = __hip_atomic_load(rres, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int take = tl == a.wl ? tl : tl + tr;  // a full left basis spans everything
-        if (threadIdx.x < tl)
-            S.pos[threadIdx.x] =
-                __hip_atomic_load(lres + 1 + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        else if (threadIdx.x < take)
-            S.pos[threadIdx.x] = __hip_atomic_load(rres + 1 + threadIdx.x - tl, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-        if (threadIdx.x == 0) S.nrows = take;
+        __syncthreads();  // every thread has read S.t before it changes
+        // a full left basis spans everything; an empty side adds nothing: no
+        // elimination needed, the other side's basis is the merged one
+        const bool lazy = tl == a.wl || tl == 0 || tr == 0;
+        const int32_t* one = tl == a.wl || tr == 0 ? lres : rres;
+        const int tone = tl == a.wl || tr == 0 ? tl : tr;
+        if (lazy) {
+            if (threadIdx.x < tone)
+                S.basis[threadIdx.x] = __hip_atomic_load(one + 1 + threadIdx.x, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+            if (threadIdx.x == 0) S.t = tone;
+        } else {
+            if (threadIdx.x < tl)
+                S.pos[threadIdx.x] = __hip_atomic_load(lres + 1 + threadIdx.x, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+            else if (threadIdx.x < tl + tr)
+                S.pos[threadIdx.x] = __hip_atomic_load(rres + 1 + threadIdx.x - tl,
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (threadIdx.x == 0) S.nrows = tl + tr;
+        }
         __syncthreads();
+        if (!lazy) node_gj(a, S, v, T, L);
+        regs = !lazy;
         ++level;
         k >>= 1;
         nodes = up;
-        need_gj = true;
     }
 }
 
@@ -341,7 +374,6 @@ struct OpArgs {
     void* Bfrag;
     int32_t nyb, nab;  // blocks of the Y and A parts (the rest compact the list)
     int32_t fp64;
-    uint4 scale;  // 256^l mod p, l = 0..3
 };
 
 // Y part: one block per 32 update columns.  Y[s][c] = sum_s' Pinv[s][s'] R[s'][c]
@@ -392,23 +424,22 @@ __device__ void operands_y(const OpArgs& a, int b) {
     }
     __syncthreads();
     if (!a.fp64) {
-        // int8 B fragment (cb = b, one k-block): plane 4l + l', lane L holds column
-        // L % 32 and rows 16 (L / 32) + i; row y pre-scaled by 256^l mod p
-        const int L = tid & 63, l = tid >> 6;
-        const uint32_t sc = l == 0 ? a.scale.x : l == 1 ? a.scale.y : l == 2 ? a.scale.z : a.scale.w;
-        int8_t outb[4][16];
-        for (int i = 0; i < 16; ++i) {
-            const uint32_t y = sY[16 * (L >> 5) + i][L & 31];
-            const uint32_t yl = l == 0 ? y : mul_mod(y, sc, F);
-            int8_t d[4];
-            digits4(centre(yl, F.p), d);
-            for (int lp = 0; lp < 4; ++lp) outb[lp][i] = d[lp];
-        }
-        int8_t* base = (int8_t*)a.Bfrag + ((int64_t)b * 16 + 4 * l) * 1024 + L * 16;
-        for (int lp = 0; lp < 4; ++lp) {
-            v4i vv;
-            __builtin_memcpy(&vv, outb[lp], 16);
-            *(v4i*)(base + lp * 1024) = vv;
+        // int8 B fragment (cb = b, one k-block): digit plane l', lane L holds
+        // column L % 32 and rows 16 (L / 32) + i
+        if (tid < 64) {
+            const int L = tid;
+            int8_t outb[4][16];
+            for (int i = 0; i < 16; ++i) {
+                int8_t d[4];
+                digits4(centre(sY[16 * (L >> 5) + i][L & 31], F.p), d);
+                for (int lp = 0; lp < 4; ++lp) outb[lp][i] = d[lp];
+            }
+            int8_t* base = (int8_t*)a.Bfrag + (int64_t)b * 4 * 1024 + L * 16;
+            for (int lp = 0; lp < 4; ++lp) {
+                v4i vv;
+                __builtin_memcpy(&vv, outb[lp], 16);
+                *(v4i*)(base + lp * 1024) = vv;
+            }
         }
     } else {
         // FP64 B fragments (cb16 = 2b, 2b + 1; 8 k-blocks of 4): lane L holds
@@ -597,9 +628,6 @@ hipError_t leaf_operands(const PlainArgs& w, const LeafState& ls, const uint32_t
     // tiles of four 32-row blocks (4 per operand block); FP64 64-row tiles of
     // four 16-row blocks (2 per operand block)
     a.nab = fp64 ? (int32_t)(ceil_div(w.m, 64) * 2) : (int32_t)ceil_div(w.m, 128);
-    uint32_t sc[4] = {1, 0, 0, 0};
-    for (int l = 1; l < 4; ++l) sc[l] = (uint32_t)(((uint64_t)sc[l - 1] * 256u) % w.F.p);
-    a.scale = make_uint4(sc[0], sc[1], sc[2], sc[3]);
     const int64_t ncb = ceil_div(w.m > 0 ? w.m : 1, 256);
     hipLaunchKernelGGL(leaf_operands_kernel, dim3((unsigned)(a.nyb + a.nab + ncb)), dim3(256), 0,
                        s, a);
