@@ -228,25 +228,190 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
     // epilogue: 32x32 accumulator layout: lane L holds column L%32 and rows
     // 8*(r/4) + 4*(L/32) + r%4 for r = 0..15.  All loads are issued before the
     // first store so their latencies overlap.
+    // (addresses are clamped into the matrix so that every load is issued
+    // unconditionally; out-of-range values are discarded afterwards)
     const int64_t col = cb * 32 + (lane & 31);
-    bool fresh[16];
+    const int64_t colc = col < N ? col : N - 1;
+    int rcv[16];
     uint32_t cur[16];
     for (int r = 0; r < 16; ++r) {
         const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int rc = row < w.m ? w.rowcol[row] : -1;
-        fresh[r] = rc >= fresh_lo && rc < fresh_hi;  // a pivot row of this panel
-    }
-    for (int r = 0; r < 16; ++r) {
-        const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        cur[r] = (col < N && row < w.m && !fresh[r])
-                     ? __builtin_nontemporal_load(dst.M + row * dst.ld + col0 + col)
-                     : 0u;
+        const int64_t rowc = row < w.m ? row : w.m - 1;
+        rcv[r] = w.rowcol[rowc];
+        cur[r] = __builtin_nontemporal_load(dst.M + rowc * dst.ld + col0 + colc);
     }
     if (col >= N) return;
     for (int r = 0; r < 16; ++r) {
         const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         if (row >= w.m) continue;
-        dst.M[row * dst.ld + col0 + col] = fold7(acc, r, cur[r], c32, w.F);
+        const bool fresh = rcv[r] >= fresh_lo && rcv[r] < fresh_hi;  // a pivot row of this panel
+        dst.M[row * dst.ld + col0 + col] = fold7(acc, r, fresh ? 0u : cur[r], c32, w.F);
+    }
+}
+
+// Leaf product on int8 MFMA: PR columns [l0, l0 + N) of every row become
+// C + A . Y, and Y itself for the leaf's pivot rows, where A = -(the row's
+// values at the leaf's pivot columns) and Y = P^-1 R, R being the pivot rows as
+// the selection saved them, with each pivot's implicit 1 in the transform block.
+// Block: 4 waves over 128 rows x 32 columns; every block forms its own 32-column
+// slice of Y (a 32 x 32 x t product in FP64 with exact 16-bit splits) and the
+// int8 digits of its rows' multipliers in registers.  The leaf's pivot columns
+// are not written (their unit-vector form is implied by the bookkeeping), so no
+// multiplier is overwritten while other blocks still read it.
+// The launch also builds the next leaf's candidate list (one entry per thread).
+// When the selection already built Y's fragments (out->yready), they are
+// loaded instead.
+__global__ __launch_bounds__(kThreads, 2) void leaf_product_i8_kernel(
+    PlainArgs w, Mat pr, int32_t l0, int32_t wl, int32_t wj, int32_t gcol0, int64_t N,
+    const LeafOut* out, const uint32_t* rsave, int64_t ldr, double c32, const int32_t* cand,
+    int32_t* cand_next, const int32_t* count, int32_t* count_next, const int8_t* yfrag) {
+    __shared__ uint32_t sP[32][33];
+    __shared__ uint32_t sR[32][33];
+    __shared__ uint32_t sY[32][33];
+    __shared__ v4i sB[4 * 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t rb = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t cb = blockIdx.y;
+    const int t = out->t;
+    const uint32_t p = w.F.p;
+    {
+        const int64_t i = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kThreads + tid;
+        const int E = *count;
+        if (i == 0) *count_next = E - t;
+        leaf_compact_entry(out, t, cand, cand_next, E, i);
+    }
+    // All loads below use addresses clamped into their arrays and are issued
+    // unconditionally (values out of range are discarded afterwards), so they
+    // overlap instead of waiting one by one.
+    const bool yready = out->yready != 0;
+    v4i bf[4];
+    if (yready)
+        for (int l = 0; l < 4; ++l) bf[l] = *(const v4i*)(yfrag + (cb * 4 + l) * 1024 + lane * 16);
+    else
+    for (int i = tid; i < 32 * 32; i += kThreads) {
+        const int s = i >> 5, c = i & 31;
+        const int64_t col = cb * 32 + c;
+        const uint32_t pv = out->pinv[s * 32 + c];
+        const uint32_t rv = rsave[s * ldr + (col < N ? col : N - 1)];
+        const int cs = out->col[s];
+        sP[s][c] = (s < t && c < t) ? pv : 0u;
+        sR[s][c] = (s < t && col < N) ? (col == (int64_t)wj + cs ? 1u : rv) : 0u;
+    }
+    // multipliers of this lane's A row (row 32 rb + L%32, k = 16 (L/32) + i)
+    const int64_t arow = rb * 32 + (lane & 31);
+    const int64_t arowc = arow < w.m ? arow : w.m - 1;
+    const int khalf = 16 * (lane >> 5);
+    uint32_t av[16];
+    int sel = -1;
+    {
+        int colv[32];  // the leaf's pivot columns (the array always has 32 entries)
+        bool ident = true;  // pivot columns 0 .. t-1 (dense data): contiguous loads
+        for (int k = 0; k < 32; ++k) {
+            colv[k] = out->col[k] & 31;
+            ident = ident && (k >= t || colv[k] == k);
+        }
+        const int rc = w.rowcol[arowc] - gcol0;
+        if (ident) {
+            const uint4* src = (const uint4*)(pr.M + arowc * pr.ld + l0 + khalf);
+            for (int q4 = 0; q4 < 4; ++q4) {
+                const uint4 v4 = src[q4];
+                av[4 * q4] = v4.x;
+                av[4 * q4 + 1] = v4.y;
+                av[4 * q4 + 2] = v4.z;
+                av[4 * q4 + 3] = v4.w;
+            }
+        } else {
+            for (int i = 0; i < 16; ++i)
+                av[i] = pr.M[arowc * pr.ld + l0 + (khalf ? colv[16 + i] : colv[i])];
+        }
+        for (int s2 = 0; s2 < 32; ++s2)  // the row's own pivot of this leaf, if any
+            if (s2 < t && rc >= 0 && rc < wl && colv[s2] == rc) sel = s2;
+        for (int i = 0; i < 16; ++i)
+            if (arow >= w.m || khalf + i >= t) av[i] = 0u;
+        if (arow >= w.m) sel = -1;
+    }
+    // epilogue rows: rowcol and current values, loaded before any computation
+    const int64_t col = cb * 32 + (lane & 31);
+    const int64_t colc = col < N ? col : N - 1;
+    const bool pivcol = col < wl && w.colpiv[gcol0 + (col < wl ? col : 0)] >= 0;
+    int rcv[16];
+    uint32_t cur[16];
+    for (int r = 0; r < 16; ++r) {
+        const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int64_t rowc = row < w.m ? row : w.m - 1;
+        rcv[r] = w.rowcol[rowc];
+        cur[r] = pr.M[rowc * pr.ld + l0 + colc];
+    }
+    __syncthreads();
+    if (!yready) {  // Y slice: thread -> row s = tid / 8, columns 4 (tid % 8) .. + 3
+        const int s = tid >> 3, c4 = (tid & 7) * 4;
+        double s1[4] = {0.0, 0.0, 0.0, 0.0}, s0[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int k = 0; k < t; ++k) {
+            const uint32_t pv = sP[s][k];
+            const double hi = (double)(pv >> 16), lo = (double)(pv & 0xffffu);
+            for (int e = 0; e < 4; ++e) {
+                const double rv = (double)sR[k][c4 + e];
+                s1[e] = __fma_rn(hi, rv, s1[e]);
+                s0[e] = __fma_rn(lo, rv, s0[e]);
+            }
+        }
+        for (int e = 0; e < 4; ++e) {
+            // s1 < 2^51, s0 < 2^52: exact; reduce s1, recombine below 2^53, reduce
+            double q = floor(s1[e] * w.F.pinv);
+            double h = __fma_rn(-q, w.F.dp, s1[e]);
+            q = floor(h * w.F.pinv);
+            h = __fma_rn(-q, w.F.dp, h);
+            double y = __fma_rn(h, 65536.0, s0[e]);
+            q = floor(y * w.F.pinv);
+            y = __fma_rn(-q, w.F.dp, y);
+            q = floor(y * w.F.pinv);
+            y = __fma_rn(-q, w.F.dp, y);
+            if (y < 0.0) y += w.F.dp;
+            if (y >= w.F.dp) y -= w.F.dp;
+            sY[s][c4 + e] = (uint32_t)y;
+        }
+    }
+    __syncthreads();
+    if (!yready && tid < 64) {  // B fragment: digit plane l', lane L holds column L%32, rows 16 (L/32) + i
+        int8_t outb[4][16];
+        for (int i = 0; i < 16; ++i) {
+            int8_t d[4];
+            digits4(centre(sY[16 * (tid >> 5) + i][tid & 31], p), d);
+            for (int l = 0; l < 4; ++l) outb[l][i] = d[l];
+        }
+        for (int l = 0; l < 4; ++l) {
+            v4i vv;
+            __builtin_memcpy(&vv, outb[l], 16);
+            sB[l * 64 + tid] = vv;
+        }
+    }
+    v4i af[4];
+    {
+        int8_t outa[4][16];
+        for (int i = 0; i < 16; ++i) {
+            const int k = khalf + i;
+            uint32_t a = sel >= 0 ? (k == sel ? 1u : 0u) : (av[i] == 0 ? 0u : p - av[i]);
+            int8_t d[4];
+            digits4(centre(a, p), d);
+            for (int l = 0; l < 4; ++l) outa[l][i] = d[l];
+        }
+        for (int l = 0; l < 4; ++l) __builtin_memcpy(&af[l], outa[l], 16);
+    }
+    __syncthreads();
+    v16i acc[7];
+    for (int g = 0; g < 7; ++g)
+        for (int r = 0; r < 16; ++r) acc[g][r] = 0;
+    if (!yready)
+        for (int l = 0; l < 4; ++l) bf[l] = sB[l * 64 + lane];
+    for (int l = 0; l < 4; ++l)
+        for (int lp = 0; lp < 4; ++lp)
+            acc[l + lp] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[l], bf[lp], acc[l + lp], 0, 0, 0);
+    if (col >= N || pivcol) return;
+    for (int r = 0; r < 16; ++r) {
+        const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (row >= w.m) continue;
+        const bool fresh = rcv[r] >= gcol0 && rcv[r] < gcol0 + wl;  // a pivot row of this leaf
+        pr.M[row * pr.ld + l0 + col] = fold7(acc, r, fresh ? 0u : cur[r], c32, w.F);
     }
 }
 
@@ -307,22 +472,22 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(PlainArgs w, Mat dst
             for (int b = 0; b < 2; ++b)
                 acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
     }
+    // clamped addresses: every load is issued unconditionally
     uint32_t cur[2][2][4];
     bool fresh[2][4];
     for (int a = 0; a < 2; ++a)
         for (int i = 0; i < 4; ++i) {
             const int64_t row = (rb0 + a) * 16 + (lane >> 4) + 4 * i;
-            const int rc = row < w.m ? w.rowcol[row] : -1;
+            const int rc = w.rowcol[row < w.m ? row : w.m - 1];
             fresh[a][i] = rc >= fresh_lo && rc < fresh_hi;
         }
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) {
             const int64_t col = (cb0 + b) * 16 + (lane & 15);
+            const int64_t colc = col < N ? col : N - 1;
             for (int i = 0; i < 4; ++i) {
                 const int64_t row = (rb0 + a) * 16 + (lane >> 4) + 4 * i;
-                cur[a][b][i] = (col < N && row < w.m && !fresh[a][i])
-                                   ? dst.M[row * dst.ld + col0 + col]
-                                   : 0u;
+                cur[a][b][i] = dst.M[(row < w.m ? row : w.m - 1) * dst.ld + col0 + colc];
             }
         }
     for (int a = 0; a < 2; ++a) {
@@ -389,7 +554,7 @@ size_t carve_blocked(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, B
     int8_t* A = c.take<int8_t>(abytes);
     int8_t* B = c.take<int8_t>(bbytes);
     LeafState ls;
-    leaf_carve(c, m, &ls);
+    leaf_carve(c, m, Nl, &ls);
     if (b) {
         plain_carve(ws, m, n, k, b->w);
         b->PR = Mat{PR, ldpr};
@@ -497,16 +662,31 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
             // block up to this leaf's pivots (beyond it every row is still zero)
             const int64_t N = (int64_t)wj + wl;
             lt.before(LINAC_KERNEL_SELECT);
-            e = leaf_select(w, b.leaf, b.PR.M, b.PR.ld, l0, wl, j0 + l0, parity, s);
+            e = leaf_select(w, b.leaf, b.PR.M, b.PR.ld, l0, wl, wj, j0 + l0, parity, N,
+                            fp64 ? nullptr : b.Bfrag, s);
             lt.after();
             if (e != hipSuccess) break;
-            lt.before(LINAC_KERNEL_OPERANDS);
-            e = leaf_operands(w, b.leaf, b.PR.M, b.PR.ld, l0, wl, wj, j0 + l0, N, parity, fp64,
-                              b.Afrag, b.Bfrag, s);
-            lt.after();
-            if (e != hipSuccess) break;
-            e = run_product(b, w, fp64, b.PR, (int64_t)l0, N, fp64 ? kLeaf / 4 : 1, j0 + l0,
-                            j0 + l0 + wl, s, lt, LINAC_KERNEL_LEAF_PRODUCT);
+            if (fp64) {
+                lt.before(LINAC_KERNEL_OPERANDS);
+                e = leaf_operands(w, b.leaf, b.PR.M, b.PR.ld, l0, wl, wj, j0 + l0, N, parity, fp64,
+                                  b.Afrag, b.Bfrag, s);
+                lt.after();
+                if (e != hipSuccess) break;
+                e = run_product(b, w, fp64, b.PR, (int64_t)l0, N, kLeaf / 4, j0 + l0, j0 + l0 + wl,
+                                s, lt, LINAC_KERNEL_LEAF_PRODUCT);
+            } else {
+                const double c32 = (double)((((uint64_t)1) << 32) % w.F.p);
+                lt.before(LINAC_KERNEL_LEAF_PRODUCT);
+                hipLaunchKernelGGL(leaf_product_i8_kernel,
+                                   dim3((unsigned)ceil_div(m, 128), (unsigned)ceil_div(N, 32)),
+                                   dim3(kThreads), 0, s, w, b.PR, l0, wl, wj, j0 + l0, N,
+                                   (const LeafOut*)b.leaf.out, (const uint32_t*)b.leaf.rsave,
+                                   b.leaf.ldr, c32, (const int32_t*)b.leaf.cand[parity],
+                                   b.leaf.cand[parity ^ 1], (const int32_t*)(b.leaf.count + parity),
+                                   b.leaf.count + (parity ^ 1), (const int8_t*)b.Bfrag);
+                lt.after();
+                e = hipGetLastError();
+            }
             ++leaf_index;
         }
         if (e != hipSuccess) break;

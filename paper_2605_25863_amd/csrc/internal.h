@@ -98,7 +98,8 @@ hipError_t plain_finish_rref(const PlainArgs& a, uint32_t* A, int64_t lda, int32
 // the pivot columns (row-major, stride 32).
 struct LeafOut {
     int32_t t;
-    int32_t pad[63];
+    int32_t yready;  // 1: the selection also built Y = P^-1 R as int8 B fragments
+    int32_t pad[62];
     int32_t pos[32];
     int32_t row[32];
     int32_t col[32];
@@ -114,19 +115,48 @@ struct LeafState {
     int32_t* cnt[2];
     int32_t* res;
     LeafOut* out;
+    uint32_t* rsave;  // the pivot rows over the columns the leaf updates, as selected
+    int64_t ldr;
     int32_t nodes;
     int32_t gmax;
 };
 
+// The next leaf's candidate list: entry i of the current one (E entries) moves
+// down by the number of this leaf's pivot positions below it, unless it is one
+// of them (order kept).
+__device__ __forceinline__ void leaf_compact_entry(const LeafOut* out, int32_t t,
+                                                   const int32_t* cand, int32_t* cand_next,
+                                                   int32_t E, int64_t i) {
+    if (i >= E) return;
+    int pos[32];  // all loads first (the array always has 32 entries)
+    for (int k = 0; k < 32; ++k) pos[k] = out->pos[k];
+    const int32_t row = cand[i];
+    int shift = 0;
+    bool gone = false;
+    for (int k = 0; k < 32; ++k) {
+        const bool in = k < t;
+        shift += in && pos[k] < i;
+        gone |= in && pos[k] == i;
+    }
+    if (!gone) cand_next[i - shift] = row;
+}
+
 int32_t leaf_nodes(int64_t m);
-void leaf_carve(Carver& c, int64_t m, LeafState* ls);
+void leaf_carve(Carver& c, int64_t m, int64_t ldr, LeafState* ls);
 hipError_t leaf_init(const LeafState& ls, int32_t m, hipStream_t s);
+// The selection of a leaf over PR columns [l0, l0 + wl).  ncopy = the number
+// of PR columns the leaf updates (from l0), wj = the panel width.  With yfrag
+// non-NULL it also builds Y = P^-1 R over those columns as int8 B fragments
+// (one k-block, 4 digit planes per 32 columns) when the first chunk of
+// candidates already decides the leaf, setting out->yready; otherwise it saves
+// the pivot rows in ls.rsave (row s = pivot s) for the product to form Y.
 hipError_t leaf_select(const PlainArgs& w, const LeafState& ls, const uint32_t* PR, int64_t ldpr,
-                       int32_t l0, int32_t wl, int32_t gcol0, int32_t parity, hipStream_t s);
-// Operands of the leaf product over PR columns [l0, l0 + N): the B operand
-// Y = P^-1 R and the A operand (multipliers), in the layouts of the blocked
-// path's product kernels (int8: 32 x 32 blocks with one k-block of 32; FP64:
-// 16 x 16 blocks with 8 k-blocks of 4); also compacts the candidate list.
+                       int32_t l0, int32_t wl, int32_t wj, int32_t gcol0, int32_t parity,
+                       int64_t ncopy, int8_t* yfrag, hipStream_t s);
+// Operands of the FP64 leaf product over PR columns [l0, l0 + N): the B operand
+// Y = P^-1 R and the A operand (multipliers) in the layout of the FP64 product
+// kernel (16 x 16 blocks with 8 k-blocks of 4); also compacts the candidate
+// list.
 hipError_t leaf_operands(const PlainArgs& w, const LeafState& ls, const uint32_t* PR, int64_t ldpr,
                          int32_t l0, int32_t wl, int32_t wj, int32_t gcol0, int64_t N,
                          int32_t parity, bool fp64, void* Afrag, void* Bfrag, hipStream_t s);

@@ -39,8 +39,10 @@ namespace {
 
 constexpr int kSelWaves = 16;
 constexpr int kSelThreads = 64 * kSelWaves;
-constexpr int kChunk = 64;     // candidate rows per tree node
+constexpr int kChunk = 32;     // candidate rows per first-level tree node
 constexpr int kNodeInts = 64;  // per node: basis size, then its list positions
+
+typedef int v4i __attribute__((ext_vector_type(4)));
 
 struct Lazy {
     double p, pinv;
@@ -109,15 +111,22 @@ struct SelArgs {
     int32_t* cnt_next;
     int32_t* res;
     LeafOut* out;
+    uint32_t* rsave;
+    int64_t ldr;
+    int64_t ncopy;
+    int32_t wj;      // panel width (the transform block starts at PR column wj)
+    int8_t* yfrag;   // int8 B fragments of Y, or NULL
 };
 
 // Shared memory of the selection kernel.
 struct Sel {
     double f[2][64];              // the current pivot column (double-buffered by step)
-    unsigned long long mask[2];   // its eligible non-zero rows
+    double d[2];                  // its pivot value
+    int32_t q[2];                 // its pivot row within the node, -1 for a free column
     double cp[32];                // product of the pivot values before pivot s
     int32_t pos[64];              // list positions of this node's rows (lane order)
     int32_t basis[32];            // list positions of the node's basis rows (pivot order)
+    int32_t rows[32];             // their row ids (final node)
     int32_t sidx[64];             // lane -> pivot index, -1
     int32_t pl[32];               // pivot index -> lane
     int32_t pc[32];               // pivot index -> leaf column
@@ -136,62 +145,115 @@ __device__ int node_id(int level, int k, int gmax) {
     return base + k;
 }
 
-// Gauss-Jordan over the leaf columns of the node's rows (lane = row).  Wave v
-// holds leaf columns v and v + 16 (v[]) and transform columns v and v + 16 (T[]).
-__device__ __forceinline__ void node_gj(const SelArgs& a, Sel& S, double v[2], double T[2], const Lazy& L) {
+// Gauss-Jordan over the leaf columns of the node's rows.  R = 64: lane = row,
+// wave v holds leaf columns v and v + 16 (v[0], v[1]) and transform columns v
+// and v + 16 (T[0], T[1]).  R = 32: lane = 32 h + row, wave v holds leaf column
+// v + 16 h and transform column v + 16 h in v[0] and T[0] (half the work per
+// step).  Per step the owner wave of column j finds the first eligible row with
+// a non-zero entry and posts it with the column and the pivot value to LDS.
+template <int R>
+__device__ __forceinline__ void node_gj(const SelArgs& a, Sel& S, double v[2], double T[2],
+                                        const Lazy& L) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int R = S.nrows;
-    const int32_t row = lane < R ? a.cand[S.pos[lane]] : -1;
-    for (int r = 0; r < 2; ++r) {
-        const int c = wave + 16 * r;
-        v[r] = (row >= 0 && c < a.wl) ? (double)a.PR[(int64_t)row * a.ldpr + a.l0 + c] : 0.0;
-        T[r] = 0.0;
+    const int h = R == 32 ? lane >> 5 : 0;
+    const int r = R == 32 ? lane & 31 : lane;  // this lane's row within the node
+    const int nrows = S.nrows;
+    const int32_t row = r < nrows ? a.cand[S.pos[r]] : -1;
+#pragma unroll
+    for (int k = 0; k < (R == 64 ? 2 : 1); ++k) {
+        const int c = R == 64 ? wave + 16 * k : wave + 16 * h;
+        v[k] = (row >= 0 && c < a.wl) ? (double)a.PR[(int64_t)row * a.ldpr + a.l0 + c] : 0.0;
+        T[k] = 0.0;
     }
     if (threadIdx.x < 64) S.sidx[threadIdx.x] = -1;
-    const unsigned long long valid = R >= 64 ? ~0ull : ((1ull << R) - 1ull);
+    const unsigned long long valid = nrows >= 64 ? ~0ull : ((1ull << nrows) - 1ull);
     unsigned long long chosen = 0;
     int t = 0;
     double cprod = 1.0;  // common scale of the non-pivot rows' own coefficient
-    __syncthreads();
-    for (int j = 0; j < a.wl; ++j) {
-        const int buf = j & 1;
-        if (wave == (j & 15)) {
-            const double x = j < 16 ? v[0] : v[1];
-            const unsigned long long nz = __ballot(lz_canon(x, L) != 0.0);
-            S.f[buf][lane] = x;
-            if (lane == 0) S.mask[buf] = nz & valid & ~chosen;
-        }
-        __syncthreads();
-        const unsigned long long m = S.mask[buf];
+    // Owner wave of column j: post the first eligible row with a non-zero entry
+    // (-1: free column), its pivot value and the column itself.  A lazy value
+    // x in (-3p, 3p) is zero mod p iff |x| is 0, p or 2p.
+    auto detect = [&](int j) {
+        const int hj = j >> 4;
+        const double x = (R == 64 && hj) ? v[1] : v[0];
+        const double ax = fabs(x);
+        const unsigned long long nz = __ballot(!(ax == 0.0 || ax == L.p || ax == 2.0 * L.p));
+        const unsigned long long m =
+            (R == 32 ? (nz >> (32 * hj)) & 0xffffffffull : nz) & valid & ~chosen;
         const int mlo = uniform((int)(uint32_t)m), mhi = uniform((int)(uint32_t)(m >> 32));
-        if ((mlo | mhi) == 0) continue;  // free column
-        const int q = mlo != 0 ? __builtin_ctz((uint32_t)mlo) : 32 + __builtin_ctz((uint32_t)mhi);
-        const double fi = S.f[buf][lane];
-        const double d = S.f[buf][q];
+        const int q = mlo != 0 ? __builtin_ctz((uint32_t)mlo)
+                               : (mhi != 0 ? 32 + __builtin_ctz((uint32_t)mhi) : -1);
+        const int buf = j & 1;
+        if (R == 64 || h == hj) S.f[buf][r] = x;
+        const double d = q >= 0 ? readlane_d(x, R == 32 ? 32 * hj + q : q) : 0.0;
+        if (lane == 0) {
+            S.q[buf] = q;
+            S.d[buf] = d;
+        }
+    };
+    __syncthreads();
+    if (wave == 0 && a.wl > 0) detect(0);
+    for (int j = 0; j < a.wl; ++j) {
+        __syncthreads();  // step j posted; every wave is done with step j - 1's post
+        const int buf = j & 1;
+        const int qv = S.q[buf];
+        const double fi = S.f[buf][r];
+        const double d = S.d[buf];
+        const int q = uniform(qv);
         const int s = t;
-        if (threadIdx.x == 0) {
-            S.pl[s] = q;
-            S.pc[s] = j;
-            S.sidx[q] = s;
-            S.cp[s] = cprod;
-        }
+        if (q >= 0) {
+            if (threadIdx.x == 0) {
+                S.pl[s] = q;
+                S.pc[s] = j;
+                S.sidx[q] = s;
+                S.cp[s] = cprod;
+            }
+            // leaf columns first: the next column's owner posts right after
+            if (R == 64) {
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int c = wave + 16 * r;
-            if (c > j && c < a.wl) {
-                const double u = readlane_d(v[r], q);
-                if (lane != q) v[r] = lz_ff(d, v[r], fi, u, L);
+                for (int k = 0; k < 2; ++k) {
+                    const int c = wave + 16 * k;
+                    if (c > j && c < a.wl) {
+                        const double u = readlane_d(v[k], q);
+                        if (r != q) v[k] = lz_ff(d, v[k], fi, u, L);
+                    }
+                }
+            } else {
+                const int c = wave + 16 * h;
+                if (wave + 16 > j) {  // some column of this wave still changes
+                    const double u0 = readlane_d(v[0], q), u1 = readlane_d(v[0], 32 + q);
+                    if (c > j && c < a.wl && r != q) v[0] = lz_ff(d, v[0], fi, h ? u1 : u0, L);
+                }
             }
-            if (c < s) {
-                const double u = readlane_d(T[r], q);
-                if (lane != q) T[r] = lz_ff(d, T[r], fi, u, L);
-            } else if (c == s) {
-                T[r] = lane == q ? cprod : -lz_mul(fi, cprod, L);
-            }
+            chosen |= 1ull << q;
         }
-        cprod = lz_mul(cprod, d, L);
-        chosen |= 1ull << q;
-        t = s + 1;
+        if (j + 1 < a.wl && wave == ((j + 1) & 15)) detect(j + 1);
+        if (q >= 0) {
+            if (R == 64) {
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const int c = wave + 16 * k;
+                    if (c < s) {
+                        const double u = readlane_d(T[k], q);
+                        if (r != q) T[k] = lz_ff(d, T[k], fi, u, L);
+                    } else if (c == s) {
+                        T[k] = r == q ? cprod : -lz_mul(fi, cprod, L);
+                    }
+                }
+            } else {
+                const int c = wave + 16 * h;
+                if (wave <= s) {
+                    const double u0 = readlane_d(T[0], q), u1 = readlane_d(T[0], 32 + q);
+                    if (c < s) {
+                        if (r != q) T[0] = lz_ff(d, T[0], fi, h ? u1 : u0, L);
+                    } else if (c == s) {
+                        T[0] = r == q ? cprod : -lz_mul(fi, cprod, L);
+                    }
+                }
+            }
+            cprod = lz_mul(cprod, d, L);
+            t = s + 1;
+        }
     }
     if (threadIdx.x == 0) {
         S.t = t;
@@ -202,32 +264,50 @@ __device__ __forceinline__ void node_gj(const SelArgs& a, Sel& S, double v[2], d
     __syncthreads();
 }
 
-// Final node: P^-1, the leaf result and the pivot bookkeeping.
-__device__ __forceinline__ void publish(const SelArgs& a, Sel& S, const double T[2], const Lazy& L) {
+// Final node: P^-1, the leaf result, the pivot bookkeeping, and a copy of the
+// pivot rows over the columns the leaf updates (the product overwrites them).
+template <int R>
+__device__ __forceinline__ void publish(const SelArgs& a, Sel& S, const double T[2], bool save_rows,
+                                        const Lazy& L) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int h = R == 32 ? lane >> 5 : 0;
+    const int r = R == 32 ? lane & 31 : lane;
     const int t = S.t;
+    if (threadIdx.x < t) S.rows[threadIdx.x] = a.cand[S.basis[threadIdx.x]];
+    __syncthreads();
     if (threadIdx.x == 0) {
         __hip_atomic_store(a.cnt_cur + (a.ncnt - 1), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         S.bcast = a.w.state[0];
         if (t > 0) S.total = lz_inverse(lz_canon(S.total, L), a.w.F.p, L);
+    } else if (threadIdx.x >= 64 && t > 0 && save_rows) {  // meanwhile the other waves save the rows
+        for (int64_t c = threadIdx.x - 64; c < a.ncopy; c += kSelThreads - 64) {
+            // every load issued before any store; pivots k >= t reuse pivot 0's
+            // row (S.rows[0] is set because t > 0)
+            uint32_t x[32];
+#pragma unroll
+            for (int k = 0; k < 32; ++k)
+                x[k] = a.PR[(int64_t)S.rows[k < t ? k : 0] * a.ldpr + a.l0 + c];
+#pragma unroll
+            for (int k = 0; k < 32; ++k)
+                if (k < t) a.rsave[k * a.ldr + c] = x[k];
+        }
     }
     __syncthreads();
-    const int s = lane < S.nrows ? S.sidx[lane] : -1;
+    const int s = r < S.nrows ? S.sidx[r] : -1;
     if (s >= 0) {
         const double dinv = lz_mul(S.cp[s], S.total, L);
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int c = wave + 16 * r;
-            if (c < t) a.out->pinv[s * 32 + c] = (uint32_t)lz_canon(lz_mul(dinv, T[r], L), L);
+        for (int k = 0; k < (R == 64 ? 2 : 1); ++k) {
+            const int c = R == 64 ? wave + 16 * k : wave + 16 * h;
+            if (c < t) a.out->pinv[s * 32 + c] = (uint32_t)lz_canon(lz_mul(dinv, T[k], L), L);
         }
     }
     const int r0 = S.bcast;
     if (threadIdx.x < t) {
         const int i = threadIdx.x;
-        const int pos = S.basis[i];
-        const int row = a.cand[pos];
+        const int row = S.rows[i];
         const int gcol = a.gcol0 + S.pc[i];
-        a.out->pos[i] = pos;
+        a.out->pos[i] = S.basis[i];
         a.out->row[i] = row;
         a.out->col[i] = S.pc[i];
         a.w.pivrow[r0 + i] = row;
@@ -239,46 +319,118 @@ __device__ __forceinline__ void publish(const SelArgs& a, Sel& S, const double T
     }
     if (threadIdx.x == 0) {
         a.out->t = t;
+        a.out->yready = 0;
         a.w.state[0] = r0 + t;
+    }
+}
+
+// One 32-column block of Y = P^-1 R (R = the pivot rows over the leaf's update
+// columns, with each new pivot's implicit 1 in the transform block) as int8 B
+// fragments: thread (s, c) forms Y[s][c] with exact 16-bit-split FP64 sums and
+// writes its four digits into the fragment's byte layout (digit plane l, lane
+// c + 32 (s / 16), byte s % 16).
+__device__ void build_y_block(const SelArgs& a, int g, const Lazy& L) {
+    __shared__ uint32_t sP[32][33];
+    __shared__ uint32_t sR[32][33];
+    __shared__ __attribute__((aligned(16))) int8_t sB[4][64][16];
+    const int tid = threadIdx.x;
+    const int s = tid >> 5, c = tid & 31;
+    const int t = a.out->t;
+    const int64_t col = (int64_t)g * 32 + c;
+    {
+        const int k = s;  // this thread stages R[k][c] and Pinv[k][c]
+        const int krow = a.out->row[k < t ? k : 0];
+        const int kcol = a.out->col[k];
+        const int64_t colc = col < a.ncopy ? col : a.ncopy - 1;
+        const uint32_t rv = a.PR[(int64_t)(t > 0 ? krow : 0) * a.ldpr + a.l0 + colc];
+        const uint32_t pv = a.out->pinv[k * 32 + c];
+        sR[k][c] = (k < t && col < a.ncopy) ? (col == (int64_t)a.wj + kcol ? 1u : rv) : 0u;
+        sP[k][c] = (k < t && c < t) ? pv : 0u;
+    }
+    __syncthreads();
+    double s1 = 0.0, s0 = 0.0;
+    for (int k = 0; k < t; ++k) {
+        const uint32_t pv = sP[s][k];
+        const double r = (double)sR[k][c];
+        s1 = __fma_rn((double)(pv >> 16), r, s1);
+        s0 = __fma_rn((double)(pv & 0xffffu), r, s0);
+    }
+    // s1 < 2^51, s0 < 2^52: exact; (s1 mod p) 2^16 + s0 < 2^53
+    const double y = lz_canon_wide(__fma_rn(lz_canon_wide(s1, L), 65536.0, s0), L);
+    const uint32_t p = a.w.F.p;
+    const uint32_t yv = (uint32_t)y;
+    int32_t x = yv > (p - 1) / 2 ? (int32_t)yv - (int32_t)p : (int32_t)yv;
+    for (int l = 0; l < 4; ++l) {
+        const int8_t d = (int8_t)(x & 0xff);
+        sB[l][c + 32 * (s >> 4)][s & 15] = d;
+        x = (x - d) >> 8;
+    }
+    __syncthreads();
+    if (tid < 256) {
+        const int l = tid >> 6, L2 = tid & 63;
+        *(v4i*)(a.yfrag + ((int64_t)g * 4 + l) * 1024 + L2 * 16) = *(const v4i*)&sB[l][L2][0];
     }
 }
 
 // The last arrival counter of each set is the "published" flag: once the final
 // node is known, workgroups still merging stop at their next tree level.
-__global__ __launch_bounds__(kSelThreads) void leaf_select_kernel(SelArgs a) {
+//
+// Two launches per leaf: `first` runs the first chunk alone (one workgroup, no
+// other work on the device) and publishes when that chunk already has full
+// rank, as with dense data; the full tree launch then finds the result
+// published and ends at once, or selects over all candidates.
+__global__ __launch_bounds__(kSelThreads) void leaf_select_kernel(SelArgs a, int32_t first) {
     __shared__ Sel S;
     const Lazy L{(double)a.w.F.p, a.w.F.pinv};
     int32_t* published = a.cnt_cur + (a.ncnt - 1);
-    for (int i = blockIdx.x * kSelThreads + threadIdx.x; i < a.ncnt; i += gridDim.x * kSelThreads)
-        a.cnt_next[i] = 0;
+    if (!first)
+        for (int i = blockIdx.x * kSelThreads + threadIdx.x; i < a.ncnt;
+             i += gridDim.x * kSelThreads)
+            a.cnt_next[i] = 0;
     const int E = *a.count;
     const int G = (E + kChunk - 1) / kChunk;
     const int g = blockIdx.x;
+    if (!first) {
+        if (threadIdx.x == 0)
+            S.bcast = __hip_atomic_load(published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        if (S.bcast != 0) {  // decided by the first launch: build Y instead
+            if (a.yfrag && (int64_t)g * 32 < a.ncopy) build_y_block(a, g, L);
+            if (a.yfrag && g == 0 && threadIdx.x == 0) a.out->yready = 1;
+            return;
+        }
+    }
     if (E == 0) {
-        if (g == 0 && threadIdx.x == 0) a.out->t = 0;
+        if (first && threadIdx.x == 0) {
+            __hip_atomic_store(published, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            a.out->t = 0;
+            a.out->yready = 0;
+        }
         return;
     }
     if (g >= G) return;
-    if (threadIdx.x == 0)
-        S.bcast = g > 0 ? __hip_atomic_load(published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
     if (threadIdx.x < 64) S.pos[threadIdx.x] = g * kChunk + threadIdx.x;
     if (threadIdx.x == 0) S.nrows = min(kChunk, E - g * kChunk);
     __syncthreads();
-    if (S.bcast != 0) return;
     int level = 0, k = g, nodes = G;
     double v[2], T[2];
-    node_gj(a, S, v, T, L);
-    bool regs = true;  // v, T hold the Gauss-Jordan of the node's basis rows
+    node_gj<32>(a, S, v, T, L);
+    if (first && !(S.t == a.wl || nodes == 1)) return;  // the tree launch decides
+    int regs = 32;  // v, T hold the Gauss-Jordan of the node's basis rows in this layout (0: none)
     while (true) {
         const int t = S.t;
         if ((k == 0 && t == a.wl) || nodes == 1) {
-            if (!regs) {  // a basis passed up without elimination: reduce it now
+            if (regs == 0) {  // a basis passed up without elimination: reduce it now
                 if (threadIdx.x < t) S.pos[threadIdx.x] = S.basis[threadIdx.x];
                 if (threadIdx.x == 0) S.nrows = t;
                 __syncthreads();
-                node_gj(a, S, v, T, L);
+                node_gj<32>(a, S, v, T, L);
+                regs = 32;
             }
-            publish(a, S, T, L);
+            // the tree launch leaves Y to the product, which needs the rows as selected
+            const bool save_rows = !first && a.yfrag != nullptr;
+            if (regs == 32) publish<32>(a, S, T, save_rows, L);
+            else publish<64>(a, S, T, save_rows, L);
             return;
         }
         const int up = (nodes + 1) >> 1;
@@ -328,8 +480,12 @@ __global__ __launch_bounds__(kSelThreads) void leaf_select_kernel(SelArgs a) {
             if (threadIdx.x == 0) S.nrows = tl + tr;
         }
         __syncthreads();
-        if (!lazy) node_gj(a, S, v, T, L);
-        regs = !lazy;
+        if (lazy) {
+            regs = 0;
+        } else {
+            node_gj<64>(a, S, v, T, L);
+            regs = 64;
+        }
         ++level;
         k >>= 1;
         nodes = up;
@@ -357,19 +513,17 @@ __device__ __forceinline__ void digits4(int32_t x, int8_t d[4]) {
     }
 }
 
-typedef int v4i __attribute__((ext_vector_type(4)));
-
 struct OpArgs {
     PlainArgs w;
     const uint32_t* PR;
     int64_t ldpr;
     int32_t l0, wl, wj, gcol0;
     int64_t N;  // PR columns [l0, l0 + N) are updated
+    const LeafOut* out;
     const int32_t* cand;
     int32_t* cand_next;
     const int32_t* count;
     int32_t* count_next;
-    const LeafOut* out;
     void* Afrag;
     void* Bfrag;
     int32_t nyb, nab;  // blocks of the Y and A parts (the rest compact the list)
@@ -514,31 +668,18 @@ __device__ void operands_a(const OpArgs& a, int b) {
     }
 }
 
-// Drop the leaf's pivot rows from the candidate list (order kept).
-__device__ void operands_compact(const OpArgs& a, int b) {
-    __shared__ int32_t pos[32];
-    const int tid = threadIdx.x;
-    const int t = a.out->t;
-    if (tid < 32) pos[tid] = tid < t ? a.out->pos[tid] : INT32_MAX;
-    __syncthreads();
-    const int E = *a.count;
-    const int64_t i = (int64_t)b * 256 + tid;
-    if (b == 0 && tid == 0) *a.count_next = E - t;
-    if (i >= E) return;
-    int shift = 0;
-    bool gone = false;
-    for (int s = 0; s < t; ++s) {
-        shift += pos[s] < i;
-        gone |= pos[s] == i;
-    }
-    if (!gone) a.cand_next[i - shift] = a.cand[i];
-}
-
 __global__ __launch_bounds__(256) void leaf_operands_kernel(OpArgs a) {
     const int b = blockIdx.x;
-    if (b < a.nyb) operands_y(a, b);
-    else if (b < a.nyb + a.nab) operands_a(a, b - a.nyb);
-    else operands_compact(a, b - a.nyb - a.nab);
+    if (b < a.nyb) {
+        operands_y(a, b);
+    } else if (b < a.nyb + a.nab) {
+        operands_a(a, b - a.nyb);
+    } else {
+        const int64_t i = (int64_t)(b - a.nyb - a.nab) * 256 + threadIdx.x;
+        const int t = a.out->t, E = *a.count;
+        if (i == 0) *a.count_next = E - t;
+        leaf_compact_entry(a.out, t, a.cand, a.cand_next, E, i);
+    }
 }
 
 }  // namespace
@@ -553,7 +694,7 @@ int32_t leaf_nodes(int64_t m) {
     return (int32_t)(tot + 1);
 }
 
-void leaf_carve(Carver& c, int64_t m, LeafState* ls) {
+void leaf_carve(Carver& c, int64_t m, int64_t ldr, LeafState* ls) {
     const int32_t nodes = leaf_nodes(m);
     int32_t* cand0 = c.take<int32_t>(m > 0 ? m : 1);
     int32_t* cand1 = c.take<int32_t>(m > 0 ? m : 1);
@@ -561,7 +702,10 @@ void leaf_carve(Carver& c, int64_t m, LeafState* ls) {
     int32_t* cnt = c.take<int32_t>(2 * (int64_t)nodes);
     int32_t* res = c.take<int32_t>((int64_t)nodes * kNodeInts);
     LeafOut* out = c.take<LeafOut>(1);
+    uint32_t* rsave = c.take<uint32_t>(32 * ldr);
     if (ls) {
+        ls->rsave = rsave;
+        ls->ldr = ldr;
         ls->cand[0] = cand0;
         ls->cand[1] = cand1;
         ls->count = count;
@@ -583,7 +727,8 @@ hipError_t leaf_init(const LeafState& ls, int32_t m, hipStream_t s) {
 }
 
 hipError_t leaf_select(const PlainArgs& w, const LeafState& ls, const uint32_t* PR, int64_t ldpr,
-                       int32_t l0, int32_t wl, int32_t gcol0, int32_t parity, hipStream_t s) {
+                       int32_t l0, int32_t wl, int32_t wj, int32_t gcol0, int32_t parity,
+                       int64_t ncopy, int8_t* yfrag, hipStream_t s) {
     SelArgs a;
     a.w = w;
     a.PR = PR;
@@ -599,7 +744,15 @@ hipError_t leaf_select(const PlainArgs& w, const LeafState& ls, const uint32_t* 
     a.cnt_next = ls.cnt[parity ^ 1];
     a.res = ls.res;
     a.out = ls.out;
-    hipLaunchKernelGGL(leaf_select_kernel, dim3((unsigned)ls.gmax), dim3(kSelThreads), 0, s, a);
+    a.rsave = ls.rsave;
+    a.ldr = ls.ldr;
+    a.ncopy = ncopy;
+    a.wj = wj;
+    a.yfrag = yfrag;
+    const int64_t nyb = ceil_div(ncopy, 32);
+    const unsigned grid = (unsigned)(ls.gmax > nyb ? ls.gmax : nyb);
+    hipLaunchKernelGGL(leaf_select_kernel, dim3(1), dim3(kSelThreads), 0, s, a, 1);
+    hipLaunchKernelGGL(leaf_select_kernel, dim3(grid), dim3(kSelThreads), 0, s, a, 0);
     return hipGetLastError();
 }
 
@@ -615,11 +768,11 @@ hipError_t leaf_operands(const PlainArgs& w, const LeafState& ls, const uint32_t
     a.wj = wj;
     a.gcol0 = gcol0;
     a.N = N;
+    a.out = ls.out;
     a.cand = ls.cand[parity];
     a.cand_next = ls.cand[parity ^ 1];
     a.count = ls.count + parity;
     a.count_next = ls.count + (parity ^ 1);
-    a.out = ls.out;
     a.Afrag = Afrag;
     a.Bfrag = Bfrag;
     a.fp64 = fp64 ? 1 : 0;
