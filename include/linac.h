@@ -169,7 +169,10 @@ linac_status linac_solve_batched(const linac_system* sys, int32_t count, void* w
  *   "panel":          array of {"n_max": N, "panel": w}: panel width w for
  *                     min(m, n) <= N (first match, ascending N; w a multiple of
  *                     32 in [32, 512]); larger sizes use the last entry;
- *   "batched_per_cu": resident workgroups per compute unit of the batched launch.
+ *   "batched_per_cu": resident workgroups per compute unit of the batched launch;
+ *   "lookahead":      1 (default) or 0: whether the blocked int8 path overlaps the
+ *                     next panel's pivot selection with the trailing update (on a
+ *                     second stream that the call joins back to s).
  * Unknown keys are ignored.  Returns LINAC_E_INVALID_ARG (and keeps the current
  * table) for malformed text or out-of-range values.  Host only. */
 linac_status linac_load_tuning(const char* json);

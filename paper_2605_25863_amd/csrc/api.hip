@@ -18,6 +18,25 @@
 
 using namespace linac;
 
+hipError_t linac::side_stream(hipStream_t* out) {
+    static std::mutex mu;
+    static std::vector<hipStream_t> streams;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
+    if (!streams[dev]) {
+        e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            streams[dev] = nullptr;
+            return e;
+        }
+    }
+    *out = streams[dev];
+    return hipSuccess;
+}
+
 namespace {
 
 thread_local int g_last_hip = 0;
@@ -86,6 +105,7 @@ struct PanelRule {
 struct Tuning {
     int64_t blocked_min = 1024;  // AUTO takes the blocked path from min(m, n) >= this
     int32_t batched_per_cu = 4;
+    int32_t lookahead = 1;       // blocked int8: overlap the next panel with the trailing update
     std::vector<PanelRule> panels{{1 << 30, 256}};
 };
 std::mutex g_tune_mu;
@@ -177,6 +197,7 @@ linac_status parse_tuning(const char* json, Tuning* t) {
         const double v = kv.second;
         if (k == "blocked_min") nt.blocked_min = (int64_t)v;
         else if (k == "batched_per_cu") nt.batched_per_cu = (int32_t)v;
+        else if (k == "lookahead") nt.lookahead = (int32_t)v;
         else if (k.rfind("panel.", 0) == 0) {
             size_t dot = k.find('.', 6);
             if (dot == std::string::npos) return LINAC_E_INVALID_ARG;
@@ -189,7 +210,8 @@ linac_status parse_tuning(const char* json, Tuning* t) {
     }
     for (const PanelRule& pr : rules)
         if (pr.n_max <= 0 || pr.panel < 32 || pr.panel > 512 || pr.panel % 32) return LINAC_E_INVALID_ARG;
-    if (nt.blocked_min < 1 || nt.batched_per_cu < 1 || nt.batched_per_cu > 16)
+    if (nt.blocked_min < 1 || nt.batched_per_cu < 1 || nt.batched_per_cu > 16 ||
+        (nt.lookahead != 0 && nt.lookahead != 1))
         return LINAC_E_INVALID_ARG;
     std::sort(rules.begin(), rules.end(),
               [](const PanelRule& a, const PanelRule& b) { return a.n_max < b.n_max; });
@@ -241,7 +263,7 @@ hipError_t run_path(int path, void* ws, int64_t m, int64_t n, int64_t k, PlainAr
                     const linac_opts* opts, hipStream_t s) {
     if (path == LINAC_PATH_PLAIN) return plain_eliminate(a, opts, s);
     return blocked_eliminate(ws, m, n, k, panel_width(opts, m, n), path == LINAC_PATH_BLOCKED_FP64,
-                             a, opts, s);
+                             tuning().lookahead != 0, a, opts, s);
 }
 
 bool size_ok(int64_t m, int64_t n, int64_t k) {

@@ -252,15 +252,18 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
 // Leaf product on int8 MFMA: PR columns [l0, l0 + N) of every row become
 // C + A . Y, and Y itself for the leaf's pivot rows, where A = -(the row's
 // values at the leaf's pivot columns) and Y = P^-1 R, R being the pivot rows as
-// the selection saved them, with each pivot's implicit 1 in the transform block.
-// Block: 4 waves over 128 rows x 32 columns; every block forms its own 32-column
-// slice of Y (a 32 x 32 x t product in FP64 with exact 16-bit splits) and the
-// int8 digits of its rows' multipliers in registers.  The leaf's pivot columns
-// are not written (their unit-vector form is implied by the bookkeeping), so no
-// multiplier is overwritten while other blocks still read it.
-// The launch also builds the next leaf's candidate list (one entry per thread).
-// When the selection already built Y's fragments (out->yready), they are
-// loaded instead.
+// the selection saw them, with each pivot's implicit 1 in the transform block.
+// Block: 4 waves over 128 rows and kLeafBlocks consecutive 32-column blocks,
+// taken one after the other with the same multipliers (int8 digits built in
+// registers).  Y's fragments come from the selection when it built them
+// (out->yready); otherwise every block forms its own slices of Y (32 x 32 x t
+// products in FP64 with exact 16-bit splits) from the rows the selection saved.
+// The leaf's pivot columns are not written (their unit-vector form is implied
+// by the bookkeeping), so no multiplier is overwritten while other blocks still
+// read it.  The launch also builds the next leaf's candidate list (one entry per
+// thread).
+constexpr int kLeafBlocks = 2;
+
 __global__ __launch_bounds__(kThreads, 2) void leaf_product_i8_kernel(
     PlainArgs w, Mat pr, int32_t l0, int32_t wl, int32_t wj, int32_t gcol0, int64_t N,
     const LeafOut* out, const uint32_t* rsave, int64_t ldr, double c32, const int32_t* cand,
@@ -271,7 +274,8 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_product_i8_kernel(
     __shared__ v4i sB[4 * 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t rb = (int64_t)blockIdx.x * 4 + wave;
-    const int64_t cb = blockIdx.y;
+    const int64_t cb0 = (int64_t)blockIdx.y * kLeafBlocks;
+    const int64_t NB = ceil_div(N, 32);
     const int t = out->t;
     const uint32_t p = w.F.p;
     {
@@ -284,19 +288,6 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_product_i8_kernel(
     // unconditionally (values out of range are discarded afterwards), so they
     // overlap instead of waiting one by one.
     const bool yready = out->yready != 0;
-    v4i bf[4];
-    if (yready)
-        for (int l = 0; l < 4; ++l) bf[l] = *(const v4i*)(yfrag + (cb * 4 + l) * 1024 + lane * 16);
-    else
-    for (int i = tid; i < 32 * 32; i += kThreads) {
-        const int s = i >> 5, c = i & 31;
-        const int64_t col = cb * 32 + c;
-        const uint32_t pv = out->pinv[s * 32 + c];
-        const uint32_t rv = rsave[s * ldr + (col < N ? col : N - 1)];
-        const int cs = out->col[s];
-        sP[s][c] = (s < t && c < t) ? pv : 0u;
-        sR[s][c] = (s < t && col < N) ? (col == (int64_t)wj + cs ? 1u : rv) : 0u;
-    }
     // multipliers of this lane's A row (row 32 rb + L%32, k = 16 (L/32) + i)
     const int64_t arow = rb * 32 + (lane & 31);
     const int64_t arowc = arow < w.m ? arow : w.m - 1;
@@ -306,6 +297,7 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_product_i8_kernel(
     {
         int colv[32];  // the leaf's pivot columns (the array always has 32 entries)
         bool ident = true;  // pivot columns 0 .. t-1 (dense data): contiguous loads
+#pragma unroll
         for (int k = 0; k < 32; ++k) {
             colv[k] = out->col[k] & 31;
             ident = ident && (k >= t || colv[k] == k);
@@ -320,10 +312,11 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_product_i8_kernel(
                 av[4 * q4 + 2] = v4.z;
                 av[4 * q4 + 3] = v4.w;
             }
-        } else {
-            for (int i = 0; i < 16; ++i)
-                av[i] = pr.M[arowc * pr.ld + l0 + (khalf ? colv[16 + i] : colv[i])];
+        } else {  // (rare) gather by the pivot columns, read per lane
+#pragma unroll
+            for (int i = 0; i < 16; ++i) av[i] = pr.M[arowc * pr.ld + l0 + (out->col[khalf + i] & 31)];
         }
+#pragma unroll
         for (int s2 = 0; s2 < 32; ++s2)  // the row's own pivot of this leaf, if any
             if (s2 < t && rc >= 0 && rc < wl && colv[s2] == rc) sel = s2;
         for (int i = 0; i < 16; ++i)
@@ -331,58 +324,19 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_product_i8_kernel(
         if (arow >= w.m) sel = -1;
     }
     // epilogue rows: rowcol and current values, loaded before any computation
-    const int64_t col = cb * 32 + (lane & 31);
-    const int64_t colc = col < N ? col : N - 1;
-    const bool pivcol = col < wl && w.colpiv[gcol0 + (col < wl ? col : 0)] >= 0;
     int rcv[16];
-    uint32_t cur[16];
+    uint32_t cur[kLeafBlocks][16];
     for (int r = 0; r < 16; ++r) {
         const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int64_t rowc = row < w.m ? row : w.m - 1;
-        rcv[r] = w.rowcol[rowc];
-        cur[r] = pr.M[rowc * pr.ld + l0 + colc];
+        rcv[r] = w.rowcol[row < w.m ? row : w.m - 1];
     }
-    __syncthreads();
-    if (!yready) {  // Y slice: thread -> row s = tid / 8, columns 4 (tid % 8) .. + 3
-        const int s = tid >> 3, c4 = (tid & 7) * 4;
-        double s1[4] = {0.0, 0.0, 0.0, 0.0}, s0[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int k = 0; k < t; ++k) {
-            const uint32_t pv = sP[s][k];
-            const double hi = (double)(pv >> 16), lo = (double)(pv & 0xffffu);
-            for (int e = 0; e < 4; ++e) {
-                const double rv = (double)sR[k][c4 + e];
-                s1[e] = __fma_rn(hi, rv, s1[e]);
-                s0[e] = __fma_rn(lo, rv, s0[e]);
-            }
-        }
-        for (int e = 0; e < 4; ++e) {
-            // s1 < 2^51, s0 < 2^52: exact; reduce s1, recombine below 2^53, reduce
-            double q = floor(s1[e] * w.F.pinv);
-            double h = __fma_rn(-q, w.F.dp, s1[e]);
-            q = floor(h * w.F.pinv);
-            h = __fma_rn(-q, w.F.dp, h);
-            double y = __fma_rn(h, 65536.0, s0[e]);
-            q = floor(y * w.F.pinv);
-            y = __fma_rn(-q, w.F.dp, y);
-            q = floor(y * w.F.pinv);
-            y = __fma_rn(-q, w.F.dp, y);
-            if (y < 0.0) y += w.F.dp;
-            if (y >= w.F.dp) y -= w.F.dp;
-            sY[s][c4 + e] = (uint32_t)y;
-        }
-    }
-    __syncthreads();
-    if (!yready && tid < 64) {  // B fragment: digit plane l', lane L holds column L%32, rows 16 (L/32) + i
-        int8_t outb[4][16];
-        for (int i = 0; i < 16; ++i) {
-            int8_t d[4];
-            digits4(centre(sY[16 * (tid >> 5) + i][tid & 31], p), d);
-            for (int l = 0; l < 4; ++l) outb[l][i] = d[l];
-        }
-        for (int l = 0; l < 4; ++l) {
-            v4i vv;
-            __builtin_memcpy(&vv, outb[l], 16);
-            sB[l * 64 + tid] = vv;
+#pragma unroll
+    for (int cbi = 0; cbi < kLeafBlocks; ++cbi) {
+        const int64_t col = (cb0 + cbi) * 32 + (lane & 31);
+        const int64_t colc = col < N ? col : N - 1;
+        for (int r = 0; r < 16; ++r) {
+            const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            cur[cbi][r] = pr.M[(row < w.m ? row : w.m - 1) * pr.ld + l0 + colc];
         }
     }
     v4i af[4];
@@ -397,21 +351,87 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_product_i8_kernel(
         }
         for (int l = 0; l < 4; ++l) __builtin_memcpy(&af[l], outa[l], 16);
     }
-    __syncthreads();
-    v16i acc[7];
-    for (int g = 0; g < 7; ++g)
-        for (int r = 0; r < 16; ++r) acc[g][r] = 0;
-    if (!yready)
-        for (int l = 0; l < 4; ++l) bf[l] = sB[l * 64 + lane];
-    for (int l = 0; l < 4; ++l)
-        for (int lp = 0; lp < 4; ++lp)
-            acc[l + lp] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[l], bf[lp], acc[l + lp], 0, 0, 0);
-    if (col >= N || pivcol) return;
-    for (int r = 0; r < 16; ++r) {
-        const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        if (row >= w.m) continue;
-        const bool fresh = rcv[r] >= gcol0 && rcv[r] < gcol0 + wl;  // a pivot row of this leaf
-        pr.M[row * pr.ld + l0 + col] = fold7(acc, r, fresh ? 0u : cur[r], c32, w.F);
+#pragma unroll
+    for (int cbi = 0; cbi < kLeafBlocks; ++cbi) {
+        const int64_t cb = cb0 + cbi;
+        if (cb >= NB) continue;  // uniform over the block
+        v4i bf[4];
+        if (yready) {
+            for (int l = 0; l < 4; ++l) bf[l] = *(const v4i*)(yfrag + (cb * 4 + l) * 1024 + lane * 16);
+        } else {
+            __syncthreads();  // the previous slice's LDS is free
+            for (int i = tid; i < 32 * 32; i += kThreads) {
+                const int s = i >> 5, c = i & 31;
+                const int64_t col = cb * 32 + c;
+                const uint32_t pv = out->pinv[s * 32 + c];
+                const uint32_t rv = rsave[s * ldr + (col < N ? col : N - 1)];
+                const int cs = out->col[s];
+                sP[s][c] = (s < t && c < t) ? pv : 0u;
+                sR[s][c] = (s < t && col < N) ? (col == (int64_t)wj + cs ? 1u : rv) : 0u;
+            }
+            __syncthreads();
+            {  // Y slice: thread -> row s = tid / 8, columns 4 (tid % 8) .. + 3
+                const int s = tid >> 3, c4 = (tid & 7) * 4;
+                double s1[4] = {0.0, 0.0, 0.0, 0.0}, s0[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int k = 0; k < t; ++k) {
+                    const uint32_t pv = sP[s][k];
+                    const double hi = (double)(pv >> 16), lo = (double)(pv & 0xffffu);
+                    for (int e = 0; e < 4; ++e) {
+                        const double rv = (double)sR[k][c4 + e];
+                        s1[e] = __fma_rn(hi, rv, s1[e]);
+                        s0[e] = __fma_rn(lo, rv, s0[e]);
+                    }
+                }
+                for (int e = 0; e < 4; ++e) {
+                    // s1 < 2^51, s0 < 2^52: exact; reduce s1, recombine below 2^53, reduce
+                    double q = floor(s1[e] * w.F.pinv);
+                    double h = __fma_rn(-q, w.F.dp, s1[e]);
+                    q = floor(h * w.F.pinv);
+                    h = __fma_rn(-q, w.F.dp, h);
+                    double y = __fma_rn(h, 65536.0, s0[e]);
+                    q = floor(y * w.F.pinv);
+                    y = __fma_rn(-q, w.F.dp, y);
+                    q = floor(y * w.F.pinv);
+                    y = __fma_rn(-q, w.F.dp, y);
+                    if (y < 0.0) y += w.F.dp;
+                    if (y >= w.F.dp) y -= w.F.dp;
+                    sY[s][c4 + e] = (uint32_t)y;
+                }
+            }
+            __syncthreads();
+            if (tid < 64) {  // B fragment: digit plane l', lane L holds column L%32, rows 16 (L/32) + i
+                int8_t outb[4][16];
+                for (int i = 0; i < 16; ++i) {
+                    int8_t d[4];
+                    digits4(centre(sY[16 * (tid >> 5) + i][tid & 31], p), d);
+                    for (int l = 0; l < 4; ++l) outb[l][i] = d[l];
+                }
+                for (int l = 0; l < 4; ++l) {
+                    v4i vv;
+                    __builtin_memcpy(&vv, outb[l], 16);
+                    sB[l * 64 + tid] = vv;
+                }
+            }
+            __syncthreads();
+            for (int l = 0; l < 4; ++l) bf[l] = sB[l * 64 + lane];
+        }
+        v16i acc[7];
+        for (int g = 0; g < 7; ++g)
+            for (int r = 0; r < 16; ++r) acc[g][r] = 0;
+        for (int l = 0; l < 4; ++l)
+            for (int lp = 0; lp < 4; ++lp)
+                acc[l + lp] =
+                    __builtin_amdgcn_mfma_i32_32x32x32_i8(af[l], bf[lp], acc[l + lp], 0, 0, 0);
+        const int64_t col = cb * 32 + (lane & 31);
+        const bool pivcol = col < wl && w.colpiv[gcol0 + (col < wl ? col : 0)] >= 0;
+        if (col < N && !pivcol) {
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                if (row >= w.m) continue;
+                const bool fresh = rcv[r] >= gcol0 && rcv[r] < gcol0 + wl;  // a pivot row of this leaf
+                pr.M[row * pr.ld + l0 + col] = fold7(acc, r, fresh ? 0u : cur[cbi][r], c32, w.F);
+            }
+        }
     }
 }
 
@@ -532,14 +552,15 @@ struct Blocked {
     Mat PR;       // outer panel [panel | E]
     int8_t* Afrag;
     int8_t* Bfrag;
+    int8_t* Yfrag;  // the int8 leaf products' right operand (kept apart from the trailing one)
     LeafState leaf;
     int32_t panel;
 };
 
 // Workspace after the plain layout: PR (m x ldpr), the operand fragments (sized
 // for the larger of the int8 layouts, 4 B per element, and the FP64 ones, 8 B,
-// for both the trailing product and the leaf products) and the leaf selection
-// state.
+// for both the trailing product and the leaf products), the leaf products' Y
+// fragments and the leaf selection state.
 size_t carve_blocked(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, Blocked* b) {
     const size_t base = plain_workspace(m, n, k);
     Carver c(ws ? (char*)ws + base : nullptr);
@@ -553,6 +574,7 @@ size_t carve_blocked(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, B
     uint32_t* PR = c.take<uint32_t>(m * ldpr);
     int8_t* A = c.take<int8_t>(abytes);
     int8_t* B = c.take<int8_t>(bbytes);
+    int8_t* Y = c.take<int8_t>(Nl * kLeaf * 4);
     LeafState ls;
     leaf_carve(c, m, Nl, &ls);
     if (b) {
@@ -560,6 +582,7 @@ size_t carve_blocked(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, B
         b->PR = Mat{PR, ldpr};
         b->Afrag = A;
         b->Bfrag = B;
+        b->Yfrag = Y;
         b->leaf = ls;
         b->panel = panel;
     }
@@ -568,34 +591,34 @@ size_t carve_blocked(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, B
 
 // The product kernel: dst columns [col0, col0 + N) of every row become
 // delta * C + A . B from the prepared fragments (K = 32 KB for int8, 4 KB for
-// FP64); delta = 0 for the rows whose pivot column lies in [fresh_lo, fresh_hi).
-hipError_t run_product(const Blocked& b, const PlainArgs& w, bool fp64, Mat dst, int64_t col0,
-                       int64_t N, int32_t KB, int32_t fresh_lo, int32_t fresh_hi, hipStream_t s,
-                       LaunchTimer& lt, int kind) {
+// FP64; B's first fragment belongs to column col0); delta = 0 for the rows
+// whose pivot column lies in [fresh_lo, fresh_hi).
+hipError_t run_product(const PlainArgs& w, bool fp64, const int8_t* Af, const int8_t* Bf, Mat dst,
+                       int64_t col0, int64_t N, int32_t KB, int32_t fresh_lo, int32_t fresh_hi,
+                       hipStream_t s, LaunchTimer& lt, int kind) {
     const int64_t m = w.m;
-    lt.before(kind);
+    lt.before(kind, s);
     if (fp64) {
         hipLaunchKernelGGL(gemm_f64_kernel, dim3((unsigned)ceil_div(m, 64), (unsigned)ceil_div(N, 64)),
-                           dim3(kThreads), 0, s, w, dst, col0, N, (const double*)b.Afrag,
-                           (const double*)b.Bfrag, KB, ceil_div(N, 16), fresh_lo, fresh_hi);
+                           dim3(kThreads), 0, s, w, dst, col0, N, (const double*)Af,
+                           (const double*)Bf, KB, ceil_div(N, 16), fresh_lo, fresh_hi);
     } else {
         const double c32 = (double)((((uint64_t)1) << 32) % w.F.p);
         hipLaunchKernelGGL(gemm_i8_kernel, dim3((unsigned)ceil_div(m, 128), (unsigned)ceil_div(N, 32)),
-                           dim3(kThreads), 0, s, w, dst, col0, N, b.Afrag, b.Bfrag, KB, fresh_lo,
-                           fresh_hi, c32);
+                           dim3(kThreads), 0, s, w, dst, col0, N, Af, Bf, KB, fresh_lo, fresh_hi,
+                           c32);
     }
     lt.after();
     return hipGetLastError();
 }
 
-// Trailing update: dst columns [col0, col0 + N) of every row become
-// delta * C + E . X_S, where E is PR's transform block (columns [wj, 2 wj)) and
-// X_S the pivot rows of bookkeeping columns [j0, j0 + wj) read from dst (before
-// the update), with delta = 0 for the panel's pivot rows.
-hipError_t trailing_product(const Blocked& b, const PlainArgs& w, bool fp64, Mat dst, int32_t j0,
-                            int32_t wj, int64_t col0, int64_t N, hipStream_t s, LaunchTimer& lt) {
+// Operands of the trailing update of panel [j0, j0 + wj) over dst columns
+// [col0, col0 + N): A = PR's transform block (columns [wj, 2 wj)), B = X_S,
+// the pivot rows of bookkeeping columns [j0, j0 + wj) read from dst.  Returns
+// the number of k-blocks.
+int32_t trailing_operands(const Blocked& b, const PlainArgs& w, bool fp64, Mat dst, int32_t j0,
+                          int32_t wj, int64_t col0, int64_t N, hipStream_t s, LaunchTimer& lt) {
     const int64_t m = w.m;
-    if (N <= 0) return hipSuccess;
     lt.before(LINAC_KERNEL_OPERANDS);
     int32_t KB;
     if (fp64) {
@@ -616,10 +639,7 @@ hipError_t trailing_product(const Blocked& b, const PlainArgs& w, bool fp64, Mat
                            s, w, b.PR, (int64_t)wj, wj, KB, MB, b.Afrag);
     }
     lt.after();
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return run_product(b, w, fp64, dst, col0, N, KB, j0, j0 + wj, s, lt,
-                       LINAC_KERNEL_TRAIL_PRODUCT);
+    return KB;
 }
 
 }  // namespace
@@ -635,8 +655,17 @@ size_t blocked_workspace(int64_t m, int64_t n, int64_t k, int32_t panel) {
 // transform block, where the leaf's pivots carry their implicit 1).  After the
 // last leaf, PR holds the reduced panel and the panel transform, and one MFMA
 // product with K = panel updates all trailing columns of W.
+//
+// Look-ahead (int8 path): the trailing update of panel k is split into the
+// next panel's columns (on the caller's stream, before that panel starts) and
+// the remaining columns, which run on a side stream while the next panel's
+// leaves (latency bound, on few compute units) proceed.  The next panel's
+// trailing operands wait for that remainder: it writes the columns they read.
+// The leaves touch only PR, the leaf state and the pivot bookkeeping; of those
+// the remainder reads only rowcol, to spot the previous panel's pivot rows,
+// which new pivot rows (from -1 to a later column) never are either way.
 hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, bool fp64,
-                             PlainArgs& out, const linac_opts* opts, hipStream_t s) {
+                             bool overlap, PlainArgs& out, const linac_opts* opts, hipStream_t s) {
     Blocked b;
     carve_blocked(ws, m, n, k, panel, &b);
     b.w.F = out.F;
@@ -649,7 +678,21 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
     const Mat Wm{w.W, w.ld};
     int64_t outer_products = 0;
     LaunchTimer lt(opts, s);
-    hipError_t e = leaf_init(b.leaf, (int32_t)m, s);
+    hipStream_t side = nullptr;
+    hipEvent_t ev_t1 = nullptr, ev_t2 = nullptr;
+    const bool lookahead = overlap && !fp64 && n > panel;
+    hipError_t e = hipSuccess;
+    if (lookahead) {
+        e = side_stream(&side);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_t1, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_t2, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            if (ev_t1) (void)hipEventDestroy(ev_t1);
+            return e;
+        }
+    }
+    bool t2_pending = false;
+    if (e == hipSuccess) e = leaf_init(b.leaf, (int32_t)m, s);
     int32_t leaf_index = 0;
     for (int32_t j0 = 0; j0 < n && e == hipSuccess; j0 += panel) {
         const int32_t wj = (int32_t)(n - j0 < panel ? n - j0 : panel);
@@ -663,7 +706,7 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
             const int64_t N = (int64_t)wj + wl;
             lt.before(LINAC_KERNEL_SELECT);
             e = leaf_select(w, b.leaf, b.PR.M, b.PR.ld, l0, wl, wj, j0 + l0, parity, N,
-                            fp64 ? nullptr : b.Bfrag, s);
+                            fp64 ? nullptr : b.Yfrag, s);
             lt.after();
             if (e != hipSuccess) break;
             if (fp64) {
@@ -672,34 +715,63 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
                                   b.Afrag, b.Bfrag, s);
                 lt.after();
                 if (e != hipSuccess) break;
-                e = run_product(b, w, fp64, b.PR, (int64_t)l0, N, kLeaf / 4, j0 + l0, j0 + l0 + wl,
-                                s, lt, LINAC_KERNEL_LEAF_PRODUCT);
+                e = run_product(w, fp64, b.Afrag, b.Bfrag, b.PR, (int64_t)l0, N, kLeaf / 4, j0 + l0,
+                                j0 + l0 + wl, s, lt, LINAC_KERNEL_LEAF_PRODUCT);
             } else {
                 const double c32 = (double)((((uint64_t)1) << 32) % w.F.p);
                 lt.before(LINAC_KERNEL_LEAF_PRODUCT);
                 hipLaunchKernelGGL(leaf_product_i8_kernel,
-                                   dim3((unsigned)ceil_div(m, 128), (unsigned)ceil_div(N, 32)),
+                                   dim3((unsigned)ceil_div(m, 128),
+                                        (unsigned)ceil_div(N, 32 * kLeafBlocks)),
                                    dim3(kThreads), 0, s, w, b.PR, l0, wl, wj, j0 + l0, N,
                                    (const LeafOut*)b.leaf.out, (const uint32_t*)b.leaf.rsave,
                                    b.leaf.ldr, c32, (const int32_t*)b.leaf.cand[parity],
                                    b.leaf.cand[parity ^ 1], (const int32_t*)(b.leaf.count + parity),
-                                   b.leaf.count + (parity ^ 1), (const int8_t*)b.Bfrag);
+                                   b.leaf.count + (parity ^ 1), (const int8_t*)b.Yfrag);
                 lt.after();
                 e = hipGetLastError();
             }
             ++leaf_index;
         }
         if (e != hipSuccess) break;
+        if (t2_pending) {  // the previous remainder writes the columns read next
+            e = hipStreamWaitEvent(s, ev_t2, 0);
+            t2_pending = false;
+            if (e != hipSuccess) break;
+        }
         const int64_t N = ncols - (j0 + wj);
         if (N > 0) {
             if (opts && opts->ev_begin && outer_products == 0) (void)hipEventRecord(opts->ev_begin, s);
-            e = trailing_product(b, w, fp64, Wm, j0, wj, (int64_t)j0 + wj, N, s, lt);
+            const int64_t col0 = (int64_t)j0 + wj;
+            const int32_t KB = trailing_operands(b, w, fp64, Wm, j0, wj, col0, N, s, lt);
+            e = hipGetLastError();
+            // the next panel's columns now, the rest on the side stream
+            const int64_t n1 = lookahead && N > panel ? panel : N;
+            if (e == hipSuccess)
+                e = run_product(w, fp64, b.Afrag, b.Bfrag, Wm, col0, n1, KB, j0, j0 + wj, s, lt,
+                                LINAC_KERNEL_TRAIL_PRODUCT);
+            if (e == hipSuccess && n1 < N) {
+                e = hipEventRecord(ev_t1, s);
+                if (e == hipSuccess) e = hipStreamWaitEvent(side, ev_t1, 0);
+                if (e == hipSuccess)
+                    e = run_product(w, fp64, b.Afrag, b.Bfrag + (n1 / 32) * KB * 4 * 1024, Wm,
+                                    col0 + n1, N - n1, KB, j0, j0 + wj, side, lt,
+                                    LINAC_KERNEL_TRAIL_PRODUCT);
+                if (e == hipSuccess) e = hipEventRecord(ev_t2, side);
+                t2_pending = e == hipSuccess;
+            }
             ++outer_products;
         }
         hipLaunchKernelGGL(panel_writeback_kernel, dim3((unsigned)ceil_div(m * wj, 256)), dim3(256),
                            0, s, w, b.PR, Wm, (int64_t)j0, wj, j0);
         if (e == hipSuccess) e = hipGetLastError();
     }
+    if (t2_pending) {
+        const hipError_t e2 = hipStreamWaitEvent(s, ev_t2, 0);
+        if (e == hipSuccess) e = e2;
+    }
+    if (ev_t1) (void)hipEventDestroy(ev_t1);
+    if (ev_t2) (void)hipEventDestroy(ev_t2);
     if (opts && opts->ev_end && outer_products > 0) (void)hipEventRecord(opts->ev_end, s);
     if (opts && opts->dominant_launches) *opts->dominant_launches = outer_products;
     return e;

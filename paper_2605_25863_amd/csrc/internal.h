@@ -67,18 +67,25 @@ struct LaunchTimer {
     int32_t used = 0;
     LaunchTimer(const linac_opts* opts, hipStream_t st) : o(opts), s(st) {}
     bool on() const { return o && o->launch_events && o->launch_cap > 0 && used < o->launch_cap; }
-    void before(int kind) {
+    hipStream_t cur = nullptr;  // the stream of the launch being bracketed
+    void before(int kind, hipStream_t on_stream = nullptr) {
         if (!on()) return;
-        (void)hipEventRecord(o->launch_events[2 * used], s);
+        cur = on_stream ? on_stream : s;
+        (void)hipEventRecord(o->launch_events[2 * used], cur);
         if (o->launch_kinds) o->launch_kinds[used] = kind;
     }
     void after() {
         if (!on()) return;
-        (void)hipEventRecord(o->launch_events[2 * used + 1], s);
+        (void)hipEventRecord(o->launch_events[2 * used + 1], cur);
         ++used;
         if (o->launch_used) *o->launch_used = used;
     }
 };
+
+// A second stream per device (created on first use, default priority) for work
+// that may overlap the caller's stream within one call; the call joins it back
+// to the caller's stream before returning.
+hipError_t side_stream(hipStream_t* out);
 
 // One Gauss-Jordan step for local pivot column j over local columns [.., ncols_eff).
 hipError_t launch_gj_step(const PlainArgs& a, int32_t j, int32_t ncols_eff, hipStream_t s);
@@ -129,10 +136,12 @@ __device__ __forceinline__ void leaf_compact_entry(const LeafOut* out, int32_t t
                                                    int32_t E, int64_t i) {
     if (i >= E) return;
     int pos[32];  // all loads first (the array always has 32 entries)
+#pragma unroll
     for (int k = 0; k < 32; ++k) pos[k] = out->pos[k];
     const int32_t row = cand[i];
     int shift = 0;
     bool gone = false;
+#pragma unroll
     for (int k = 0; k < 32; ++k) {
         const bool in = k < t;
         shift += in && pos[k] < i;
@@ -166,7 +175,7 @@ hipError_t leaf_operands(const PlainArgs& w, const LeafState& ls, const uint32_t
 // carved bookkeeping out (for the shared extraction kernels).
 size_t blocked_workspace(int64_t m, int64_t n, int64_t k, int32_t panel);
 hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, bool fp64,
-                             PlainArgs& a, const linac_opts* opts, hipStream_t s);
+                             bool lookahead, PlainArgs& a, const linac_opts* opts, hipStream_t s);
 
 // Batched path (batched.hip): workspace = [queue counter | descriptors | one
 // working region per system].

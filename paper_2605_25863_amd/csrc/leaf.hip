@@ -37,7 +37,7 @@ namespace linac {
 
 namespace {
 
-constexpr int kSelWaves = 16;
+constexpr int kSelWaves = 4;
 constexpr int kSelThreads = 64 * kSelWaves;
 constexpr int kChunk = 32;     // candidate rows per first-level tree node
 constexpr int kNodeInts = 64;  // per node: basis size, then its list positions
@@ -145,23 +145,34 @@ __device__ int node_id(int level, int k, int gmax) {
     return base + k;
 }
 
-// Gauss-Jordan over the leaf columns of the node's rows.  R = 64: lane = row,
-// wave v holds leaf columns v and v + 16 (v[0], v[1]) and transform columns v
-// and v + 16 (T[0], T[1]).  R = 32: lane = 32 h + row, wave v holds leaf column
-// v + 16 h and transform column v + 16 h in v[0] and T[0] (half the work per
-// step).  Per step the owner wave of column j finds the first eligible row with
-// a non-zero entry and posts it with the column and the pivot value to LDS.
+// Register layout of the selection's Gauss-Jordan (4 waves, one per SIMD).
+// R = 32 rows: lane = 32 h + row; register k of wave v holds column 8k + 4h + v
+// (k < 4).  R = 64 rows: lane = row; register k holds column 4k + v (k < 8).
+// Leaf columns live in v[], transform columns in T[], with the same layout.
 template <int R>
-__device__ __forceinline__ void node_gj(const SelArgs& a, Sel& S, double v[2], double T[2],
+struct Lay {
+    static constexpr int kRegs = R == 32 ? 4 : 8;
+    __device__ static int col(int wave, int h, int k) { return R == 32 ? 8 * k + 4 * h + wave : 4 * k + wave; }
+    __device__ static int owner_wave(int j) { return j & 3; }
+    __device__ static int owner_half(int j) { return R == 32 ? (j >> 2) & 1 : 0; }
+    __device__ static int owner_reg(int j) { return R == 32 ? j >> 3 : j >> 2; }
+};
+
+// Gauss-Jordan over the leaf columns of the node's rows.  Per step the owner
+// wave of column j finds the first eligible row with a non-zero entry and
+// posts it with the column and the pivot value to LDS.
+template <int R>
+__device__ __forceinline__ void node_gj(const SelArgs& a, Sel& S, double v[8], double T[8],
                                         const Lazy& L) {
+    typedef Lay<R> Y;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int h = R == 32 ? lane >> 5 : 0;
     const int r = R == 32 ? lane & 31 : lane;  // this lane's row within the node
     const int nrows = S.nrows;
     const int32_t row = r < nrows ? a.cand[S.pos[r]] : -1;
 #pragma unroll
-    for (int k = 0; k < (R == 64 ? 2 : 1); ++k) {
-        const int c = R == 64 ? wave + 16 * k : wave + 16 * h;
+    for (int k = 0; k < Y::kRegs; ++k) {
+        const int c = Y::col(wave, h, k);
         v[k] = (row >= 0 && c < a.wl) ? (double)a.PR[(int64_t)row * a.ldpr + a.l0 + c] : 0.0;
         T[k] = 0.0;
     }
@@ -170,12 +181,14 @@ __device__ __forceinline__ void node_gj(const SelArgs& a, Sel& S, double v[2], d
     unsigned long long chosen = 0;
     int t = 0;
     double cprod = 1.0;  // common scale of the non-pivot rows' own coefficient
-    // Owner wave of column j: post the first eligible row with a non-zero entry
-    // (-1: free column), its pivot value and the column itself.  A lazy value
-    // x in (-3p, 3p) is zero mod p iff |x| is 0, p or 2p.
+    // A lazy value x in (-3p, 3p) is zero mod p iff |x| is 0, p or 2p.
     auto detect = [&](int j) {
-        const int hj = j >> 4;
-        const double x = (R == 64 && hj) ? v[1] : v[0];
+        const int hj = Y::owner_half(j), kj = Y::owner_reg(j);
+        // x = v[kj] as arithmetic (exact: one term is the value, the rest are 0),
+        // which keeps the registers out of indexed scratch memory
+        double x = 0.0;
+#pragma unroll
+        for (int k = 0; k < Y::kRegs; ++k) x = __fma_rn(v[k], k == kj ? 1.0 : 0.0, x);
         const double ax = fabs(x);
         const unsigned long long nz = __ballot(!(ax == 0.0 || ax == L.p || ax == 2.0 * L.p));
         const unsigned long long m =
@@ -191,8 +204,14 @@ __device__ __forceinline__ void node_gj(const SelArgs& a, Sel& S, double v[2], d
             S.d[buf] = d;
         }
     };
+    // this lane's copy of the pivot row's entry in register k
+    auto prow = [&](double x, int q) {
+        if (R == 64) return readlane_d(x, q);
+        const double u0 = readlane_d(x, q), u1 = readlane_d(x, 32 + q);
+        return h ? u1 : u0;
+    };
     __syncthreads();
-    if (wave == 0 && a.wl > 0) detect(0);
+    if (wave == Y::owner_wave(0) && a.wl > 0) detect(0);
     for (int j = 0; j < a.wl; ++j) {
         __syncthreads();  // step j posted; every wave is done with step j - 1's post
         const int buf = j & 1;
@@ -209,45 +228,29 @@ __device__ __forceinline__ void node_gj(const SelArgs& a, Sel& S, double v[2], d
                 S.cp[s] = cprod;
             }
             // leaf columns first: the next column's owner posts right after
-            if (R == 64) {
 #pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    const int c = wave + 16 * k;
-                    if (c > j && c < a.wl) {
-                        const double u = readlane_d(v[k], q);
-                        if (r != q) v[k] = lz_ff(d, v[k], fi, u, L);
-                    }
-                }
-            } else {
-                const int c = wave + 16 * h;
-                if (wave + 16 > j) {  // some column of this wave still changes
-                    const double u0 = readlane_d(v[0], q), u1 = readlane_d(v[0], 32 + q);
-                    if (c > j && c < a.wl && r != q) v[0] = lz_ff(d, v[0], fi, h ? u1 : u0, L);
+            for (int k = 0; k < Y::kRegs; ++k) {
+                const int cmax = R == 32 ? 8 * k + 4 + wave : 4 * k + wave;
+                if (cmax > j) {
+                    const double u = prow(v[k], q);
+                    const int c = Y::col(wave, h, k);
+                    if (c > j && c < a.wl && r != q) v[k] = lz_ff(d, v[k], fi, u, L);
                 }
             }
             chosen |= 1ull << q;
         }
-        if (j + 1 < a.wl && wave == ((j + 1) & 15)) detect(j + 1);
+        if (j + 1 < a.wl && wave == Y::owner_wave(j + 1)) detect(j + 1);
         if (q >= 0) {
-            if (R == 64) {
 #pragma unroll
-                for (int k = 0; k < 2; ++k) {
-                    const int c = wave + 16 * k;
+            for (int k = 0; k < Y::kRegs; ++k) {
+                const int cmin = R == 32 ? 8 * k + wave : 4 * k + wave;
+                if (cmin <= s) {
+                    const double u = prow(T[k], q);
+                    const int c = Y::col(wave, h, k);
                     if (c < s) {
-                        const double u = readlane_d(T[k], q);
                         if (r != q) T[k] = lz_ff(d, T[k], fi, u, L);
                     } else if (c == s) {
                         T[k] = r == q ? cprod : -lz_mul(fi, cprod, L);
-                    }
-                }
-            } else {
-                const int c = wave + 16 * h;
-                if (wave <= s) {
-                    const double u0 = readlane_d(T[0], q), u1 = readlane_d(T[0], 32 + q);
-                    if (c < s) {
-                        if (r != q) T[0] = lz_ff(d, T[0], fi, h ? u1 : u0, L);
-                    } else if (c == s) {
-                        T[0] = r == q ? cprod : -lz_mul(fi, cprod, L);
                     }
                 }
             }
@@ -267,7 +270,7 @@ __device__ __forceinline__ void node_gj(const SelArgs& a, Sel& S, double v[2], d
 // Final node: P^-1, the leaf result, the pivot bookkeeping, and a copy of the
 // pivot rows over the columns the leaf updates (the product overwrites them).
 template <int R>
-__device__ __forceinline__ void publish(const SelArgs& a, Sel& S, const double T[2], bool save_rows,
+__device__ __forceinline__ void publish(const SelArgs& a, Sel& S, const double T[8], bool save_rows,
                                         const Lazy& L) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int h = R == 32 ? lane >> 5 : 0;
@@ -281,15 +284,17 @@ __device__ __forceinline__ void publish(const SelArgs& a, Sel& S, const double T
         if (t > 0) S.total = lz_inverse(lz_canon(S.total, L), a.w.F.p, L);
     } else if (threadIdx.x >= 64 && t > 0 && save_rows) {  // meanwhile the other waves save the rows
         for (int64_t c = threadIdx.x - 64; c < a.ncopy; c += kSelThreads - 64) {
-            // every load issued before any store; pivots k >= t reuse pivot 0's
-            // row (S.rows[0] is set because t > 0)
-            uint32_t x[32];
+            // eight loads in flight before their stores; pivots k >= t reuse pivot
+            // 0's row (S.rows[0] is set because t > 0)
+            for (int k0 = 0; k0 < 32; k0 += 8) {
+                uint32_t x[8];
 #pragma unroll
-            for (int k = 0; k < 32; ++k)
-                x[k] = a.PR[(int64_t)S.rows[k < t ? k : 0] * a.ldpr + a.l0 + c];
+                for (int k = 0; k < 8; ++k)
+                    x[k] = a.PR[(int64_t)S.rows[k0 + k < t ? k0 + k : 0] * a.ldpr + a.l0 + c];
 #pragma unroll
-            for (int k = 0; k < 32; ++k)
-                if (k < t) a.rsave[k * a.ldr + c] = x[k];
+                for (int k = 0; k < 8; ++k)
+                    if (k0 + k < t) a.rsave[(k0 + k) * a.ldr + c] = x[k];
+            }
         }
     }
     __syncthreads();
@@ -297,8 +302,8 @@ __device__ __forceinline__ void publish(const SelArgs& a, Sel& S, const double T
     if (s >= 0) {
         const double dinv = lz_mul(S.cp[s], S.total, L);
 #pragma unroll
-        for (int k = 0; k < (R == 64 ? 2 : 1); ++k) {
-            const int c = R == 64 ? wave + 16 * k : wave + 16 * h;
+        for (int k = 0; k < Lay<R>::kRegs; ++k) {
+            const int c = Lay<R>::col(wave, h, k);
             if (c < t) a.out->pinv[s * 32 + c] = (uint32_t)lz_canon(lz_mul(dinv, T[k], L), L);
         }
     }
@@ -334,11 +339,10 @@ __device__ void build_y_block(const SelArgs& a, int g, const Lazy& L) {
     __shared__ uint32_t sR[32][33];
     __shared__ __attribute__((aligned(16))) int8_t sB[4][64][16];
     const int tid = threadIdx.x;
-    const int s = tid >> 5, c = tid & 31;
     const int t = a.out->t;
-    const int64_t col = (int64_t)g * 32 + c;
-    {
-        const int k = s;  // this thread stages R[k][c] and Pinv[k][c]
+    for (int i = tid; i < 32 * 32; i += kSelThreads) {  // stage R[k][c] and Pinv[k][c]
+        const int k = i >> 5, c = i & 31;
+        const int64_t col = (int64_t)g * 32 + c;
         const int krow = a.out->row[k < t ? k : 0];
         const int kcol = a.out->col[k];
         const int64_t colc = col < a.ncopy ? col : a.ncopy - 1;
@@ -348,25 +352,27 @@ __device__ void build_y_block(const SelArgs& a, int g, const Lazy& L) {
         sP[k][c] = (k < t && c < t) ? pv : 0u;
     }
     __syncthreads();
-    double s1 = 0.0, s0 = 0.0;
-    for (int k = 0; k < t; ++k) {
-        const uint32_t pv = sP[s][k];
-        const double r = (double)sR[k][c];
-        s1 = __fma_rn((double)(pv >> 16), r, s1);
-        s0 = __fma_rn((double)(pv & 0xffffu), r, s0);
-    }
-    // s1 < 2^51, s0 < 2^52: exact; (s1 mod p) 2^16 + s0 < 2^53
-    const double y = lz_canon_wide(__fma_rn(lz_canon_wide(s1, L), 65536.0, s0), L);
     const uint32_t p = a.w.F.p;
-    const uint32_t yv = (uint32_t)y;
-    int32_t x = yv > (p - 1) / 2 ? (int32_t)yv - (int32_t)p : (int32_t)yv;
-    for (int l = 0; l < 4; ++l) {
-        const int8_t d = (int8_t)(x & 0xff);
-        sB[l][c + 32 * (s >> 4)][s & 15] = d;
-        x = (x - d) >> 8;
+    for (int i = tid; i < 32 * 32; i += kSelThreads) {
+        const int s = i >> 5, c = i & 31;
+        double s1 = 0.0, s0 = 0.0;
+        for (int k = 0; k < t; ++k) {
+            const uint32_t pv = sP[s][k];
+            const double r = (double)sR[k][c];
+            s1 = __fma_rn((double)(pv >> 16), r, s1);
+            s0 = __fma_rn((double)(pv & 0xffffu), r, s0);
+        }
+        // s1 < 2^51, s0 < 2^52: exact; (s1 mod p) 2^16 + s0 < 2^53
+        const uint32_t yv = (uint32_t)lz_canon_wide(__fma_rn(lz_canon_wide(s1, L), 65536.0, s0), L);
+        int32_t x = yv > (p - 1) / 2 ? (int32_t)yv - (int32_t)p : (int32_t)yv;
+        for (int l = 0; l < 4; ++l) {
+            const int8_t dg = (int8_t)(x & 0xff);
+            sB[l][c + 32 * (s >> 4)][s & 15] = dg;
+            x = (x - dg) >> 8;
+        }
     }
     __syncthreads();
-    if (tid < 256) {
+    {
         const int l = tid >> 6, L2 = tid & 63;
         *(v4i*)(a.yfrag + ((int64_t)g * 4 + l) * 1024 + L2 * 16) = *(const v4i*)&sB[l][L2][0];
     }
@@ -379,7 +385,8 @@ __device__ void build_y_block(const SelArgs& a, int g, const Lazy& L) {
 // other work on the device) and publishes when that chunk already has full
 // rank, as with dense data; the full tree launch then finds the result
 // published and ends at once, or selects over all candidates.
-__global__ __launch_bounds__(kSelThreads) void leaf_select_kernel(SelArgs a, int32_t first) {
+template <bool first>
+__global__ __launch_bounds__(kSelThreads, first ? 4 : 1) void leaf_select_kernel(SelArgs a) {
     __shared__ Sel S;
     const Lazy L{(double)a.w.F.p, a.w.F.pinv};
     int32_t* published = a.cnt_cur + (a.ncnt - 1);
@@ -413,9 +420,12 @@ __global__ __launch_bounds__(kSelThreads) void leaf_select_kernel(SelArgs a, int
     if (threadIdx.x == 0) S.nrows = min(kChunk, E - g * kChunk);
     __syncthreads();
     int level = 0, k = g, nodes = G;
-    double v[2], T[2];
+    double v[8], T[8];
     node_gj<32>(a, S, v, T, L);
-    if (first && !(S.t == a.wl || nodes == 1)) return;  // the tree launch decides
+    if (first) {
+        if (S.t == a.wl || nodes == 1) publish<32>(a, S, T, false, L);
+        return;  // otherwise the tree launch decides
+    }
     int regs = 32;  // v, T hold the Gauss-Jordan of the node's basis rows in this layout (0: none)
     while (true) {
         const int t = S.t;
@@ -751,8 +761,8 @@ hipError_t leaf_select(const PlainArgs& w, const LeafState& ls, const uint32_t* 
     a.yfrag = yfrag;
     const int64_t nyb = ceil_div(ncopy, 32);
     const unsigned grid = (unsigned)(ls.gmax > nyb ? ls.gmax : nyb);
-    hipLaunchKernelGGL(leaf_select_kernel, dim3(1), dim3(kSelThreads), 0, s, a, 1);
-    hipLaunchKernelGGL(leaf_select_kernel, dim3(grid), dim3(kSelThreads), 0, s, a, 0);
+    hipLaunchKernelGGL(leaf_select_kernel<true>, dim3(1), dim3(kSelThreads), 0, s, a);
+    hipLaunchKernelGGL(leaf_select_kernel<false>, dim3(grid), dim3(kSelThreads), 0, s, a);
     return hipGetLastError();
 }
 

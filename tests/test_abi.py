@@ -155,7 +155,7 @@ def test_tuning_table_parsing(lib):
     lib.linac_solve_workspace(1500, 1500, 4, ctypes.byref(plain), ctypes.byref(b))
     assert a.value == b.value
     for bad in (b"{", b"[1,2", b'{"panel": [{"n_max": 10, "panel": 33}]}',
-                b'{"batched_per_cu": 0}', b"{} trailing"):
+                b'{"batched_per_cu": 0}', b'{"lookahead": 2}', b"{} trailing"):
         assert lib.linac_load_tuning(bad) == INVALID
     # the previous valid table is still in force
     assert lib.linac_solve_workspace(4096, 4096, 16, ctypes.byref(opts), ctypes.byref(a)) == OK
