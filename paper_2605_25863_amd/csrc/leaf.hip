@@ -123,6 +123,9 @@ struct Sel {
     double f[2][64];              // the current pivot column (double-buffered by step)
     double d[2];                  // its pivot value
     int32_t q[2];                 // its pivot row within the node, -1 for a free column
+    double f2[2][32];             // pair steps: the second column after the first pivot
+    double d2[2];
+    int32_t q2[2];
     double cp[32];                // product of the pivot values before pivot s
     int32_t pos[64];              // list positions of this node's rows (lane order)
     int32_t basis[32];            // list positions of the node's basis rows (pivot order)
@@ -267,14 +270,202 @@ __device__ __forceinline__ void node_gj(const SelArgs& a, Sel& S, double v[8], d
     __syncthreads();
 }
 
+// The 32-row elimination two columns per step (16 synchronisations per leaf
+// instead of 32).  Lane = 32 h + row; register 2k + e of wave v holds column
+// 2P + e of pair P = 8k + 4h + v (k, e in {0, 1}); T[] likewise.  The owner
+// wave of pair P finds the first column's pivot, applies it to the second
+// column itself, finds the second pivot and posts both; every wave then applies
+// the two pivots in order.  Same results as one column per step.
+__device__ __forceinline__ void node_gj_pairs(const SelArgs& a, Sel& S, double v[8], double T[8],
+                                              const Lazy& L) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int h = lane >> 5, r = lane & 31;
+    const int nrows = S.nrows;
+    const int32_t row = r < nrows ? a.cand[S.pos[r]] : -1;
+    auto colof = [&](int reg) { return 2 * (8 * (reg >> 1) + 4 * h + wave) + (reg & 1); };
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int c = colof(k);
+        v[k] = (row >= 0 && c < a.wl) ? (double)a.PR[(int64_t)row * a.ldpr + a.l0 + c] : 0.0;
+        T[k] = 0.0;
+    }
+    if (threadIdx.x < 64) S.sidx[threadIdx.x] = -1;
+    const unsigned long long valid = nrows >= 32 ? 0xffffffffull : ((1ull << nrows) - 1ull);
+    unsigned long long chosen = 0;  // rows of this node (bits 0..31)
+    int t = 0;
+    double cprod = 1.0;
+    auto prow = [&](double x, int q) {  // the pivot row's entry of this lane's column
+        const double u0 = readlane_d(x, q), u1 = readlane_d(x, 32 + q);
+        return h ? u1 : u0;
+    };
+    auto first_nz = [&](double x, int hh, unsigned long long excl) {
+        const double ax = fabs(x);  // lazy value in (-3p, 3p): zero iff |x| is 0, p or 2p
+        const unsigned long long nz = __ballot(!(ax == 0.0 || ax == L.p || ax == 2.0 * L.p));
+        const unsigned long long m = ((nz >> (32 * hh)) & 0xffffffffull) & valid & ~excl;
+        const int mlo = uniform((int)(uint32_t)m);
+        return mlo != 0 ? __builtin_ctz((uint32_t)mlo) : -1;
+    };
+    const int npairs = (a.wl + 1) >> 1;
+    // owner of pair P: post both pivots (the second column exists iff 2P + 1 < wl)
+    auto detect = [&](int P) {
+        const int hp = (P >> 2) & 1, kp = P >> 3;
+        double xa = 0.0, xb = 0.0;  // registers 2 kp and 2 kp + 1, selected arithmetically
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            xa = __fma_rn(v[2 * k], k == kp ? 1.0 : 0.0, xa);
+            xb = __fma_rn(v[2 * k + 1], k == kp ? 1.0 : 0.0, xb);
+        }
+        const int q1 = first_nz(xa, hp, chosen);
+        const double d1 = q1 >= 0 ? readlane_d(xa, 32 * hp + q1) : 0.0;
+        if (q1 >= 0) {
+            const double ub = readlane_d(xb, 32 * hp + q1);
+            if (r != q1) xb = lz_ff(d1, xb, xa, ub, L);
+        }
+        int q2 = -1;
+        double d2 = 0.0;
+        if (2 * P + 1 < a.wl) {
+            q2 = first_nz(xb, hp, chosen | (q1 >= 0 ? 1ull << q1 : 0ull));
+            d2 = q2 >= 0 ? readlane_d(xb, 32 * hp + q2) : 0.0;
+        }
+        const int buf = P & 1;
+        if (h == hp) {
+            S.f[buf][r] = xa;
+            S.f2[buf][r] = xb;
+        }
+        if (lane == 0) {
+            S.q[buf] = q1;
+            S.d[buf] = d1;
+            S.q2[buf] = q2;
+            S.d2[buf] = d2;
+        }
+    };
+    __syncthreads();
+    if (wave == 0 && a.wl > 0) detect(0);
+    for (int P = 0; P < npairs; ++P) {
+        __syncthreads();  // pair P posted; every wave is done with pair P - 1's post
+        const int buf = P & 1;
+        const int q1v = S.q[buf], q2v = S.q2[buf];
+        const double f1 = S.f[buf][r], f2 = S.f2[buf][r];
+        const double d1 = S.d[buf], d2 = S.d2[buf];
+        const int q1 = uniform(q1v), q2 = uniform(q2v);
+        const int j = 2 * P;
+        const int s1 = t, s2 = t + (q1 >= 0);
+        if (threadIdx.x == 0) {
+            if (q1 >= 0) {
+                S.pl[s1] = q1;
+                S.pc[s1] = j;
+                S.sidx[q1] = s1;
+                S.cp[s1] = cprod;
+            }
+            if (q2 >= 0) {
+                S.pl[s2] = q2;
+                S.pc[s2] = j + 1;
+                S.sidx[q2] = s2;
+                S.cp[s2] = q1 >= 0 ? lz_mul(cprod, d1, L) : cprod;
+            }
+        }
+        // Updates are computed for whole registers and kept by a select (no
+        // per-lane branches), pivot 1 on every register before pivot 2, so the
+        // independent FP64 chains of the registers overlap.  Leaf columns come
+        // first: the next pair's owner posts right after them.
+        {
+            double x[4], u[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) x[k] = v[k];
+            if (q1 >= 0) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) u[k] = prow(x[k], q1);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int c = colof(k);
+                    const int cmax = 2 * (8 * (k >> 1) + 4 + wave) + (k & 1);
+                    if (cmax > j) {  // wave-uniform
+                        const double y = lz_ff(d1, x[k], f1, u[k], L);
+                        x[k] = (c > j && c < a.wl && r != q1) ? y : x[k];
+                    }
+                }
+            }
+            if (q2 >= 0) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) u[k] = prow(x[k], q2);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int c = colof(k);
+                    const int cmax = 2 * (8 * (k >> 1) + 4 + wave) + (k & 1);
+                    if (cmax > j + 1) {
+                        const double y = lz_ff(d2, x[k], f2, u[k], L);
+                        x[k] = (c > j + 1 && c < a.wl && r != q2) ? y : x[k];
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = x[k];
+        }
+        if (q1 >= 0) chosen |= 1ull << q1;
+        if (q2 >= 0) chosen |= 1ull << q2;
+        if (P + 1 < npairs && wave == ((P + 1) & 3)) detect(P + 1);
+        // transform columns: pivot 1 at column s1, then pivot 2 at column s2
+        {
+            double x[4], u[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) x[k] = T[k];
+            if (q1 >= 0) {
+                const double inj = -lz_mul(f1, cprod, L);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) u[k] = prow(x[k], q1);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int c = colof(k);
+                    const int cmin = 2 * (8 * (k >> 1) + wave) + (k & 1);
+                    if (cmin <= s1) {
+                        const double y = lz_ff(d1, x[k], f1, u[k], L);
+                        x[k] = c < s1 ? (r != q1 ? y : x[k]) : (c == s1 ? (r == q1 ? cprod : inj) : x[k]);
+                    }
+                }
+            }
+            if (q2 >= 0) {
+                const double cp2 = q1 >= 0 ? lz_mul(cprod, d1, L) : cprod;
+                const double inj = -lz_mul(f2, cp2, L);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) u[k] = prow(x[k], q2);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int c = colof(k);
+                    const int cmin = 2 * (8 * (k >> 1) + wave) + (k & 1);
+                    if (cmin <= s2) {
+                        const double y = lz_ff(d2, x[k], f2, u[k], L);
+                        x[k] = c < s2 ? (r != q2 ? y : x[k]) : (c == s2 ? (r == q2 ? cp2 : inj) : x[k]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) T[k] = x[k];
+        }
+        if (q1 >= 0) cprod = lz_mul(cprod, d1, L);
+        if (q2 >= 0) cprod = lz_mul(cprod, d2, L);
+        t = s2 + (q2 >= 0);
+    }
+    if (threadIdx.x == 0) {
+        S.t = t;
+        S.total = cprod;
+    }
+    __syncthreads();
+    if (threadIdx.x < t) S.basis[threadIdx.x] = S.pos[S.pl[threadIdx.x]];
+    __syncthreads();
+}
+
 // Final node: P^-1, the leaf result, the pivot bookkeeping, and a copy of the
 // pivot rows over the columns the leaf updates (the product overwrites them).
+// R = 32: the pair layout of node_gj_pairs; R = 64: the layout of node_gj<64>.
 template <int R>
 __device__ __forceinline__ void publish(const SelArgs& a, Sel& S, const double T[8], bool save_rows,
                                         const Lazy& L) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int h = R == 32 ? lane >> 5 : 0;
     const int r = R == 32 ? lane & 31 : lane;
+    auto colof = [&](int k) {
+        return R == 32 ? 2 * (8 * (k >> 1) + 4 * h + wave) + (k & 1) : Lay<64>::col(wave, 0, k);
+    };
     const int t = S.t;
     if (threadIdx.x < t) S.rows[threadIdx.x] = a.cand[S.basis[threadIdx.x]];
     __syncthreads();
@@ -302,8 +493,8 @@ __device__ __forceinline__ void publish(const SelArgs& a, Sel& S, const double T
     if (s >= 0) {
         const double dinv = lz_mul(S.cp[s], S.total, L);
 #pragma unroll
-        for (int k = 0; k < Lay<R>::kRegs; ++k) {
-            const int c = Lay<R>::col(wave, h, k);
+        for (int k = 0; k < (R == 32 ? 4 : 8); ++k) {
+            const int c = colof(k);
             if (c < t) a.out->pinv[s * 32 + c] = (uint32_t)lz_canon(lz_mul(dinv, T[k], L), L);
         }
     }
@@ -421,7 +612,7 @@ __global__ __launch_bounds__(kSelThreads, first ? 4 : 1) void leaf_select_kernel
     __syncthreads();
     int level = 0, k = g, nodes = G;
     double v[8], T[8];
-    node_gj<32>(a, S, v, T, L);
+    node_gj_pairs(a, S, v, T, L);
     if (first) {
         if (S.t == a.wl || nodes == 1) publish<32>(a, S, T, false, L);
         return;  // otherwise the tree launch decides
@@ -434,7 +625,7 @@ __global__ __launch_bounds__(kSelThreads, first ? 4 : 1) void leaf_select_kernel
                 if (threadIdx.x < t) S.pos[threadIdx.x] = S.basis[threadIdx.x];
                 if (threadIdx.x == 0) S.nrows = t;
                 __syncthreads();
-                node_gj<32>(a, S, v, T, L);
+                node_gj_pairs(a, S, v, T, L);
                 regs = 32;
             }
             // the tree launch leaves Y to the product, which needs the rows as selected
