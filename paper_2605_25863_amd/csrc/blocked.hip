@@ -681,6 +681,9 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
     hipStream_t side = nullptr;
     hipEvent_t ev_t1 = nullptr, ev_t2 = nullptr;
     const bool lookahead = overlap && !fp64 && n > panel;
+    // Y built by the selection's second launch when the first one decided the
+    // leaf (faster than a rebuild in every product workgroup)
+    const bool select_y = true;
     hipError_t e = hipSuccess;
     if (lookahead) {
         e = side_stream(&side);
@@ -706,7 +709,7 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
             const int64_t N = (int64_t)wj + wl;
             lt.before(LINAC_KERNEL_SELECT);
             e = leaf_select(w, b.leaf, b.PR.M, b.PR.ld, l0, wl, wj, j0 + l0, parity, N,
-                            fp64 ? nullptr : b.Yfrag, s);
+                            fp64 || !select_y ? nullptr : b.Yfrag, !fp64, s);
             lt.after();
             if (e != hipSuccess) break;
             if (fp64) {

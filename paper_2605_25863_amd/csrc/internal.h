@@ -157,11 +157,12 @@ hipError_t leaf_init(const LeafState& ls, int32_t m, hipStream_t s);
 // of PR columns the leaf updates (from l0), wj = the panel width.  With yfrag
 // non-NULL it also builds Y = P^-1 R over those columns as int8 B fragments
 // (one k-block, 4 digit planes per 32 columns) when the first chunk of
-// candidates already decides the leaf, setting out->yready; otherwise it saves
-// the pivot rows in ls.rsave (row s = pivot s) for the product to form Y.
+// candidates already decides the leaf, setting out->yready.  With save_rows,
+// every result that leaves Y to the product (out->yready = 0) also saves the
+// pivot rows over those columns in ls.rsave (row s = pivot s).
 hipError_t leaf_select(const PlainArgs& w, const LeafState& ls, const uint32_t* PR, int64_t ldpr,
                        int32_t l0, int32_t wl, int32_t wj, int32_t gcol0, int32_t parity,
-                       int64_t ncopy, int8_t* yfrag, hipStream_t s);
+                       int64_t ncopy, int8_t* yfrag, bool save_rows, hipStream_t s);
 // Operands of the FP64 leaf product over PR columns [l0, l0 + N): the B operand
 // Y = P^-1 R and the A operand (multipliers) in the layout of the FP64 product
 // kernel (16 x 16 blocks with 8 k-blocks of 4); also compacts the candidate

@@ -116,6 +116,7 @@ struct SelArgs {
     int64_t ncopy;
     int32_t wj;      // panel width (the transform block starts at PR column wj)
     int8_t* yfrag;   // int8 B fragments of Y, or NULL
+    int32_t save_rows;  // keep a copy of the pivot rows for the product to rebuild Y from
 };
 
 // Shared memory of the selection kernel.
@@ -276,16 +277,62 @@ __device__ __forceinline__ void node_gj(const SelArgs& a, Sel& S, double v[8], d
 // wave of pair P finds the first column's pivot, applies it to the second
 // column itself, finds the second pivot and posts both; every wave then applies
 // the two pivots in order.  Same results as one column per step.
+// Column of register k in the pair layout (see node_gj_pairs).
+__device__ __forceinline__ int pair_col(int k, int h, int wave) {
+    return 2 * (8 * (k >> 1) + 4 * h + wave) + (k & 1);
+}
+
+// The pivot row's entry in this lane's column of a pair-layout register.
+__device__ __forceinline__ double pair_row(double x, int q, int h) {
+    const double u0 = readlane_d(x, q), u1 = readlane_d(x, 32 + q);
+    return h ? u1 : u0;
+}
+
+// One pivot (row q, value d, column values f) on the leaf registers K0..3,
+// columns after jj: straight-line code over whole registers, the result kept
+// per lane by a select, so the registers' FP64 chains interleave.
+template <int K0>
+__device__ __forceinline__ void pair_leaf_pivot(double x[4], int q, double d, double f, int jj, int h,
+                                                int wave, int r, int wl, const Lazy& L) {
+    double u[4];
+#pragma unroll
+    for (int k = K0; k < 4; ++k) u[k] = pair_row(x[k], q, h);
+#pragma unroll
+    for (int k = K0; k < 4; ++k) {
+        const int c = pair_col(k, h, wave);
+        const double y = lz_ff(d, x[k], f, u[k], L);
+        x[k] = (c > jj && c < wl && r != q) ? y : x[k];
+    }
+}
+
+// The same pivot on the transform registers 0..K1-1: columns before s are
+// updated, column s receives the pivot's new transform column (cp on the pivot
+// row, inj elsewhere), later columns are still zero.
+template <int K1>
+__device__ __forceinline__ void pair_t_pivot(double x[4], int q, double d, double f, int s, double cp,
+                                             double inj, int h, int wave, int r, const Lazy& L) {
+    double u[4];
+#pragma unroll
+    for (int k = 0; k < K1; ++k) u[k] = pair_row(x[k], q, h);
+#pragma unroll
+    for (int k = 0; k < K1; ++k) {
+        const int c = pair_col(k, h, wave);
+        const double y = lz_ff(d, x[k], f, u[k], L);
+        x[k] = c < s ? (r != q ? y : x[k]) : (c == s ? (r == q ? cp : inj) : x[k]);
+    }
+}
+
 __device__ __forceinline__ void node_gj_pairs(const SelArgs& a, Sel& S, double v[8], double T[8],
                                               const Lazy& L) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // wave-uniform by construction; readfirstlane lets the compiler see it, so
+    // conditions on it stay scalar branches instead of exec-masked regions
+    const int lane = threadIdx.x & 63, wave = uniform(threadIdx.x >> 6);
     const int h = lane >> 5, r = lane & 31;
     const int nrows = S.nrows;
     const int32_t row = r < nrows ? a.cand[S.pos[r]] : -1;
-    auto colof = [&](int reg) { return 2 * (8 * (reg >> 1) + 4 * h + wave) + (reg & 1); };
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        const int c = colof(k);
+        const int c = pair_col(k, h, wave);
         v[k] = (row >= 0 && c < a.wl) ? (double)a.PR[(int64_t)row * a.ldpr + a.l0 + c] : 0.0;
         T[k] = 0.0;
     }
@@ -294,10 +341,6 @@ __device__ __forceinline__ void node_gj_pairs(const SelArgs& a, Sel& S, double v
     unsigned long long chosen = 0;  // rows of this node (bits 0..31)
     int t = 0;
     double cprod = 1.0;
-    auto prow = [&](double x, int q) {  // the pivot row's entry of this lane's column
-        const double u0 = readlane_d(x, q), u1 = readlane_d(x, 32 + q);
-        return h ? u1 : u0;
-    };
     auto first_nz = [&](double x, int hh, unsigned long long excl) {
         const double ax = fabs(x);  // lazy value in (-3p, 3p): zero iff |x| is 0, p or 2p
         const unsigned long long nz = __ballot(!(ax == 0.0 || ax == L.p || ax == 2.0 * L.p));
@@ -364,82 +407,32 @@ __device__ __forceinline__ void node_gj_pairs(const SelArgs& a, Sel& S, double v
                 S.cp[s2] = q1 >= 0 ? lz_mul(cprod, d1, L) : cprod;
             }
         }
-        // Updates are computed for whole registers and kept by a select (no
-        // per-lane branches), pivot 1 on every register before pivot 2, so the
-        // independent FP64 chains of the registers overlap.  Leaf columns come
-        // first: the next pair's owner posts right after them.
-        {
-            double x[4], u[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) x[k] = v[k];
-            if (q1 >= 0) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) u[k] = prow(x[k], q1);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int c = colof(k);
-                    const int cmax = 2 * (8 * (k >> 1) + 4 + wave) + (k & 1);
-                    if (cmax > j) {  // wave-uniform
-                        const double y = lz_ff(d1, x[k], f1, u[k], L);
-                        x[k] = (c > j && c < a.wl && r != q1) ? y : x[k];
-                    }
-                }
-            }
-            if (q2 >= 0) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) u[k] = prow(x[k], q2);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int c = colof(k);
-                    const int cmax = 2 * (8 * (k >> 1) + 4 + wave) + (k & 1);
-                    if (cmax > j + 1) {
-                        const double y = lz_ff(d2, x[k], f2, u[k], L);
-                        x[k] = (c > j + 1 && c < a.wl && r != q2) ? y : x[k];
-                    }
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) v[k] = x[k];
+        // Leaf columns first (the next pair's owner posts right after them),
+        // pivot 1 on every register before pivot 2.  Registers 0 and 1 hold
+        // columns below 16 only, registers 2 and 3 columns from 16 on, so the
+        // live registers follow from a scalar test.
+        if (q1 >= 0) {
+            if (j < 16) pair_leaf_pivot<0>(v, q1, d1, f1, j, h, wave, r, a.wl, L);
+            else pair_leaf_pivot<2>(v, q1, d1, f1, j, h, wave, r, a.wl, L);
+        }
+        if (q2 >= 0) {
+            if (j + 1 < 16) pair_leaf_pivot<0>(v, q2, d2, f2, j + 1, h, wave, r, a.wl, L);
+            else pair_leaf_pivot<2>(v, q2, d2, f2, j + 1, h, wave, r, a.wl, L);
         }
         if (q1 >= 0) chosen |= 1ull << q1;
         if (q2 >= 0) chosen |= 1ull << q2;
         if (P + 1 < npairs && wave == ((P + 1) & 3)) detect(P + 1);
         // transform columns: pivot 1 at column s1, then pivot 2 at column s2
-        {
-            double x[4], u[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) x[k] = T[k];
-            if (q1 >= 0) {
-                const double inj = -lz_mul(f1, cprod, L);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) u[k] = prow(x[k], q1);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int c = colof(k);
-                    const int cmin = 2 * (8 * (k >> 1) + wave) + (k & 1);
-                    if (cmin <= s1) {
-                        const double y = lz_ff(d1, x[k], f1, u[k], L);
-                        x[k] = c < s1 ? (r != q1 ? y : x[k]) : (c == s1 ? (r == q1 ? cprod : inj) : x[k]);
-                    }
-                }
-            }
-            if (q2 >= 0) {
-                const double cp2 = q1 >= 0 ? lz_mul(cprod, d1, L) : cprod;
-                const double inj = -lz_mul(f2, cp2, L);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) u[k] = prow(x[k], q2);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int c = colof(k);
-                    const int cmin = 2 * (8 * (k >> 1) + wave) + (k & 1);
-                    if (cmin <= s2) {
-                        const double y = lz_ff(d2, x[k], f2, u[k], L);
-                        x[k] = c < s2 ? (r != q2 ? y : x[k]) : (c == s2 ? (r == q2 ? cp2 : inj) : x[k]);
-                    }
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) T[k] = x[k];
+        if (q1 >= 0) {
+            const double inj = -lz_mul(f1, cprod, L);
+            if (s1 < 16) pair_t_pivot<2>(T, q1, d1, f1, s1, cprod, inj, h, wave, r, L);
+            else pair_t_pivot<4>(T, q1, d1, f1, s1, cprod, inj, h, wave, r, L);
+        }
+        if (q2 >= 0) {
+            const double cp2 = q1 >= 0 ? lz_mul(cprod, d1, L) : cprod;
+            const double inj = -lz_mul(f2, cp2, L);
+            if (s2 < 16) pair_t_pivot<2>(T, q2, d2, f2, s2, cp2, inj, h, wave, r, L);
+            else pair_t_pivot<4>(T, q2, d2, f2, s2, cp2, inj, h, wave, r, L);
         }
         if (q1 >= 0) cprod = lz_mul(cprod, d1, L);
         if (q2 >= 0) cprod = lz_mul(cprod, d2, L);
@@ -614,7 +607,7 @@ __global__ __launch_bounds__(kSelThreads, first ? 4 : 1) void leaf_select_kernel
     double v[8], T[8];
     node_gj_pairs(a, S, v, T, L);
     if (first) {
-        if (S.t == a.wl || nodes == 1) publish<32>(a, S, T, false, L);
+        if (S.t == a.wl || nodes == 1) publish<32>(a, S, T, a.save_rows && !a.yfrag, L);
         return;  // otherwise the tree launch decides
     }
     int regs = 32;  // v, T hold the Gauss-Jordan of the node's basis rows in this layout (0: none)
@@ -629,7 +622,7 @@ __global__ __launch_bounds__(kSelThreads, first ? 4 : 1) void leaf_select_kernel
                 regs = 32;
             }
             // the tree launch leaves Y to the product, which needs the rows as selected
-            const bool save_rows = !first && a.yfrag != nullptr;
+            const bool save_rows = a.save_rows != 0;
             if (regs == 32) publish<32>(a, S, T, save_rows, L);
             else publish<64>(a, S, T, save_rows, L);
             return;
@@ -929,7 +922,7 @@ hipError_t leaf_init(const LeafState& ls, int32_t m, hipStream_t s) {
 
 hipError_t leaf_select(const PlainArgs& w, const LeafState& ls, const uint32_t* PR, int64_t ldpr,
                        int32_t l0, int32_t wl, int32_t wj, int32_t gcol0, int32_t parity,
-                       int64_t ncopy, int8_t* yfrag, hipStream_t s) {
+                       int64_t ncopy, int8_t* yfrag, bool save_rows, hipStream_t s) {
     SelArgs a;
     a.w = w;
     a.PR = PR;
@@ -950,6 +943,7 @@ hipError_t leaf_select(const PlainArgs& w, const LeafState& ls, const uint32_t* 
     a.ncopy = ncopy;
     a.wj = wj;
     a.yfrag = yfrag;
+    a.save_rows = save_rows ? 1 : 0;
     const int64_t nyb = ceil_div(ncopy, 32);
     const unsigned grid = (unsigned)(ls.gmax > nyb ? ls.gmax : nyb);
     hipLaunchKernelGGL(leaf_select_kernel<true>, dim3(1), dim3(kSelThreads), 0, s, a);
