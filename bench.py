@@ -23,9 +23,19 @@ library records a HIP event pair around every hot-kernel launch on its stream
   products      multiply-add (16 limb products, 2 ops each), peak 5000 TOP/s
                 (the leaves' pivot selections and operand builds are listed
                 by time only);
-  batched       vector ALU: one Shoup mulmod-subtract = 17 VALU issue slots
-                (3 quarter-rate 32-bit multiplies + 5 simple ops), so the chip
-                peak is 256 CU x 64 lanes x 2.4 GHz / 17 = 2.31e12 updates/s.
+  select        vector ALU (FP64): the leaf's pivot selection eliminates its
+                first chunk of 32 candidate rows fraction-free, one lazy
+                multiply-subtract pair (13 FP64 instructions) per element
+                update; peak 256 CU x 64 lanes x 2.4 GHz / 13 = 3.02e12
+                updates/s.  One workgroup runs the chain of 32 dependent
+                pivots, so this kernel is bound by that chain's latency, far
+                below the chip's ALU peak;
+  batched       HBM-bound: every pivot step of a system streams the system
+                (8 algorithmic bytes per element update, as for the plain
+                step; the thousand resident systems overflow L2 and MALL),
+                peak 8000 GB/s; its vector-ALU view (one Shoup mulmod-subtract
+                = 17 VALU issue slots, chip peak 256 CU x 64 lanes x 2.4 GHz /
+                17 = 2.31e12 updates/s) is reported beside it.
 """
 
 from __future__ import annotations
@@ -46,6 +56,7 @@ HBM_PEAK_GBS = 8000.0
 I8_PEAK_TOPS = 5000.0
 FP64_PEAK_TFLOPS = 78.6
 VALU_UPDATES_PEAK = 256 * 64 * 2.4e9 / 17.0  # updates/s
+SELECT_UPDATES_PEAK = 256 * 64 * 2.4e9 / 13.0  # lazy FP64 updates/s
 LEAF = 32
 PROFILES = os.path.join(ROOT, "profiles")
 
@@ -81,6 +92,20 @@ def blocked_work(m: int, n: int, ncols: int, panel: int):
             leaf_macs += m * (wj + wl) * wl
         trail_macs += m * (ncols - j0 - wj) * wj
     return leaf_macs, trail_macs
+
+
+def select_updates(n: int, panel: int) -> int:
+    """Element updates of the leaves' first-chunk eliminations on a full-rank
+    system: a leaf of wl columns takes wl pivots in a chunk of 32 rows, and
+    each pivot rewrites the 31 other rows over the wl - 1 leaf columns after it
+    and the transform columns before it (wl - 1 in all)."""
+    total = 0
+    for j0 in range(0, n, panel):
+        wj = min(panel, n - j0)
+        for l0 in range(0, wj, LEAF):
+            wl = min(LEAF, wj - l0)
+            total += wl * 31 * (wl - 1)
+    return total
 
 
 def kernel_source_hash(names) -> str:
@@ -120,7 +145,7 @@ def cpu_baseline(target_s: float = 15.0):
     t1 = run(1024)
     rate = gj_updates(1024, 1024, 1040) / t1
     n = 1024
-    for cand in (1536, 2048, 2560, 3072, 3584, 4096):
+    for cand in (1536, 2048, 2560, 3072, 3584, 4096, 4608, 5120, 5632, 6144):
         if gj_updates(cand, cand, cand + 16) / rate <= target_s:
             n = cand
     t = run(n) if n != 1024 else t1
@@ -134,13 +159,10 @@ def cpu_baseline(target_s: float = 15.0):
 PATHS = {"auto": 0, "plain": 1, "int8": 2, "fp64": 3}
 
 
-def _resolved_path(lx, m, n, path_name):
-    """The path AUTO takes for this shape (the library decides by size)."""
-    if path_name != "auto":
-        return path_name
-    auto = lx.solve_workspace_bytes(m, n, 0, lx.PATH_AUTO)
-    plain = lx.solve_workspace_bytes(m, n, 0, lx.PATH_PLAIN)
-    return "plain" if auto == plain else "int8"
+def _resolved_plan(lx, m, n, path_name, panel):
+    """(path name, panel width) the library takes for this shape and request."""
+    pth, pw = lx.plan(m, n, PATHS[path_name], panel)
+    return {v: k for k, v in PATHS.items() if k != "auto"}[pth], pw
 
 
 def _rooflines(kinds, m, n, ncols, path_name, panel, src_hash, workload):
@@ -158,19 +180,34 @@ def _rooflines(kinds, m, n, ncols, path_name, panel, src_hash, workload):
         leaf_macs, trail_macs = blocked_work(m, n, ncols, panel)
         per_mac_ops, peak, unit = (32.0, I8_PEAK_TOPS, "TOP/s") if path_name == "int8" else \
             (2.0, FP64_PEAK_TFLOPS, "TFLOP/s")
-        for kind, macs, kname in (("leaf_product", leaf_macs, "gemm (leaf transform)"),
-                                  ("trail_product", trail_macs, "gemm (trailing update)")):
+        int8 = path_name == "int8"
+        for kind, macs, kname in (("leaf_product", leaf_macs,
+                                   "leaf_product_i8_kernel (leaf transform)" if int8
+                                   else "gemm_f64_kernel (leaf transform)"),
+                                  ("trail_product", trail_macs,
+                                   ("gemm_i8_kernel" if int8 else "gemm_f64_kernel")
+                                   + " (trailing update)")):
             if kind in kinds:
                 nl, ms = kinds[kind]
-                out[kind] = {"bound": "mfma", "kernel": ("gemm_i8_kernel " if path_name == "int8"
-                                                         else "gemm_f64_kernel ") + kname,
+                out[kind] = {"bound": "mfma", "kernel": kname,
                              "launches": nl, "avg_launch_us": ms * 1e3 / nl,
                              "algorithmic_ops_per_launch": per_mac_ops * macs / nl,
                              "achieved": per_mac_ops * macs / (ms / 1e3) / 1e12, "peak": peak,
                              "unit": unit}
+        if "select" in kinds:
+            nl, ms = kinds["select"]
+            upd = select_updates(n, panel)
+            out["select"] = {"bound": "alu", "kernel": "leaf_select_kernel (first chunk, then "
+                                                       "the tree or Y launch)",
+                             "limiter": "latency of the dependent pivot chain in one workgroup",
+                             "launches": nl, "avg_launch_us": ms * 1e3 / nl,
+                             "algorithmic_updates_per_launch": upd / nl,
+                             "achieved": upd / (ms / 1e3) / 1e9,
+                             "peak": SELECT_UPDATES_PEAK / 1e9, "unit": "Gupdates/s"}
     for name, r in out.items():
-        r["frac"] = round(r["achieved"] / r["peak"], 4)
-        r["achieved"] = round(r["achieved"], 1)
+        r["frac"] = float(f"{r['achieved'] / r['peak']:.3g}")
+        r["achieved"] = float(f"{r['achieved']:.4g}")
+        r["peak"] = float(f"{r['peak']:.4g}")
         r["avg_launch_us"] = round(r["avg_launch_us"], 3)
         r["total_ms"] = round(kinds[name][1], 3)
         r["traffic"] = measured_traffic(r["kernel"].split()[0], workload, src_hash)
@@ -194,7 +231,7 @@ def bench_dense(args):
            torch.empty(min(m, n), dtype=torch.int32, device=dev),
            torch.empty(k, dtype=torch.uint8, device=dev))
     stream = torch.cuda.current_stream()
-    path_name = _resolved_path(lx, m, n, args.path)
+    path_name, panel = _resolved_plan(lx, m, n, args.path, args.panel)
     path = PATHS[path_name]
     ws = torch.empty(lx.solve_workspace_bytes(m, n, k, path, args.panel), dtype=torch.uint8,
                      device=dev)
@@ -222,7 +259,6 @@ def bench_dense(args):
     lx.solve(At, Bt, p, path=path, out=out, workspace=ws, stream=stream, panel_width=args.panel,
              per_launch=lt)
     kinds = lt.by_kind()
-    panel = args.panel or 256
     src_hash = kernel_source_hash(["plain.hip", "blocked.hip", "leaf.hip", "field.h"])
     roofs = _rooflines(kinds, m, n, n + k, path_name, panel, src_hash, args.config)
     dominant = max(roofs, key=lambda name: roofs[name]["total_ms"]) if roofs else None
@@ -243,7 +279,8 @@ def bench_dense(args):
         "data": "synthetic (seeded uniform residues)",
         "config": {"workload": f"{args.config}: one dense n={n} system, {k} right-hand sides, "
                                f"p={p}, {path_name} path", "n": n, "k": k, "p": p,
-                   "path": path_name, "seed": {"c1": 1, "c2": 2, "c3": 3}[args.config]},
+                   "path": path_name, "panel": panel,
+                   "seed": {"c1": 1, "c2": 2, "c3": 3}[args.config]},
         "roofline": roofs.get(dominant),
         "rooflines": roofs,
         "kernel_ms_by_kind": {kk: round(v[1], 3) for kk, v in kinds.items()},
@@ -294,11 +331,20 @@ def bench_batched(args):
            "config": {"workload": "c4: 4096 systems, n~U{32..512}, k~U{1..8}, a seeded 31-bit "
                                   "prime each, 205 rank deficient"},
            "gop_per_s": round(ops / (ms_per_step / 1e3) / 1e9, 2),
-           "roofline": {"bound": "alu", "kernel": "batched_kernel", "launches": nl,
+           # each pivot step streams its system through the memory side (the
+           # resident systems overflow L2 and MALL): 8 algorithmic bytes per
+           # element update, as for the plain step; the ALU view beside it
+           "roofline": {"bound": "hbm", "kernel": "batched_kernel", "launches": nl,
                         "avg_launch_us": round(kms * 1e3 / nl, 3),
-                        "achieved": round(achieved / 1e9, 2),
-                        "peak": round(VALU_UPDATES_PEAK / 1e9, 1), "unit": "Gupdates/s",
-                        "frac": round(achieved / VALU_UPDATES_PEAK, 4), "traffic": None}}
+                        "algorithmic_bytes_per_launch": 8.0 * upd / nl,
+                        "achieved": round(8.0 * achieved / 1e9, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(8.0 * achieved / 1e9 / HBM_PEAK_GBS, 4),
+                        "traffic": measured_traffic("batched_kernel", "c4",
+                                                    kernel_source_hash(["batched.hip", "field.h"])),
+                        "alu": {"achieved": round(achieved / 1e9, 2),
+                                "peak": round(VALU_UPDATES_PEAK / 1e9, 1), "unit": "Gupdates/s",
+                                "frac": round(achieved / VALU_UPDATES_PEAK, 4)}}}
     if not args.no_plain_compare:
         # the same systems, one linac_solve each on the plain path
         wss = []

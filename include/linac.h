@@ -91,6 +91,17 @@ enum {
     LINAC_KERNEL_OPERANDS = 6       /* blocked: building the MFMA operands of a product */
 };
 
+/*
+ * The plan a call on an m x n system would follow: *path receives the path
+ * (LINAC_PATH_PLAIN, _BLOCKED_INT8 or _BLOCKED_FP64; AUTO resolved by size and
+ * the tuning table) and *panel the panel width of a blocked path (0 for the
+ * plain path).  Both are HOST pointers.  Depends only on the shape and opts
+ * (never on p or the data), so it matches the workspace queries.  Returns
+ * LINAC_E_INVALID_ARG for a NULL pointer or a negative size, and for a panel
+ * width outside 32..512 or not a multiple of 32.
+ */
+linac_status linac_plan(int64_t m, int64_t n, const linac_opts* opts, int* path, int* panel);
+
 /* Workspace (bytes) needed by linac_rref for an m x n matrix. */
 linac_status linac_rref_workspace(int64_t m, int64_t n, const linac_opts* opts, size_t* bytes);
 
@@ -156,7 +167,9 @@ linac_status linac_solve_batched_workspace(const linac_system* sys, int32_t coun
  * extension).  `sys` is a HOST array read during the call only.  The library
  * uploads the descriptors into ws and launches a graph that it captured for
  * this (ws, plan) pair on first use, replaying it on later calls.  Per system the
- * results equal those of linac_solve.
+ * results equal those of linac_solve.  Each system must fit one workgroup's
+ * bookkeeping: m <= 1024 and n + k <= 2048, else LINAC_E_UNSUPPORTED (before
+ * any device work; larger systems go through linac_solve).
  */
 linac_status linac_solve_batched(const linac_system* sys, int32_t count, void* ws,
                                  size_t ws_bytes, const linac_opts* opts, hipStream_t s);

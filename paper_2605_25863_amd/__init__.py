@@ -91,6 +91,8 @@ def _load():
     vp, i64, u32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t
     optp = ctypes.POINTER(_Opts)
     szp = ctypes.POINTER(ctypes.c_size_t)
+    lib.linac_plan.argtypes = [i64, i64, optp, ctypes.POINTER(ctypes.c_int),
+                               ctypes.POINTER(ctypes.c_int)]
     lib.linac_rref_workspace.argtypes = [i64, i64, optp, szp]
     lib.linac_rref.argtypes = [vp, i64, i64, i64, u32, vp, vp, vp, sz, optp, vp]
     lib.linac_solve_workspace.argtypes = [i64, i64, i64, optp, szp]
@@ -103,7 +105,7 @@ def _load():
     lib.linac_check_prime.argtypes = [u32]
     lib.linac_status_string.restype = ctypes.c_char_p
     lib.linac_status_string.argtypes = [ctypes.c_int]
-    for name in ("linac_rref_workspace", "linac_rref", "linac_solve_workspace", "linac_solve",
+    for name in ("linac_plan", "linac_rref_workspace", "linac_rref", "linac_solve_workspace", "linac_solve",
                  "linac_solve_batched_workspace", "linac_solve_batched", "linac_load_tuning",
                  "linac_check_prime", "linac_version", "linac_last_hip_error"):
         getattr(lib, name).restype = ctypes.c_int
@@ -125,6 +127,16 @@ def load_tuning(json_text):
     lib = _load()
     _check(lib.linac_load_tuning(None if json_text is None else json_text.encode()),
            "linac_load_tuning")
+
+
+def restore_tuning():
+    """Back to the table loaded at import: the shipped tuning file if there is
+    one, else the built-in defaults."""
+    if os.path.exists(TUNING_FILE):
+        with open(TUNING_FILE) as f:
+            load_tuning(f.read())
+    else:
+        load_tuning(None)
 
 
 def check_prime(p: int) -> int:
@@ -337,6 +349,16 @@ def solve(A, B, p: int, *, path: int = PATH_AUTO, validate: bool = False, verbos
                 pivots.cpu().numpy()[: int(rank.item())].astype(np.int64),
                 cons.cpu().numpy().astype(np.uint8))
     return X, rank, pivots, cons
+
+
+def plan(m: int, n: int, path: int = PATH_AUTO, panel_width: int = 0):
+    """(path, panel width) a call on an m x n system takes: AUTO resolved by
+    size and the tuning table; panel 0 on the plain path (linac_plan)."""
+    lib = _load()
+    o = _opts(path, panel_width)
+    pth, pw = ctypes.c_int(), ctypes.c_int()
+    _check(lib.linac_plan(m, n, ctypes.byref(o), ctypes.byref(pth), ctypes.byref(pw)), "plan")
+    return int(pth.value), int(pw.value)
 
 
 def rref_workspace_bytes(m: int, n: int, path: int = PATH_AUTO, panel_width: int = 0) -> int:

@@ -357,6 +357,18 @@ const char* linac_status_string(linac_status st) {
 
 linac_status linac_check_prime(uint32_t p) { return check_field(p); }
 
+linac_status linac_plan(int64_t m, int64_t n, const linac_opts* opts, int* path, int* panel) {
+    if (!path || !panel || m < 0 || n < 0) return LINAC_E_INVALID_ARG;
+    const int pth = choose_path(opts, m, n);
+    if (pth != LINAC_PATH_PLAIN && pth != LINAC_PATH_BLOCKED_INT8 && pth != LINAC_PATH_BLOCKED_FP64)
+        return LINAC_E_UNSUPPORTED;
+    const int32_t w = pth == LINAC_PATH_PLAIN ? 0 : panel_width(opts, m, n);
+    if (pth != LINAC_PATH_PLAIN && !panel_ok(w)) return LINAC_E_INVALID_ARG;
+    *path = pth;
+    *panel = w;
+    return LINAC_OK;
+}
+
 linac_status linac_rref_workspace(int64_t m, int64_t n, const linac_opts* opts, size_t* bytes) {
     if (!bytes || m < 0 || n < 0) return LINAC_E_INVALID_ARG;
     if (!size_ok(m, n, 0)) return LINAC_E_NOMEM;

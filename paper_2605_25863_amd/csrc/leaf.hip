@@ -9,12 +9,15 @@
 // gives its pivot columns, and the leaf is reduced as one block:
 //
 //   select    the candidate rows (eligible rows in row order) are cut into
-//             chunks of 64.  One workgroup per chunk runs Gauss-Jordan on its
+//             chunks of 32.  One workgroup per chunk runs Gauss-Jordan on its
 //             rows' leaf values (registers + LDS) and keeps a basis of at most
-//             32 rows.  Bases merge pairwise up a binary tree; the second of two
+//             32 rows.  Bases merge pairwise up a binary tree (a merge
+//             eliminates the two bases' up to 64 rows); the second of two
 //             siblings to finish does the merge.  A node that covers a prefix of
 //             the candidates and has full rank, or the root, is final.  With
-//             dense data the first chunk already has full rank.
+//             dense data the first chunk already has full rank, so a first
+//             launch runs that chunk alone and publishes it when it decides the
+//             leaf; the second launch then builds Y instead of the tree.
 //   operands  Y = P^-1 R, where P is the pivot rows' values at the pivot
 //             columns and R those rows over the columns to update (with the
 //             implicit 1 of each new pivot in the panel's transform block), and

@@ -8,6 +8,7 @@ prime, 16 right-hand sides):
   * the plain path against the blocked int8 path at growing n, to find the
     crossover "blocked_min";
   * the blocked path at each candidate panel width, per size bucket ("panel");
+  * the look-ahead switch of the blocked path at the largest size ("lookahead");
   * the batched launch at 1, 2, 4 and 8 resident workgroups per compute unit on
     a batch of uneven systems ("batched_per_cu").
 Every candidate configuration computes the same unique RREF, so the table only
@@ -55,7 +56,7 @@ def tune(quick: bool = False):
     import workloads
 
     lx.load_tuning(None)  # measure from the built-in defaults
-    sizes = (512, 1024, 2048, 4096) if quick else (512, 1024, 2048, 4096, 8192)
+    sizes = (256, 512, 1024, 2048, 4096) if quick else (256, 512, 1024, 2048, 4096, 8192)
     reps = 2 if quick else 3
     report = {"crossover": {}, "panels": {}}
     blocked_min = None
@@ -80,8 +81,20 @@ def tune(quick: bool = False):
               f"{per_panel[best_w] * 1e3:.2f} ms", flush=True)
     # the largest measured size covers everything above it
     rules[-1]["n_max"] = 1 << 30
+    # look-ahead (trailing remainder on a side stream) at the largest size
+    n = sizes[-1]
+    A, B, p = workloads.dense_system(seed=1000 + n, n=n, k=16)
+    At = torch.from_numpy(A.astype(np.int32)).cuda()
+    Bt = torch.from_numpy(B.astype(np.int32)).cuda()
+    per_la = {}
+    for la in (0, 1):
+        lx.load_tuning(json.dumps({"lookahead": la}))
+        per_la[la] = _time_solve(lx, torch, At, Bt, p, lx.PATH_BLOCKED_INT8, rules[-1]["panel"],
+                                 reps)
+        print(f"n={n} lookahead={la}: {per_la[la] * 1e3:.2f} ms", flush=True)
+    lookahead = min(per_la, key=per_la.get)
     # batched: resident workgroups per CU
-    systems = workloads.batched_systems(seed=4, count=512 if quick else 1024)
+    systems = workloads.batched_systems(seed=4, count=512 if quick else 4096)
     prep = lx.prepare_batched(systems)
     per_cu = {}
     for c in (1, 2, 4, 8):
@@ -96,10 +109,10 @@ def tune(quick: bool = False):
         print(f"batched per_cu={c}: {per_cu[c] * 1e3:.2f} ms", flush=True)
     best_cu = min(per_cu, key=per_cu.get)
     table = {"arch": "gfx950", "blocked_min": blocked_min or sizes[-1] * 2,
-             "panel": rules, "batched_per_cu": best_cu,
+             "panel": rules, "batched_per_cu": best_cu, "lookahead": lookahead,
              "measured": {"crossover_s": report["crossover"], "panel_s": report["panels"],
-                          "batched_s": per_cu}}
-    lx.load_tuning(None)
+                          "lookahead_s": per_la, "batched_s": per_cu}}
+    lx.restore_tuning()
     return table
 
 
@@ -111,7 +124,8 @@ def main():
     table = tune(args.quick)
     with open(args.out, "w") as f:
         json.dump(table, f, indent=1)
-    print(json.dumps({k: table[k] for k in ("blocked_min", "panel", "batched_per_cu")}))
+    print(json.dumps({k: table[k] for k in ("blocked_min", "panel", "batched_per_cu",
+                                             "lookahead")}))
 
 
 if __name__ == "__main__":

@@ -161,3 +161,36 @@ def test_tuning_table_parsing(lib):
     assert lib.linac_solve_workspace(4096, 4096, 16, ctypes.byref(opts), ctypes.byref(a)) == OK
     assert a.value == sz.value
     assert lib.linac_load_tuning(None) == OK
+    lx.restore_tuning()
+
+
+def test_plan(lib):
+    """linac_plan reports the path AUTO takes and the panel width, from the
+    caller's options and the tuning table, and rejects what the calls reject."""
+    import json
+    table = {"blocked_min": 2048, "panel": [{"n_max": 1024, "panel": 64},
+                                            {"n_max": 1 << 30, "panel": 384}]}
+    path, panel = ctypes.c_int(), ctypes.c_int()
+
+    def plan(m, n, opts=None):
+        st = lib.linac_plan(m, n, ctypes.byref(opts) if opts else None, ctypes.byref(path),
+                            ctypes.byref(panel))
+        return st, path.value, panel.value
+
+    assert lib.linac_load_tuning(json.dumps(table).encode()) == OK
+    try:
+        assert plan(1500, 1500) == (OK, lx.PATH_PLAIN, 0)
+        assert plan(4096, 5000) == (OK, lx.PATH_BLOCKED_INT8, 384)
+        assert plan(5000, 2048) == (OK, lx.PATH_BLOCKED_INT8, 384)
+        assert plan(800, 900, lx._opts(lx.PATH_BLOCKED_INT8)) == (OK, lx.PATH_BLOCKED_INT8, 64)
+        assert plan(800, 900, lx._opts(lx.PATH_BLOCKED_FP64, 96)) == (OK, lx.PATH_BLOCKED_FP64, 96)
+        assert plan(9000, 9000, lx._opts(lx.PATH_PLAIN, 96)) == (OK, lx.PATH_PLAIN, 0)
+        assert plan(0, 0) == (OK, lx.PATH_PLAIN, 0)
+        assert plan(800, 900, lx._opts(lx.PATH_BLOCKED_INT8, 100))[0] == INVALID
+        assert plan(800, 900, lx._opts(lx.PATH_BLOCKED_INT8, 544))[0] == INVALID
+        assert plan(-1, 5)[0] == INVALID
+        assert lib.linac_plan(5, 5, None, None, ctypes.byref(panel)) == INVALID
+        assert lib.linac_plan(5, 5, None, ctypes.byref(path), None) == INVALID
+        assert plan(5, 5, lx._opts(7))[0] == UNSUP
+    finally:
+        lx.restore_tuning()
