@@ -40,8 +40,10 @@ namespace linac {
 
 namespace {
 
-constexpr int kSelWaves = 4;
+constexpr int kSelWaves = 4;   // the tree launch
 constexpr int kSelThreads = 64 * kSelWaves;
+constexpr int kFirstWaves = 8;  // the first-chunk launch: two waves per SIMD
+constexpr int kFirstThreads = 64 * kFirstWaves;
 constexpr int kChunk = 32;     // candidate rows per first-level tree node
 constexpr int kNodeInts = 64;  // per node: basis size, then its list positions
 
@@ -62,6 +64,43 @@ __device__ __forceinline__ double lz_mul(double a, double b, const Lazy& L) {
 // d v - f u, in (-3p, 3p).
 __device__ __forceinline__ double lz_ff(double d, double v, double f, double u, const Lazy& L) {
     return lz_mul(d, v, L) - lz_mul(f, u, L);
+}
+
+// lz_ff over registers K0..K1-1 with shared d and f, written stage by stage so
+// that the 2 (K1 - K0) independent products are interleaved in the instruction
+// stream: with one wave per SIMD nothing else hides the latency of a dependent
+// chain.  Same operations, same results as lz_ff per register.
+template <int K0, int K1>
+__device__ __forceinline__ void lz_ff_n(double y[4], double d, const double x[4], double f,
+                                        const double u[4], const Lazy& L) {
+    double h1[4], h2[4], l1[4], l2[4], q1[4], q2[4];
+#pragma unroll
+    for (int k = K0; k < K1; ++k) {
+        h1[k] = d * x[k];
+        h2[k] = f * u[k];
+    }
+#pragma unroll
+    for (int k = K0; k < K1; ++k) {
+        q1[k] = h1[k] * L.pinv;
+        q2[k] = h2[k] * L.pinv;
+    }
+#pragma unroll
+    for (int k = K0; k < K1; ++k) {
+        l1[k] = __fma_rn(d, x[k], -h1[k]);
+        l2[k] = __fma_rn(f, u[k], -h2[k]);
+    }
+#pragma unroll
+    for (int k = K0; k < K1; ++k) {
+        q1[k] = floor(q1[k]);
+        q2[k] = floor(q2[k]);
+    }
+#pragma unroll
+    for (int k = K0; k < K1; ++k) {
+        h1[k] = __fma_rn(-q1[k], L.p, h1[k]);
+        h2[k] = __fma_rn(-q2[k], L.p, h2[k]);
+    }
+#pragma unroll
+    for (int k = K0; k < K1; ++k) y[k] = (h1[k] + l1[k]) - (h2[k] + l2[k]);
 }
 
 // The residue in [0, p) of an integer x with |x| < 2^34.
@@ -172,7 +211,7 @@ template <int R>
 __device__ __forceinline__ void node_gj(const SelArgs& a, Sel& S, double v[8], double T[8],
                                         const Lazy& L) {
     typedef Lay<R> Y;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = uniform(threadIdx.x >> 6);
     const int h = R == 32 ? lane >> 5 : 0;
     const int r = R == 32 ? lane & 31 : lane;  // this lane's row within the node
     const int nrows = S.nrows;
@@ -280,53 +319,65 @@ __device__ __forceinline__ void node_gj(const SelArgs& a, Sel& S, double v[8], d
 // wave of pair P finds the first column's pivot, applies it to the second
 // column itself, finds the second pivot and posts both; every wave then applies
 // the two pivots in order.  Same results as one column per step.
-// Column of register k in the pair layout (see node_gj_pairs).
+// Column of register k in the pair layout of W waves (see node_gj_pairs).
+template <int W>
 __device__ __forceinline__ int pair_col(int k, int h, int wave) {
-    return 2 * (8 * (k >> 1) + 4 * h + wave) + (k & 1);
+    return 2 * (2 * W * (k >> 1) + W * h + wave) + (k & 1);
 }
 
-// The pivot row's entry in this lane's column of a pair-layout register.
-__device__ __forceinline__ double pair_row(double x, int q, int h) {
-    const double u0 = readlane_d(x, q), u1 = readlane_d(x, 32 + q);
-    return h ? u1 : u0;
+// The pivot row's entry in this lane's column of a pair-layout register: the
+// value lane 32 h + q holds, fetched through the LDS crossbar (bpaddr = 4 (32 h
+// + q), see pair_bpaddr), two permutes and no vector-ALU work.
+__device__ __forceinline__ double pair_row(double x, int bpaddr) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_ds_bpermute(bpaddr, (int)b);
+    const int hi = __builtin_amdgcn_ds_bpermute(bpaddr, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(uint32_t)lo);
 }
 
-// One pivot (row q, value d, column values f) on the leaf registers K0..3,
+__device__ __forceinline__ int pair_bpaddr(int q) { return (int)(((threadIdx.x & 32) + q) << 2); }
+
+// One pivot (row q, value d, column values f) on the leaf registers K0..K1-1,
 // columns after jj: straight-line code over whole registers, the result kept
 // per lane by a select, so the registers' FP64 chains interleave.
-template <int K0>
+template <int W, int K0, int K1>
 __device__ __forceinline__ void pair_leaf_pivot(double x[4], int q, double d, double f, int jj, int h,
                                                 int wave, int r, int wl, const Lazy& L) {
-    double u[4];
+    double u[4], y[4];
+    const int bp = pair_bpaddr(q);
 #pragma unroll
-    for (int k = K0; k < 4; ++k) u[k] = pair_row(x[k], q, h);
+    for (int k = K0; k < K1; ++k) u[k] = pair_row(x[k], bp);
+    lz_ff_n<K0, K1>(y, d, x, f, u, L);
 #pragma unroll
-    for (int k = K0; k < 4; ++k) {
-        const int c = pair_col(k, h, wave);
-        const double y = lz_ff(d, x[k], f, u[k], L);
-        x[k] = (c > jj && c < wl && r != q) ? y : x[k];
+    for (int k = K0; k < K1; ++k) {
+        const int c = pair_col<W>(k, h, wave);
+        x[k] = (c > jj && c < wl && r != q) ? y[k] : x[k];
     }
 }
 
 // The same pivot on the transform registers 0..K1-1: columns before s are
 // updated, column s receives the pivot's new transform column (cp on the pivot
 // row, inj elsewhere), later columns are still zero.
-template <int K1>
+template <int W, int K1>
 __device__ __forceinline__ void pair_t_pivot(double x[4], int q, double d, double f, int s, double cp,
                                              double inj, int h, int wave, int r, const Lazy& L) {
-    double u[4];
+    double u[4], y[4];
+    const int bp = pair_bpaddr(q);
 #pragma unroll
-    for (int k = 0; k < K1; ++k) u[k] = pair_row(x[k], q, h);
+    for (int k = 0; k < K1; ++k) u[k] = pair_row(x[k], bp);
+    lz_ff_n<0, K1>(y, d, x, f, u, L);
 #pragma unroll
     for (int k = 0; k < K1; ++k) {
-        const int c = pair_col(k, h, wave);
-        const double y = lz_ff(d, x[k], f, u[k], L);
-        x[k] = c < s ? (r != q ? y : x[k]) : (c == s ? (r == q ? cp : inj) : x[k]);
+        const int c = pair_col<W>(k, h, wave);
+        x[k] = c < s ? (r != q ? y[k] : x[k]) : (c == s ? (r == q ? cp : inj) : x[k]);
     }
 }
 
+template <int W>
 __device__ __forceinline__ void node_gj_pairs(const SelArgs& a, Sel& S, double v[8], double T[8],
                                               const Lazy& L) {
+    static_assert(W == 4 || W == 8, "4 or 8 waves");
+    constexpr int NR = 16 / W;  // leaf (and transform) registers per lane
     // wave-uniform by construction; readfirstlane lets the compiler see it, so
     // conditions on it stay scalar branches instead of exec-masked regions
     const int lane = threadIdx.x & 63, wave = uniform(threadIdx.x >> 6);
@@ -334,8 +385,8 @@ __device__ __forceinline__ void node_gj_pairs(const SelArgs& a, Sel& S, double v
     const int nrows = S.nrows;
     const int32_t row = r < nrows ? a.cand[S.pos[r]] : -1;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int c = pair_col(k, h, wave);
+    for (int k = 0; k < NR; ++k) {
+        const int c = pair_col<W>(k, h, wave);
         v[k] = (row >= 0 && c < a.wl) ? (double)a.PR[(int64_t)row * a.ldpr + a.l0 + c] : 0.0;
         T[k] = 0.0;
     }
@@ -354,10 +405,10 @@ __device__ __forceinline__ void node_gj_pairs(const SelArgs& a, Sel& S, double v
     const int npairs = (a.wl + 1) >> 1;
     // owner of pair P: post both pivots (the second column exists iff 2P + 1 < wl)
     auto detect = [&](int P) {
-        const int hp = (P >> 2) & 1, kp = P >> 3;
+        const int hp = (P / W) & 1, kp = P / (2 * W);
         double xa = 0.0, xb = 0.0;  // registers 2 kp and 2 kp + 1, selected arithmetically
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < NR / 2; ++k) {
             xa = __fma_rn(v[2 * k], k == kp ? 1.0 : 0.0, xa);
             xb = __fma_rn(v[2 * k + 1], k == kp ? 1.0 : 0.0, xb);
         }
@@ -414,28 +465,70 @@ __device__ __forceinline__ void node_gj_pairs(const SelArgs& a, Sel& S, double v
         // pivot 1 on every register before pivot 2.  Registers 0 and 1 hold
         // columns below 16 only, registers 2 and 3 columns from 16 on, so the
         // live registers follow from a scalar test.
-        if (q1 >= 0) {
-            if (j < 16) pair_leaf_pivot<0>(v, q1, d1, f1, j, h, wave, r, a.wl, L);
-            else pair_leaf_pivot<2>(v, q1, d1, f1, j, h, wave, r, a.wl, L);
-        }
-        if (q2 >= 0) {
-            if (j + 1 < 16) pair_leaf_pivot<0>(v, q2, d2, f2, j + 1, h, wave, r, a.wl, L);
-            else pair_leaf_pivot<2>(v, q2, d2, f2, j + 1, h, wave, r, a.wl, L);
-        }
-        if (q1 >= 0) chosen |= 1ull << q1;
-        if (q2 >= 0) chosen |= 1ull << q2;
-        if (P + 1 < npairs && wave == ((P + 1) & 3)) detect(P + 1);
-        // transform columns: pivot 1 at column s1, then pivot 2 at column s2
-        if (q1 >= 0) {
-            const double inj = -lz_mul(f1, cprod, L);
-            if (s1 < 16) pair_t_pivot<2>(T, q1, d1, f1, s1, cprod, inj, h, wave, r, L);
-            else pair_t_pivot<4>(T, q1, d1, f1, s1, cprod, inj, h, wave, r, L);
-        }
-        if (q2 >= 0) {
-            const double cp2 = q1 >= 0 ? lz_mul(cprod, d1, L) : cprod;
-            const double inj = -lz_mul(f2, cp2, L);
-            if (s2 < 16) pair_t_pivot<2>(T, q2, d2, f2, s2, cp2, inj, h, wave, r, L);
-            else pair_t_pivot<4>(T, q2, d2, f2, s2, cp2, inj, h, wave, r, L);
+        const bool owner = P + 1 < npairs && wave == (P + 1) % W;
+        if constexpr (W == 4) {
+            if (!owner) {
+                if (q1 >= 0) {
+                    if (j < 16) pair_leaf_pivot<W, 0, 4>(v, q1, d1, f1, j, h, wave, r, a.wl, L);
+                    else pair_leaf_pivot<W, 2, 4>(v, q1, d1, f1, j, h, wave, r, a.wl, L);
+                }
+                if (q2 >= 0) {
+                    if (j + 1 < 16) pair_leaf_pivot<W, 0, 4>(v, q2, d2, f2, j + 1, h, wave, r, a.wl, L);
+                    else pair_leaf_pivot<W, 2, 4>(v, q2, d2, f2, j + 1, h, wave, r, a.wl, L);
+                }
+            }
+            if (q1 >= 0) chosen |= 1ull << q1;
+            if (q2 >= 0) chosen |= 1ull << q2;
+            if (owner) {
+                // the next pair's owner brings that pair's two registers up to
+                // date first, posts it, and only then updates its other registers
+                if (((P + 1) >> 3) == 0) {  // registers 0, 1 (columns below 16; here j < 16)
+                    if (q1 >= 0) pair_leaf_pivot<W, 0, 2>(v, q1, d1, f1, j, h, wave, r, a.wl, L);
+                    if (q2 >= 0) pair_leaf_pivot<W, 0, 2>(v, q2, d2, f2, j + 1, h, wave, r, a.wl, L);
+                    detect(P + 1);
+                    if (q1 >= 0) pair_leaf_pivot<W, 2, 4>(v, q1, d1, f1, j, h, wave, r, a.wl, L);
+                    if (q2 >= 0) pair_leaf_pivot<W, 2, 4>(v, q2, d2, f2, j + 1, h, wave, r, a.wl, L);
+                } else {  // registers 2, 3
+                    if (q1 >= 0) pair_leaf_pivot<W, 2, 4>(v, q1, d1, f1, j, h, wave, r, a.wl, L);
+                    if (q2 >= 0) pair_leaf_pivot<W, 2, 4>(v, q2, d2, f2, j + 1, h, wave, r, a.wl, L);
+                    detect(P + 1);
+                    if (q1 >= 0 && j < 16) pair_leaf_pivot<W, 0, 2>(v, q1, d1, f1, j, h, wave, r, a.wl, L);
+                    if (q2 >= 0 && j + 1 < 16)
+                        pair_leaf_pivot<W, 0, 2>(v, q2, d2, f2, j + 1, h, wave, r, a.wl, L);
+                }
+            }
+            // transform columns: pivot 1 at column s1, then pivot 2 at column s2
+            if (q1 >= 0) {
+                const double inj = -lz_mul(f1, cprod, L);
+                if (s1 < 16) pair_t_pivot<W, 2>(T, q1, d1, f1, s1, cprod, inj, h, wave, r, L);
+                else pair_t_pivot<W, 4>(T, q1, d1, f1, s1, cprod, inj, h, wave, r, L);
+            }
+            if (q2 >= 0) {
+                const double cp2 = q1 >= 0 ? lz_mul(cprod, d1, L) : cprod;
+                const double inj = -lz_mul(f2, cp2, L);
+                if (s2 < 16) pair_t_pivot<W, 2>(T, q2, d2, f2, s2, cp2, inj, h, wave, r, L);
+                else pair_t_pivot<W, 4>(T, q2, d2, f2, s2, cp2, inj, h, wave, r, L);
+            }
+        } else {
+            // eight waves: wave v holds columns 2 v, 2 v + 1 (half 0) and 16 + 2 v,
+            // 17 + 2 v (half 1) in registers 0 and 1, the owner's pair among them
+            const bool leaf_live = 17 + 2 * wave > j;  // some column of this wave after j
+            if (leaf_live && q1 >= 0) pair_leaf_pivot<W, 0, 2>(v, q1, d1, f1, j, h, wave, r, a.wl, L);
+            if (leaf_live && q2 >= 0)
+                pair_leaf_pivot<W, 0, 2>(v, q2, d2, f2, j + 1, h, wave, r, a.wl, L);
+            if (q1 >= 0) chosen |= 1ull << q1;
+            if (q2 >= 0) chosen |= 1ull << q2;
+            if (owner) detect(P + 1);
+            // transform columns up to s: live once s reaches this wave's first one
+            if (q1 >= 0 && 2 * wave <= s1) {
+                const double inj = -lz_mul(f1, cprod, L);
+                pair_t_pivot<W, 2>(T, q1, d1, f1, s1, cprod, inj, h, wave, r, L);
+            }
+            if (q2 >= 0 && 2 * wave <= s2) {
+                const double cp2 = q1 >= 0 ? lz_mul(cprod, d1, L) : cprod;
+                const double inj = -lz_mul(f2, cp2, L);
+                pair_t_pivot<W, 2>(T, q2, d2, f2, s2, cp2, inj, h, wave, r, L);
+            }
         }
         if (q1 >= 0) cprod = lz_mul(cprod, d1, L);
         if (q2 >= 0) cprod = lz_mul(cprod, d2, L);
@@ -453,14 +546,16 @@ __device__ __forceinline__ void node_gj_pairs(const SelArgs& a, Sel& S, double v
 // Final node: P^-1, the leaf result, the pivot bookkeeping, and a copy of the
 // pivot rows over the columns the leaf updates (the product overwrites them).
 // R = 32: the pair layout of node_gj_pairs; R = 64: the layout of node_gj<64>.
-template <int R>
+template <int R, int W>
 __device__ __forceinline__ void publish(const SelArgs& a, Sel& S, const double T[8], bool save_rows,
                                         const Lazy& L) {
+    static_assert(R == 32 || W == 4, "the 64-row layout has four waves");
+    constexpr int NR = R == 32 ? 16 / W : 8;  // transform registers per lane
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int h = R == 32 ? lane >> 5 : 0;
     const int r = R == 32 ? lane & 31 : lane;
     auto colof = [&](int k) {
-        return R == 32 ? 2 * (8 * (k >> 1) + 4 * h + wave) + (k & 1) : Lay<64>::col(wave, 0, k);
+        return R == 32 ? pair_col<W>(k, h, wave) : Lay<64>::col(wave, 0, k);
     };
     const int t = S.t;
     if (threadIdx.x < t) S.rows[threadIdx.x] = a.cand[S.basis[threadIdx.x]];
@@ -470,7 +565,7 @@ __device__ __forceinline__ void publish(const SelArgs& a, Sel& S, const double T
         S.bcast = a.w.state[0];
         if (t > 0) S.total = lz_inverse(lz_canon(S.total, L), a.w.F.p, L);
     } else if (threadIdx.x >= 64 && t > 0 && save_rows) {  // meanwhile the other waves save the rows
-        for (int64_t c = threadIdx.x - 64; c < a.ncopy; c += kSelThreads - 64) {
+        for (int64_t c = threadIdx.x - 64; c < a.ncopy; c += 64 * W - 64) {
             // eight loads in flight before their stores; pivots k >= t reuse pivot
             // 0's row (S.rows[0] is set because t > 0)
             for (int k0 = 0; k0 < 32; k0 += 8) {
@@ -489,7 +584,7 @@ __device__ __forceinline__ void publish(const SelArgs& a, Sel& S, const double T
     if (s >= 0) {
         const double dinv = lz_mul(S.cp[s], S.total, L);
 #pragma unroll
-        for (int k = 0; k < (R == 32 ? 4 : 8); ++k) {
+        for (int k = 0; k < NR; ++k) {
             const int c = colof(k);
             if (c < t) a.out->pinv[s * 32 + c] = (uint32_t)lz_canon(lz_mul(dinv, T[k], L), L);
         }
@@ -573,7 +668,8 @@ __device__ void build_y_block(const SelArgs& a, int g, const Lazy& L) {
 // rank, as with dense data; the full tree launch then finds the result
 // published and ends at once, or selects over all candidates.
 template <bool first>
-__global__ __launch_bounds__(kSelThreads, first ? 4 : 1) void leaf_select_kernel(SelArgs a) {
+__global__ __launch_bounds__(first ? kFirstThreads : kSelThreads, first ? 2 : 1) void leaf_select_kernel(
+    SelArgs a) {
     __shared__ Sel S;
     const Lazy L{(double)a.w.F.p, a.w.F.pinv};
     int32_t* published = a.cnt_cur + (a.ncnt - 1);
@@ -608,11 +704,12 @@ __global__ __launch_bounds__(kSelThreads, first ? 4 : 1) void leaf_select_kernel
     __syncthreads();
     int level = 0, k = g, nodes = G;
     double v[8], T[8];
-    node_gj_pairs(a, S, v, T, L);
     if (first) {
-        if (S.t == a.wl || nodes == 1) publish<32>(a, S, T, a.save_rows && !a.yfrag, L);
+        node_gj_pairs<kFirstWaves>(a, S, v, T, L);
+        if (S.t == a.wl || nodes == 1) publish<32, kFirstWaves>(a, S, T, a.save_rows && !a.yfrag, L);
         return;  // otherwise the tree launch decides
     }
+    node_gj_pairs<kSelWaves>(a, S, v, T, L);
     int regs = 32;  // v, T hold the Gauss-Jordan of the node's basis rows in this layout (0: none)
     while (true) {
         const int t = S.t;
@@ -621,13 +718,13 @@ __global__ __launch_bounds__(kSelThreads, first ? 4 : 1) void leaf_select_kernel
                 if (threadIdx.x < t) S.pos[threadIdx.x] = S.basis[threadIdx.x];
                 if (threadIdx.x == 0) S.nrows = t;
                 __syncthreads();
-                node_gj_pairs(a, S, v, T, L);
+                node_gj_pairs<kSelWaves>(a, S, v, T, L);
                 regs = 32;
             }
             // the tree launch leaves Y to the product, which needs the rows as selected
             const bool save_rows = a.save_rows != 0;
-            if (regs == 32) publish<32>(a, S, T, save_rows, L);
-            else publish<64>(a, S, T, save_rows, L);
+            if (regs == 32) publish<32, kSelWaves>(a, S, T, save_rows, L);
+            else publish<64, kSelWaves>(a, S, T, save_rows, L);
             return;
         }
         const int up = (nodes + 1) >> 1;
@@ -949,7 +1046,7 @@ hipError_t leaf_select(const PlainArgs& w, const LeafState& ls, const uint32_t* 
     a.save_rows = save_rows ? 1 : 0;
     const int64_t nyb = ceil_div(ncopy, 32);
     const unsigned grid = (unsigned)(ls.gmax > nyb ? ls.gmax : nyb);
-    hipLaunchKernelGGL(leaf_select_kernel<true>, dim3(1), dim3(kSelThreads), 0, s, a);
+    hipLaunchKernelGGL(leaf_select_kernel<true>, dim3(1), dim3(kFirstThreads), 0, s, a);
     hipLaunchKernelGGL(leaf_select_kernel<false>, dim3(grid), dim3(kSelThreads), 0, s, a);
     return hipGetLastError();
 }
