@@ -42,7 +42,10 @@ namespace {
 
 constexpr int kSelWaves = 4;   // the tree launch
 constexpr int kSelThreads = 64 * kSelWaves;
-constexpr int kFirstWaves = 8;  // the first-chunk launch: two waves per SIMD
+// The first-chunk launch: eight waves, two per SIMD (one wave's FP64 issue rate
+// is the limit, so a second wave per SIMD nearly doubles the throughput).  The
+// layouts also support 16 waves, measured no faster.
+constexpr int kFirstWaves = 8;
 constexpr int kFirstThreads = 64 * kFirstWaves;
 constexpr int kChunk = 32;     // candidate rows per first-level tree node
 constexpr int kNodeInts = 64;  // per node: basis size, then its list positions
@@ -319,9 +322,11 @@ __device__ __forceinline__ void node_gj(const SelArgs& a, Sel& S, double v[8], d
 // wave of pair P finds the first column's pivot, applies it to the second
 // column itself, finds the second pivot and posts both; every wave then applies
 // the two pivots in order.  Same results as one column per step.
-// Column of register k in the pair layout of W waves (see node_gj_pairs).
+// Column of register k in the pair layout of W waves (see node_gj_pairs).  With
+// 16 waves a lane holds one column: wave P has pair P, half h its column 2P + h.
 template <int W>
 __device__ __forceinline__ int pair_col(int k, int h, int wave) {
+    if (W == 16) return 2 * wave + h;
     return 2 * (2 * W * (k >> 1) + W * h + wave) + (k & 1);
 }
 
@@ -376,8 +381,8 @@ __device__ __forceinline__ void pair_t_pivot(double x[4], int q, double d, doubl
 template <int W>
 __device__ __forceinline__ void node_gj_pairs(const SelArgs& a, Sel& S, double v[8], double T[8],
                                               const Lazy& L) {
-    static_assert(W == 4 || W == 8, "4 or 8 waves");
-    constexpr int NR = 16 / W;  // leaf (and transform) registers per lane
+    static_assert(W == 4 || W == 8 || W == 16, "4, 8 or 16 waves");
+    constexpr int NR = W == 16 ? 1 : 16 / W;  // leaf (and transform) registers per lane
     // wave-uniform by construction; readfirstlane lets the compiler see it, so
     // conditions on it stay scalar branches instead of exec-masked regions
     const int lane = threadIdx.x & 63, wave = uniform(threadIdx.x >> 6);
@@ -405,6 +410,34 @@ __device__ __forceinline__ void node_gj_pairs(const SelArgs& a, Sel& S, double v
     const int npairs = (a.wl + 1) >> 1;
     // owner of pair P: post both pivots (the second column exists iff 2P + 1 < wl)
     auto detect = [&](int P) {
+        if constexpr (W == 16) {
+            // half 0 holds the pair's first column, half 1 its second
+            const double x = v[0];
+            const int q1 = first_nz(x, 0, chosen);
+            const double d1 = q1 >= 0 ? readlane_d(x, q1) : 0.0;
+            double xb = x;
+            if (q1 >= 0) {
+                const double ub = readlane_d(x, 32 + q1);
+                const double fa = pair_row(x, r << 2);  // this row's first-column value
+                if (h == 1 && r != q1) xb = lz_ff(d1, x, fa, ub, L);
+            }
+            int q2 = -1;
+            double d2 = 0.0;
+            if (2 * P + 1 < a.wl) {
+                q2 = first_nz(xb, 1, chosen | (q1 >= 0 ? 1ull << q1 : 0ull));
+                d2 = q2 >= 0 ? readlane_d(xb, 32 + q2) : 0.0;
+            }
+            const int buf = P & 1;
+            if (h == 0) S.f[buf][r] = x;
+            else S.f2[buf][r] = xb;
+            if (lane == 0) {
+                S.q[buf] = q1;
+                S.d[buf] = d1;
+                S.q2[buf] = q2;
+                S.d2[buf] = d2;
+            }
+            return;
+        }
         const int hp = (P / W) & 1, kp = P / (2 * W);
         double xa = 0.0, xb = 0.0;  // registers 2 kp and 2 kp + 1, selected arithmetically
 #pragma unroll
@@ -511,23 +544,24 @@ __device__ __forceinline__ void node_gj_pairs(const SelArgs& a, Sel& S, double v
             }
         } else {
             // eight waves: wave v holds columns 2 v, 2 v + 1 (half 0) and 16 + 2 v,
-            // 17 + 2 v (half 1) in registers 0 and 1, the owner's pair among them
-            const bool leaf_live = 17 + 2 * wave > j;  // some column of this wave after j
-            if (leaf_live && q1 >= 0) pair_leaf_pivot<W, 0, 2>(v, q1, d1, f1, j, h, wave, r, a.wl, L);
+            // 17 + 2 v (half 1) in registers 0 and 1; sixteen waves: columns 2 v
+            // and 2 v + 1 in register 0.  The owner's pair is among them.
+            const bool leaf_live = (W == 8 ? 17 : 1) + 2 * wave > j;  // a column after j
+            if (leaf_live && q1 >= 0) pair_leaf_pivot<W, 0, NR>(v, q1, d1, f1, j, h, wave, r, a.wl, L);
             if (leaf_live && q2 >= 0)
-                pair_leaf_pivot<W, 0, 2>(v, q2, d2, f2, j + 1, h, wave, r, a.wl, L);
+                pair_leaf_pivot<W, 0, NR>(v, q2, d2, f2, j + 1, h, wave, r, a.wl, L);
             if (q1 >= 0) chosen |= 1ull << q1;
             if (q2 >= 0) chosen |= 1ull << q2;
             if (owner) detect(P + 1);
             // transform columns up to s: live once s reaches this wave's first one
             if (q1 >= 0 && 2 * wave <= s1) {
                 const double inj = -lz_mul(f1, cprod, L);
-                pair_t_pivot<W, 2>(T, q1, d1, f1, s1, cprod, inj, h, wave, r, L);
+                pair_t_pivot<W, NR>(T, q1, d1, f1, s1, cprod, inj, h, wave, r, L);
             }
             if (q2 >= 0 && 2 * wave <= s2) {
                 const double cp2 = q1 >= 0 ? lz_mul(cprod, d1, L) : cprod;
                 const double inj = -lz_mul(f2, cp2, L);
-                pair_t_pivot<W, 2>(T, q2, d2, f2, s2, cp2, inj, h, wave, r, L);
+                pair_t_pivot<W, NR>(T, q2, d2, f2, s2, cp2, inj, h, wave, r, L);
             }
         }
         if (q1 >= 0) cprod = lz_mul(cprod, d1, L);
@@ -550,7 +584,7 @@ template <int R, int W>
 __device__ __forceinline__ void publish(const SelArgs& a, Sel& S, const double T[8], bool save_rows,
                                         const Lazy& L) {
     static_assert(R == 32 || W == 4, "the 64-row layout has four waves");
-    constexpr int NR = R == 32 ? 16 / W : 8;  // transform registers per lane
+    constexpr int NR = R == 32 ? (W == 16 ? 1 : 16 / W) : 8;  // transform registers per lane
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int h = R == 32 ? lane >> 5 : 0;
     const int r = R == 32 ? lane & 31 : lane;
