@@ -186,6 +186,10 @@ __device__ __forceinline__ uint32_t fold7(const v16i* acc, int r, uint32_t add, 
 // prefetched into registers.  With grid.x = row tiles and a multiple of 8 of
 // them, all blocks of one row tile run on the same XCD, so each XCD's L2 holds
 // one eighth of the A operand.
+// Tiles of 128 rows x 32 columns, taken by the workgroups in turn (row tiles
+// fastest, so that concurrent workgroups share their B slices in L2): a grid of
+// one workgroup per tile, or fewer that loop, which leaves compute units free
+// for other work on the device.
 __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat dst, int64_t col0,
                                                               int64_t N, const int8_t* Afrag,
                                                               const int8_t* Bfrag, int32_t KB,
@@ -193,59 +197,64 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
                                                               double c32) {
     __shared__ v4i sB[2][4 * 64];  // 2 x 4 KB
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t rb = (int64_t)blockIdx.x * 4 + wave;
-    const int64_t cb = blockIdx.y;
-    const int8_t* bsrc = Bfrag + (cb * KB * 4 + wave) * 1024 + lane * 16;  // wave v moves plane v
-    const int8_t* asrc = Afrag + (rb * KB * 4) * 1024 + lane * 16;
-    v16i acc[7];
-    for (int g = 0; g < 7; ++g)
-        for (int r = 0; r < 16; ++r) acc[g][r] = 0;
-    v4i stage, af[4], an[4];
-    stage = *(const v4i*)bsrc;
-    for (int l = 0; l < 4; ++l) af[l] = *(const v4i*)(asrc + l * 1024);
-    sB[0][wave * 64 + lane] = stage;
-    __builtin_amdgcn_s_waitcnt(0);  // nothing in flight at the loop head
-    __syncthreads();
-    for (int kb = 0; kb < KB; ++kb) {
-        const bool more = kb + 1 < KB;
-        if (more) {  // next k-block in flight while this one computes
-            stage = *(const v4i*)(bsrc + (int64_t)(kb + 1) * 4 * 1024);
-            for (int l = 0; l < 4; ++l)
-                an[l] = *(const v4i*)(asrc + ((int64_t)(kb + 1) * 4 + l) * 1024);
-        }
-        const v4i* sb = sB[kb & 1];
-        v4i bf[4];
-        for (int lp = 0; lp < 4; ++lp) bf[lp] = sb[lp * 64 + lane];
-        for (int l = 0; l < 4; ++l)
-            for (int lp = 0; lp < 4; ++lp)
-                acc[l + lp] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[l], bf[lp], acc[l + lp], 0, 0, 0);
-        if (more) {
-            sB[(kb + 1) & 1][wave * 64 + lane] = stage;
-            for (int l = 0; l < 4; ++l) af[l] = an[l];
-        }
+    const int64_t mtiles = ceil_div(w.m, 128);
+    const int64_t ntiles = mtiles * ceil_div(N, 32);
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t rb = (tile % mtiles) * 4 + wave;
+        const int64_t cb = tile / mtiles;
+        const int8_t* bsrc = Bfrag + (cb * KB * 4 + wave) * 1024 + lane * 16;  // wave v moves plane v
+        const int8_t* asrc = Afrag + (rb * KB * 4) * 1024 + lane * 16;
+        v16i acc[7];
+        for (int g = 0; g < 7; ++g)
+            for (int r = 0; r < 16; ++r) acc[g][r] = 0;
+        v4i stage, af[4], an[4];
+        stage = *(const v4i*)bsrc;
+        for (int l = 0; l < 4; ++l) af[l] = *(const v4i*)(asrc + l * 1024);
+        sB[0][wave * 64 + lane] = stage;  // the k loop's last barrier freed sB
+        __builtin_amdgcn_s_waitcnt(0);  // nothing in flight at the loop head
         __syncthreads();
-    }
-    // epilogue: 32x32 accumulator layout: lane L holds column L%32 and rows
-    // 8*(r/4) + 4*(L/32) + r%4 for r = 0..15.  All loads are issued before the
-    // first store so their latencies overlap.
-    // (addresses are clamped into the matrix so that every load is issued
-    // unconditionally; out-of-range values are discarded afterwards)
-    const int64_t col = cb * 32 + (lane & 31);
-    const int64_t colc = col < N ? col : N - 1;
-    int rcv[16];
-    uint32_t cur[16];
-    for (int r = 0; r < 16; ++r) {
-        const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int64_t rowc = row < w.m ? row : w.m - 1;
-        rcv[r] = w.rowcol[rowc];
-        cur[r] = __builtin_nontemporal_load(dst.M + rowc * dst.ld + col0 + colc);
-    }
-    if (col >= N) return;
-    for (int r = 0; r < 16; ++r) {
-        const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        if (row >= w.m) continue;
-        const bool fresh = rcv[r] >= fresh_lo && rcv[r] < fresh_hi;  // a pivot row of this panel
-        dst.M[row * dst.ld + col0 + col] = fold7(acc, r, fresh ? 0u : cur[r], c32, w.F);
+        for (int kb = 0; kb < KB; ++kb) {
+            const bool more = kb + 1 < KB;
+            if (more) {  // next k-block in flight while this one computes
+                stage = *(const v4i*)(bsrc + (int64_t)(kb + 1) * 4 * 1024);
+                for (int l = 0; l < 4; ++l)
+                    an[l] = *(const v4i*)(asrc + ((int64_t)(kb + 1) * 4 + l) * 1024);
+            }
+            const v4i* sb = sB[kb & 1];
+            v4i bf[4];
+            for (int lp = 0; lp < 4; ++lp) bf[lp] = sb[lp * 64 + lane];
+            for (int l = 0; l < 4; ++l)
+                for (int lp = 0; lp < 4; ++lp)
+                    acc[l + lp] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[l], bf[lp], acc[l + lp], 0, 0, 0);
+            if (more) {
+                sB[(kb + 1) & 1][wave * 64 + lane] = stage;
+                for (int l = 0; l < 4; ++l) af[l] = an[l];
+            }
+            __syncthreads();
+        }
+        // epilogue: 32x32 accumulator layout: lane L holds column L%32 and rows
+        // 8*(r/4) + 4*(L/32) + r%4 for r = 0..15.  All loads are issued before
+        // the first store so their latencies overlap (addresses clamped into the
+        // matrix so that every load is issued unconditionally; out-of-range
+        // values are discarded afterwards).
+        const int64_t col = cb * 32 + (lane & 31);
+        const int64_t colc = col < N ? col : N - 1;
+        int rcv[16];
+        uint32_t cur[16];
+        for (int r = 0; r < 16; ++r) {
+            const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            const int64_t rowc = row < w.m ? row : w.m - 1;
+            rcv[r] = w.rowcol[rowc];
+            cur[r] = __builtin_nontemporal_load(dst.M + rowc * dst.ld + col0 + colc);
+        }
+        if (col < N) {
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                if (row >= w.m) continue;
+                const bool fresh = rcv[r] >= fresh_lo && rcv[r] < fresh_hi;  // a pivot row of this panel
+                dst.M[row * dst.ld + col0 + col] = fold7(acc, r, fresh ? 0u : cur[r], c32, w.F);
+            }
+        }
     }
 }
 
@@ -595,7 +604,7 @@ size_t carve_blocked(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, B
 // whose pivot column lies in [fresh_lo, fresh_hi).
 hipError_t run_product(const PlainArgs& w, bool fp64, const int8_t* Af, const int8_t* Bf, Mat dst,
                        int64_t col0, int64_t N, int32_t KB, int32_t fresh_lo, int32_t fresh_hi,
-                       hipStream_t s, LaunchTimer& lt, int kind) {
+                       hipStream_t s, LaunchTimer& lt, int kind, int64_t max_wgs = 0) {
     const int64_t m = w.m;
     lt.before(kind, s);
     if (fp64) {
@@ -604,9 +613,10 @@ hipError_t run_product(const PlainArgs& w, bool fp64, const int8_t* Af, const in
                            (const double*)Bf, KB, ceil_div(N, 16), fresh_lo, fresh_hi);
     } else {
         const double c32 = (double)((((uint64_t)1) << 32) % w.F.p);
-        hipLaunchKernelGGL(gemm_i8_kernel, dim3((unsigned)ceil_div(m, 128), (unsigned)ceil_div(N, 32)),
-                           dim3(kThreads), 0, s, w, dst, col0, N, Af, Bf, KB, fresh_lo, fresh_hi,
-                           c32);
+        const int64_t tiles = ceil_div(m, 128) * ceil_div(N, 32);
+        const int64_t grid = max_wgs > 0 && max_wgs < tiles ? max_wgs : tiles;
+        hipLaunchKernelGGL(gemm_i8_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, w, dst, col0, N,
+                           Af, Bf, KB, fresh_lo, fresh_hi, c32);
     }
     lt.after();
     return hipGetLastError();
@@ -685,6 +695,9 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
     // leaf (faster than a rebuild in every product workgroup)
     const bool select_y = true;
     hipError_t e = hipSuccess;
+    // (a remainder capped at one workgroup per compute unit ran longer and
+    // slowed the leaves as much: the contention is in the memory system)
+    const int64_t side_wgs = 0;
     if (lookahead) {
         e = side_stream(&side);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_t1, hipEventDisableTiming);
@@ -759,7 +772,7 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
                 if (e == hipSuccess)
                     e = run_product(w, fp64, b.Afrag, b.Bfrag + (n1 / 32) * KB * 4 * 1024, Wm,
                                     col0 + n1, N - n1, KB, j0, j0 + wj, side, lt,
-                                    LINAC_KERNEL_TRAIL_PRODUCT);
+                                    LINAC_KERNEL_TRAIL_PRODUCT, side_wgs);
                 if (e == hipSuccess) e = hipEventRecord(ev_t2, side);
                 t2_pending = e == hipSuccess;
             }
