@@ -157,13 +157,12 @@ __global__ void build_a_kernel(PlainArgs w, Mat ebuf, int64_t ecol0, int32_t wj,
 // sum_s 256^s S_s reduced mod p, plus `add` (a residue, or 0): T_lo and T_hi
 // are exact in FP64; each is folded into [-p, 2p), T_hi is multiplied by
 // c32 = 2^32 mod p exactly (FMA split), and the sum is reduced once more.
-__device__ __forceinline__ uint32_t fold7(const v16i* acc, int r, uint32_t add, double c32,
-                                          const FieldConst& F) {
-    const double lo = __fma_rn(16777216.0, (double)acc[3][r],
-                               __fma_rn(65536.0, (double)acc[2][r],
-                                        __fma_rn(256.0, (double)acc[1][r], (double)acc[0][r])));
-    const double hi =
-        __fma_rn(65536.0, (double)acc[6][r], __fma_rn(256.0, (double)acc[5][r], (double)acc[4][r]));
+__device__ __forceinline__ uint32_t fold7s(int32_t s0, int32_t s1, int32_t s2, int32_t s3, int32_t s4,
+                                           int32_t s5, int32_t s6, uint32_t add, double c32,
+                                           const FieldConst& F) {
+    const double lo = __fma_rn(16777216.0, (double)s3,
+                               __fma_rn(65536.0, (double)s2, __fma_rn(256.0, (double)s1, (double)s0)));
+    const double hi = __fma_rn(65536.0, (double)s6, __fma_rn(256.0, (double)s5, (double)s4));
     const double rlo = __fma_rn(-floor(lo * F.pinv), F.dp, lo);
     const double rhi = __fma_rn(-floor(hi * F.pinv), F.dp, hi);
     const double h = rhi * c32;
@@ -173,6 +172,18 @@ __device__ __forceinline__ uint32_t fold7(const v16i* acc, int r, uint32_t add, 
     if (r2 < 0.0) r2 += F.dp;
     if (r2 >= F.dp) r2 -= F.dp;
     return (uint32_t)r2;
+}
+
+__device__ __forceinline__ uint32_t fold7(const v16i* acc, int r, uint32_t add, double c32,
+                                          const FieldConst& F) {
+    return fold7s(acc[0][r], acc[1][r], acc[2][r], acc[3][r], acc[4][r], acc[5][r], acc[6][r], add,
+                  c32, F);
+}
+
+__device__ __forceinline__ uint32_t fold7(const v4i* acc, int r, uint32_t add, double c32,
+                                          const FieldConst& F) {
+    return fold7s(acc[0][r], acc[1][r], acc[2][r], acc[3][r], acc[4][r], acc[5][r], acc[6][r], add,
+                  c32, F);
 }
 
 // Product update C = delta * C + A . B (mod p) on int8 MFMA (C = dst columns
@@ -262,29 +273,33 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
 // C + A . Y, and Y itself for the leaf's pivot rows, where A = -(the row's
 // values at the leaf's pivot columns) and Y = P^-1 R, R being the pivot rows as
 // the selection saw them, with each pivot's implicit 1 in the transform block.
-// Block: 4 waves over 128 rows and kLeafBlocks consecutive 32-column blocks,
-// taken one after the other with the same multipliers (int8 digits built in
-// registers).  Y's fragments come from the selection when it built them
-// (out->yready); otherwise every block forms its own slices of Y (32 x 32 x t
-// products in FP64 with exact 16-bit splits) from the rows the selection saved.
-// The leaf's pivot columns are not written (their unit-vector form is implied
-// by the bookkeeping), so no multiplier is overwritten while other blocks still
-// read it.  The launch also builds the next leaf's candidate list (one entry per
-// thread).
-constexpr int kLeafBlocks = 2;
+// 16x16x32 MFMA tiles keep a wave at seven 4-register accumulators, so the
+// kernel fits in 128 VGPRs and shares SIMDs with a concurrent trailing product.
+// Block: 4 waves over 64 rows (16 each) and two 16-column blocks, taken one
+// after the other with the same multipliers (int8 digits built in registers).
+// Operand lanes of the 16x16x32 int8 MFMA: A(i, k) in lane i + 16 (k / 8), byte
+// k % 8; B(k, j) in lane j + 16 (k / 8), byte k % 8; C(i, j) in lane j + 16 (i /
+// 4), register i % 4.  Y's fragments come from the selection when it built
+// them (out->yready; plane l of 16-column block b at (4 b + l) * 512 bytes, 8
+// per lane); otherwise every block forms its own slices of Y (32 x 16 x t
+// products in FP64 with exact 16-bit splits) from the rows the selection
+// saved.  The leaf's pivot columns are not written (their unit-vector form is
+// implied by the bookkeeping), so no multiplier is overwritten while other
+// blocks still read it.  The launch also builds the next leaf's candidate list
+// (one entry per thread).
+constexpr int kLeafBlocks = 2;  // 16-column blocks per workgroup
 
-__global__ __launch_bounds__(kThreads, 2) void leaf_product_i8_kernel(
+__global__ __launch_bounds__(kThreads, 4) void leaf_product_i8_kernel(
     PlainArgs w, Mat pr, int32_t l0, int32_t wl, int32_t wj, int32_t gcol0, int64_t N,
     const LeafOut* out, const uint32_t* rsave, int64_t ldr, double c32, const int32_t* cand,
     int32_t* cand_next, const int32_t* count, int32_t* count_next, const int8_t* yfrag) {
     __shared__ uint32_t sP[32][33];
-    __shared__ uint32_t sR[32][33];
-    __shared__ uint32_t sY[32][33];
-    __shared__ v4i sB[4 * 64];
+    __shared__ uint32_t sR[32][17];
+    __shared__ __attribute__((aligned(16))) int8_t sB[4][64][8];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t rb = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t rb = (int64_t)blockIdx.x * 4 + wave;  // 16-row block
     const int64_t cb0 = (int64_t)blockIdx.y * kLeafBlocks;
-    const int64_t NB = ceil_div(N, 32);
+    const int64_t NB = ceil_div(N, 16);
     const int t = out->t;
     const uint32_t p = w.F.p;
     {
@@ -297,11 +312,11 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_product_i8_kernel(
     // unconditionally (values out of range are discarded afterwards), so they
     // overlap instead of waiting one by one.
     const bool yready = out->yready != 0;
-    // multipliers of this lane's A row (row 32 rb + L%32, k = 16 (L/32) + i)
-    const int64_t arow = rb * 32 + (lane & 31);
+    // multipliers of this lane's A row (row 16 rb + L%16, k = 8 (L/16) + e)
+    const int64_t arow = rb * 16 + (lane & 15);
     const int64_t arowc = arow < w.m ? arow : w.m - 1;
-    const int khalf = 16 * (lane >> 5);
-    uint32_t av[16];
+    const int kg = 8 * (lane >> 4);
+    uint32_t av[8];
     int sel = -1;
     {
         int colv[32];  // the leaf's pivot columns (the array always has 32 entries)
@@ -313,8 +328,8 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_product_i8_kernel(
         }
         const int rc = w.rowcol[arowc] - gcol0;
         if (ident) {
-            const uint4* src = (const uint4*)(pr.M + arowc * pr.ld + l0 + khalf);
-            for (int q4 = 0; q4 < 4; ++q4) {
+            const uint4* src = (const uint4*)(pr.M + arowc * pr.ld + l0 + kg);
+            for (int q4 = 0; q4 < 2; ++q4) {
                 const uint4 v4 = src[q4];
                 av[4 * q4] = v4.x;
                 av[4 * q4 + 1] = v4.y;
@@ -323,119 +338,104 @@ __global__ __launch_bounds__(kThreads, 2) void leaf_product_i8_kernel(
             }
         } else {  // (rare) gather by the pivot columns, read per lane
 #pragma unroll
-            for (int i = 0; i < 16; ++i) av[i] = pr.M[arowc * pr.ld + l0 + (out->col[khalf + i] & 31)];
+            for (int e = 0; e < 8; ++e) av[e] = pr.M[arowc * pr.ld + l0 + (out->col[kg + e] & 31)];
         }
 #pragma unroll
         for (int s2 = 0; s2 < 32; ++s2)  // the row's own pivot of this leaf, if any
             if (s2 < t && rc >= 0 && rc < wl && colv[s2] == rc) sel = s2;
-        for (int i = 0; i < 16; ++i)
-            if (arow >= w.m || khalf + i >= t) av[i] = 0u;
+        for (int e = 0; e < 8; ++e)
+            if (arow >= w.m || kg + e >= t) av[e] = 0u;
         if (arow >= w.m) sel = -1;
     }
-    // epilogue rows: rowcol and current values, loaded before any computation
-    int rcv[16];
-    uint32_t cur[kLeafBlocks][16];
-    for (int r = 0; r < 16; ++r) {
-        const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    // epilogue rows (16 rb + 4 (L/16) + r): rowcol and current values, loaded
+    // before any computation
+    int rcv[4];
+    uint32_t cur[kLeafBlocks][4];
+    for (int r = 0; r < 4; ++r) {
+        const int64_t row = rb * 16 + 4 * (lane >> 4) + r;
         rcv[r] = w.rowcol[row < w.m ? row : w.m - 1];
     }
 #pragma unroll
     for (int cbi = 0; cbi < kLeafBlocks; ++cbi) {
-        const int64_t col = (cb0 + cbi) * 32 + (lane & 31);
+        const int64_t col = (cb0 + cbi) * 16 + (lane & 15);
         const int64_t colc = col < N ? col : N - 1;
-        for (int r = 0; r < 16; ++r) {
-            const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        for (int r = 0; r < 4; ++r) {
+            const int64_t row = rb * 16 + 4 * (lane >> 4) + r;
             cur[cbi][r] = pr.M[(row < w.m ? row : w.m - 1) * pr.ld + l0 + colc];
         }
     }
-    v4i af[4];
+    long af[4];
     {
-        int8_t outa[4][16];
-        for (int i = 0; i < 16; ++i) {
-            const int k = khalf + i;
-            uint32_t a = sel >= 0 ? (k == sel ? 1u : 0u) : (av[i] == 0 ? 0u : p - av[i]);
+        int8_t outa[4][8];
+        for (int e = 0; e < 8; ++e) {
+            const int k = kg + e;
+            uint32_t x = sel >= 0 ? (k == sel ? 1u : 0u) : (av[e] == 0 ? 0u : p - av[e]);
             int8_t d[4];
-            digits4(centre(a, p), d);
-            for (int l = 0; l < 4; ++l) outa[l][i] = d[l];
+            digits4(centre(x, p), d);
+            for (int l = 0; l < 4; ++l) outa[l][e] = d[l];
         }
-        for (int l = 0; l < 4; ++l) __builtin_memcpy(&af[l], outa[l], 16);
+        for (int l = 0; l < 4; ++l) __builtin_memcpy(&af[l], outa[l], 8);
     }
 #pragma unroll
     for (int cbi = 0; cbi < kLeafBlocks; ++cbi) {
         const int64_t cb = cb0 + cbi;
         if (cb >= NB) continue;  // uniform over the block
-        v4i bf[4];
+        long bf[4];
         if (yready) {
-            for (int l = 0; l < 4; ++l) bf[l] = *(const v4i*)(yfrag + (cb * 4 + l) * 1024 + lane * 16);
+            for (int l = 0; l < 4; ++l) bf[l] = *(const long*)(yfrag + (cb * 4 + l) * 512 + lane * 8);
         } else {
             __syncthreads();  // the previous slice's LDS is free
             for (int i = tid; i < 32 * 32; i += kThreads) {
                 const int s = i >> 5, c = i & 31;
-                const int64_t col = cb * 32 + c;
-                const uint32_t pv = out->pinv[s * 32 + c];
+                sP[s][c] = (s < t && c < t) ? out->pinv[s * 32 + c] : 0u;
+            }
+            for (int i = tid; i < 32 * 16; i += kThreads) {
+                const int s = i >> 4, c = i & 15;
+                const int64_t col = cb * 16 + c;
                 const uint32_t rv = rsave[s * ldr + (col < N ? col : N - 1)];
                 const int cs = out->col[s];
-                sP[s][c] = (s < t && c < t) ? pv : 0u;
                 sR[s][c] = (s < t && col < N) ? (col == (int64_t)wj + cs ? 1u : rv) : 0u;
             }
             __syncthreads();
-            {  // Y slice: thread -> row s = tid / 8, columns 4 (tid % 8) .. + 3
-                const int s = tid >> 3, c4 = (tid & 7) * 4;
-                double s1[4] = {0.0, 0.0, 0.0, 0.0}, s0[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int i = tid; i < 32 * 16; i += kThreads) {  // Y(s, c) in FP64 with 16-bit splits
+                const int s = i >> 4, c = i & 15;
+                double s1 = 0.0, s0 = 0.0;
                 for (int k = 0; k < t; ++k) {
                     const uint32_t pv = sP[s][k];
-                    const double hi = (double)(pv >> 16), lo = (double)(pv & 0xffffu);
-                    for (int e = 0; e < 4; ++e) {
-                        const double rv = (double)sR[k][c4 + e];
-                        s1[e] = __fma_rn(hi, rv, s1[e]);
-                        s0[e] = __fma_rn(lo, rv, s0[e]);
-                    }
+                    const double rv = (double)sR[k][c];
+                    s1 = __fma_rn((double)(pv >> 16), rv, s1);
+                    s0 = __fma_rn((double)(pv & 0xffffu), rv, s0);
                 }
-                for (int e = 0; e < 4; ++e) {
-                    // s1 < 2^51, s0 < 2^52: exact; reduce s1, recombine below 2^53, reduce
-                    double q = floor(s1[e] * w.F.pinv);
-                    double h = __fma_rn(-q, w.F.dp, s1[e]);
-                    q = floor(h * w.F.pinv);
-                    h = __fma_rn(-q, w.F.dp, h);
-                    double y = __fma_rn(h, 65536.0, s0[e]);
-                    q = floor(y * w.F.pinv);
-                    y = __fma_rn(-q, w.F.dp, y);
-                    q = floor(y * w.F.pinv);
-                    y = __fma_rn(-q, w.F.dp, y);
-                    if (y < 0.0) y += w.F.dp;
-                    if (y >= w.F.dp) y -= w.F.dp;
-                    sY[s][c4 + e] = (uint32_t)y;
-                }
+                // s1 < 2^51, s0 < 2^52: exact; reduce s1, recombine below 2^53, reduce
+                double q = floor(s1 * w.F.pinv);
+                double h = __fma_rn(-q, w.F.dp, s1);
+                q = floor(h * w.F.pinv);
+                h = __fma_rn(-q, w.F.dp, h);
+                double y = __fma_rn(h, 65536.0, s0);
+                q = floor(y * w.F.pinv);
+                y = __fma_rn(-q, w.F.dp, y);
+                q = floor(y * w.F.pinv);
+                y = __fma_rn(-q, w.F.dp, y);
+                if (y < 0.0) y += w.F.dp;
+                if (y >= w.F.dp) y -= w.F.dp;
+                int8_t d[4];
+                digits4(centre((uint32_t)y, p), d);
+                for (int l = 0; l < 4; ++l) sB[l][c + 16 * (s >> 3)][s & 7] = d[l];
             }
             __syncthreads();
-            if (tid < 64) {  // B fragment: digit plane l', lane L holds column L%32, rows 16 (L/32) + i
-                int8_t outb[4][16];
-                for (int i = 0; i < 16; ++i) {
-                    int8_t d[4];
-                    digits4(centre(sY[16 * (tid >> 5) + i][tid & 31], p), d);
-                    for (int l = 0; l < 4; ++l) outb[l][i] = d[l];
-                }
-                for (int l = 0; l < 4; ++l) {
-                    v4i vv;
-                    __builtin_memcpy(&vv, outb[l], 16);
-                    sB[l * 64 + tid] = vv;
-                }
-            }
-            __syncthreads();
-            for (int l = 0; l < 4; ++l) bf[l] = sB[l * 64 + lane];
+            for (int l = 0; l < 4; ++l) __builtin_memcpy(&bf[l], sB[l][lane], 8);
         }
-        v16i acc[7];
+        v4i acc[7];
         for (int g = 0; g < 7; ++g)
-            for (int r = 0; r < 16; ++r) acc[g][r] = 0;
+            for (int r = 0; r < 4; ++r) acc[g][r] = 0;
         for (int l = 0; l < 4; ++l)
             for (int lp = 0; lp < 4; ++lp)
-                acc[l + lp] =
-                    __builtin_amdgcn_mfma_i32_32x32x32_i8(af[l], bf[lp], acc[l + lp], 0, 0, 0);
-        const int64_t col = cb * 32 + (lane & 31);
+                acc[l + lp] = __builtin_amdgcn_mfma_i32_16x16x32_i8(af[l], bf[lp], acc[l + lp], 0, 0, 0);
+        const int64_t col = cb * 16 + (lane & 15);
         const bool pivcol = col < wl && w.colpiv[gcol0 + (col < wl ? col : 0)] >= 0;
         if (col < N && !pivcol) {
-            for (int r = 0; r < 16; ++r) {
-                const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = rb * 16 + 4 * (lane >> 4) + r;
                 if (row >= w.m) continue;
                 const bool fresh = rcv[r] >= gcol0 && rcv[r] < gcol0 + wl;  // a pivot row of this leaf
                 pr.M[row * pr.ld + l0 + col] = fold7(acc, r, fresh ? 0u : cur[cbi][r], c32, w.F);
@@ -737,8 +737,8 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
                 const double c32 = (double)((((uint64_t)1) << 32) % w.F.p);
                 lt.before(LINAC_KERNEL_LEAF_PRODUCT);
                 hipLaunchKernelGGL(leaf_product_i8_kernel,
-                                   dim3((unsigned)ceil_div(m, 128),
-                                        (unsigned)ceil_div(N, 32 * kLeafBlocks)),
+                                   dim3((unsigned)ceil_div(m, 64),
+                                        (unsigned)ceil_div(N, 16 * kLeafBlocks)),
                                    dim3(kThreads), 0, s, w, b.PR, l0, wl, wj, j0 + l0, N,
                                    (const LeafOut*)b.leaf.out, (const uint32_t*)b.leaf.rsave,
                                    b.leaf.ldr, c32, (const int32_t*)b.leaf.cand[parity],

@@ -653,7 +653,9 @@ __device__ __forceinline__ void publish(const SelArgs& a, Sel& S, const double T
 __device__ void build_y_block(const SelArgs& a, int g, const Lazy& L) {
     __shared__ uint32_t sP[32][33];
     __shared__ uint32_t sR[32][33];
-    __shared__ __attribute__((aligned(16))) int8_t sB[4][64][16];
+    // the two 16-column blocks of this 32-column slice, in the B lanes of the
+    // 16x16x32 int8 MFMA: Y(s, c) in lane c + 16 (s / 8), byte s % 8
+    __shared__ __attribute__((aligned(16))) int8_t sB[2][4][64][8];
     const int tid = threadIdx.x;
     const int t = a.out->t;
     for (int i = tid; i < 32 * 32; i += kSelThreads) {  // stage R[k][c] and Pinv[k][c]
@@ -683,14 +685,15 @@ __device__ void build_y_block(const SelArgs& a, int g, const Lazy& L) {
         int32_t x = yv > (p - 1) / 2 ? (int32_t)yv - (int32_t)p : (int32_t)yv;
         for (int l = 0; l < 4; ++l) {
             const int8_t dg = (int8_t)(x & 0xff);
-            sB[l][c + 32 * (s >> 4)][s & 15] = dg;
+            sB[c >> 4][l][(c & 15) + 16 * (s >> 3)][s & 7] = dg;
             x = (x - dg) >> 8;
         }
     }
     __syncthreads();
-    {
-        const int l = tid >> 6, L2 = tid & 63;
-        *(v4i*)(a.yfrag + ((int64_t)g * 4 + l) * 1024 + L2 * 16) = *(const v4i*)&sB[l][L2][0];
+    {  // plane l of 16-column block b at (4 b + l) * 512 bytes; 16 bytes (two lanes) per thread
+        const int half = tid >> 7, l = (tid >> 5) & 3, L2 = (tid & 31) * 2;
+        *(v4i*)(a.yfrag + ((int64_t)(2 * g + half) * 4 + l) * 512 + L2 * 8) =
+            *(const v4i*)&sB[half][l][L2][0];
     }
 }
 
