@@ -154,15 +154,22 @@ __device__ void solve_one(const SysDesc& d, BatchLds& L) {
         // rows are zero before j0, so PN is too)
         const int c0 = j0 & ~3;
         const int ngroups = (ncols - c0 + 3) >> 2;
+        // (all kPB terms are evaluated with every load issued first: beyond np
+        // the coefficients are zero and the row index is clamped to pivot 0)
         for (int i = tid; i < np * ngroups; i += kThreads) {
             const int t = i / ngroups, c = c0 + 4 * (i % ngroups);
             const int qt = L.pivrow[rank + t];
+            uint4 wv[kPB];
+#pragma unroll
+            for (int sidx = 0; sidx < kPB; ++sidx)
+                wv[sidx] = *(const uint4*)(d.W + (int64_t)L.pivrow[rank + (sidx < np ? sidx : 0)] * ldw + c);
             double s1[4] = {0.0, 0.0, 0.0, 0.0}, s0[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int sidx = 0; sidx < np; ++sidx) {
+#pragma unroll
+            for (int sidx = 0; sidx < kPB; ++sidx) {
                 const uint32_t tv = L.T[qt * kPB + sidx];
-                const uint4 wv = *(const uint4*)(d.W + (int64_t)L.pivrow[rank + sidx] * ldw + c);
                 const double hi = (double)(tv >> 16), lo = (double)(tv & 0xffffu);
-                const uint32_t w4[4] = {wv.x, wv.y, wv.z, wv.w};
+                const uint32_t w4[4] = {wv[sidx].x, wv[sidx].y, wv[sidx].z, wv[sidx].w};
+#pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     s1[e] = __fma_rn(hi, (double)w4[e], s1[e]);
                     s0[e] = __fma_rn(lo, (double)w4[e], s0[e]);
@@ -187,21 +194,29 @@ __device__ void solve_one(const SysDesc& d, BatchLds& L) {
                 *dst = *(const uint4*)(PN + (int64_t)L.pt[r] * ldw + c);
                 continue;
             }
+            uint32_t a[kPB];  // zero beyond np
             bool any = false;
-            for (int t = 0; t < np; ++t) any |= L.P[r * kPB + t] != 0;
+#pragma unroll
+            for (int t = 0; t < kPB; ++t) {
+                a[t] = L.P[r * kPB + t];
+                any |= a[t] != 0;
+            }
             if (!any) continue;
+            uint4 pv[kPB];
+#pragma unroll
+            for (int t = 0; t < kPB; ++t) pv[t] = *(const uint4*)(PN + (int64_t)(t < np ? t : 0) * ldw + c);
+            const uint4 x = *dst;
             double s1[4] = {0.0, 0.0, 0.0, 0.0}, s0[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int t = 0; t < np; ++t) {
-                const uint32_t a = L.P[r * kPB + t];
-                const uint4 pv = *(const uint4*)(PN + (int64_t)t * ldw + c);
-                const double hi = (double)(a >> 16), lo = (double)(a & 0xffffu);
-                const uint32_t p4[4] = {pv.x, pv.y, pv.z, pv.w};
+#pragma unroll
+            for (int t = 0; t < kPB; ++t) {
+                const double hi = (double)(a[t] >> 16), lo = (double)(a[t] & 0xffffu);
+                const uint32_t p4[4] = {pv[t].x, pv[t].y, pv[t].z, pv[t].w};
+#pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     s1[e] = __fma_rn(hi, (double)p4[e], s1[e]);
                     s0[e] = __fma_rn(lo, (double)p4[e], s0[e]);
                 }
             }
-            const uint4 x = *dst;
             const uint32_t x4[4] = {x.x, x.y, x.z, x.w};
             uint32_t o[4];
             for (int e = 0; e < 4; ++e) o[e] = sub_mod(x4[e], split_reduce(s1[e], s0[e], F), p);
