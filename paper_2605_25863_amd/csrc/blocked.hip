@@ -72,15 +72,25 @@ __global__ __launch_bounds__(kThreads) void panel_extract_kernel(int32_t m, Mat 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t d0 = (int64_t)blockIdx.y * 256 + lane * 4;
     const int row0 = blockIdx.x * kTileRows + wave * 8;
+    // all eight rows' loads first (128-bit where the four columns are inside
+    // the panel: c0 and d0 are multiples of 4), then the stores
+    uint4 v[8];
+#pragma unroll
+    for (int rr = 0; rr < 8; ++rr) {
+        const int64_t r = row0 + rr < m ? row0 + rr : m - 1;
+        const uint32_t* srow = src.M + r * src.ld + c0;
+        if (d0 + 3 < width) {
+            v[rr] = *(const uint4*)(srow + d0);
+        } else {
+            uint32_t x[4];
+            for (int e = 0; e < 4; ++e) x[e] = d0 + e < width ? srow[d0 + e] : 0u;
+            v[rr] = make_uint4(x[0], x[1], x[2], x[3]);
+        }
+    }
+#pragma unroll
     for (int rr = 0; rr < 8; ++rr) {
         const int r = row0 + rr;
-        if (r >= m || d0 >= dst.ld) continue;
-        uint32_t v[4];
-        for (int e = 0; e < 4; ++e) {
-            const int64_t c = d0 + e;
-            v[e] = c < width ? src.M[(int64_t)r * src.ld + c0 + c] : 0u;
-        }
-        *(uint4*)(dst.M + (int64_t)r * dst.ld + d0) = make_uint4(v[0], v[1], v[2], v[3]);
+        if (r < m && d0 < dst.ld) *(uint4*)(dst.M + (int64_t)r * dst.ld + d0) = v[rr];
     }
 }
 
@@ -138,12 +148,25 @@ __global__ void build_a_kernel(PlainArgs w, Mat ebuf, int64_t ecol0, int32_t wj,
     const int64_t rb = t / KB;
     const int64_t row = rb * 32 + (L & 31);
     const uint32_t p = w.F.p;
+    const int k0 = kb * 32 + 16 * (L >> 5);
+    uint32_t ev[16];
+    if (row < w.m && k0 + 15 < wj && (ecol0 & 3) == 0) {  // 128-bit loads (row starts and k0 are multiples of 4)
+        const uint4* src = (const uint4*)(ebuf.M + row * ebuf.ld + ecol0 + k0);
+        for (int q = 0; q < 4; ++q) {
+            const uint4 x = src[q];
+            ev[4 * q] = x.x;
+            ev[4 * q + 1] = x.y;
+            ev[4 * q + 2] = x.z;
+            ev[4 * q + 3] = x.w;
+        }
+    } else {
+        for (int i = 0; i < 16; ++i)
+            ev[i] = (row < w.m && k0 + i < wj) ? ebuf.M[row * ebuf.ld + ecol0 + k0 + i] : 0u;
+    }
     int8_t out[4][16];
     for (int i = 0; i < 16; ++i) {
-        const int k = kb * 32 + 16 * (L >> 5) + i;
-        uint32_t e = (row < w.m && k < wj) ? ebuf.M[row * ebuf.ld + ecol0 + k] : 0u;
         int8_t d[4];
-        digits4(centre(e, p), d);
+        digits4(centre(ev[i], p), d);
         for (int l = 0; l < 4; ++l) out[l][i] = d[l];
     }
     int8_t* base = Afrag + ((rb * KB + kb) * 4) * 1024 + L * 16;
