@@ -78,3 +78,43 @@ def test_c4_full_batch(gpu):
         assert r == (n - 1 if s["deficient"] else n)
         assert cons.all()  # dependent rows were built on [A | B]
         assert np.array_equal(oracle.matmul_mod(s["A"], X, s["p"]), s["B"].astype(np.uint64))
+
+
+def _lowrank(rng, m, n, r, p):
+    """(U V) mod p with small factors (entries below 2^15, so int64 sums are exact)."""
+    U = rng.integers(0, 1 << 15, size=(m, r), dtype=np.int64)
+    V = rng.integers(0, 1 << 15, size=(r, n), dtype=np.int64)
+    return ((U @ V) % p).astype(np.uint32)
+
+
+def test_passes_at_the_limits(gpu):
+    """The batched kernel reduces a system in passes of 8 pivot columns: systems
+    at the size limits of one workgroup (1024 rows, n + k = 2048), passes that
+    hold free columns, passes cut short when the rank reaches m, rank-deficient
+    and inconsistent systems, p = 2 and 3, and an all-zero system."""
+    rng = np.random.default_rng(77)
+    systems = []
+
+    def add(A, B, p):
+        systems.append(dict(A=np.ascontiguousarray(A, dtype=np.uint32),
+                            B=np.ascontiguousarray(B, dtype=np.uint32), p=int(p)))
+
+    p31 = workloads.draw_prime31(rng)
+    add(workloads.uniform(rng, (1024, 1000), p31), workloads.uniform(rng, (1024, 8), p31), p31)
+    add(workloads.uniform(rng, (300, 2040), p31), workloads.uniform(rng, (300, 8), p31), p31)
+    add(workloads.uniform(rng, (1024, 64), p31), workloads.uniform(rng, (1024, 3), p31), p31)
+    add(workloads.uniform(rng, (500, 400), 2), workloads.uniform(rng, (500, 4), 2), 2)
+    add(_lowrank(rng, 400, 400, 37, 3), workloads.uniform(rng, (400, 3), 3), 3)
+    A = workloads.uniform(rng, (512, 480), p31)
+    A[:, ::7] = 0  # free columns inside most passes
+    add(A, workloads.uniform(rng, (512, 5), p31), p31)
+    A = workloads.uniform(rng, (512, 480), p31)
+    A[:, 9::11] = A[:, 3::11][:, : A[:, 9::11].shape[1]]  # repeated columns: free later on
+    add(A, workloads.uniform(rng, (512, 5), p31), p31)
+    A = _lowrank(rng, 600, 500, 45, p31)
+    B = np.concatenate([_lowrank(rng, 600, 3, 45, p31), workloads.uniform(rng, (600, 3), p31)], axis=1)
+    add(A, B, p31)  # rank 45 (w.h.p.); random right-hand sides are inconsistent
+    add(np.zeros((64, 64), dtype=np.uint32), workloads.uniform(rng, (64, 2), p31), p31)
+    add(workloads.uniform(rng, (7, 1500), p31), workloads.uniform(rng, (7, 1), p31), p31)
+    print("limits batch", [(s["A"].shape, s["B"].shape[1], s["p"]) for s in systems], flush=True)
+    _check_all(systems, lx.solve_batched(systems), tag="limits")
