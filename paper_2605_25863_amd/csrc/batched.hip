@@ -10,21 +10,22 @@
 // Per system, Gauss-Jordan (Sec. 3.2) in passes of kPB pivot columns, so that
 // the system streams through the memory system once per pass, not once per
 // column (with a thousand systems in flight they do not stay in cache):
-//   1. the pass's columns of every row are copied to LDS and reduced there:
-//      pivot = the smallest non-pivot row with a non-zero entry, one modular
-//      inverse per pivot, every other eligible row updated; each row also
-//      tracks the coefficients of its current values over the pass's pivot
-//      rows as they were at the pass start;
+//   1. the pass's columns of every candidate row are copied to LDS and
+//      eliminated there to find the pivots: pivot = the smallest non-pivot
+//      row with a non-zero entry; the elimination is fraction-free (no
+//      inverse on this serial chain);
 //   2. the pass's pivot rows fully reduced (unit vectors at the pass's pivot
-//      columns): PN_t = sum_s T[q_t][s] row_{q_s}, kPB-term dot products over
-//      the full width;
+//      columns): PN_t = sum_s T[t][s] row_{q_s}, with T the inverse of the
+//      pivot block M[s][u] = row_{q_s}[col_u] (one wave, one inverse per pivot
+//      in parallel), kPB-term dot products over the full width;
 //   3. every other row r (earlier pivots included) becomes r - sum_t
 //      r[col_t] PN_t, the unique row of its coset with zeros at the pass's
 //      pivot columns, and the pivot rows become PN.
-// The dot products run in FP64 with the multiplier split into 16-bit halves,
-// so every partial sum is exact (below 2^53).  Rows are never moved: pivot s
-// is recorded in LDS.  Finally rank, pivots, X (free variables 0) and
-// consistency are written.
+// The dot products run in FP64 with one factor split into 16-bit halves, so
+// every partial sum is exact (below 2^53); step 3, a product of the rows'
+// multipliers by the reduced pivot rows, runs on the FP64 matrix cores.  Rows
+// are never moved: pivot s is recorded in LDS.  Finally rank, pivots, X (free
+// variables 0) and consistency are written.
 #include <vector>
 
 #include "internal.h"
@@ -37,6 +38,16 @@ constexpr int kThreads = 256;
 constexpr int kMaxRows = 1024;   // LDS bookkeeping bound per system
 constexpr int kMaxCols = 2048;   // n + k bound
 constexpr int kPB = 8;           // pivot columns per pass
+
+// Global-memory views of the descriptor's pointers.  The descriptor is read
+// from memory, so through its generic pointers every access would compile to a
+// flat access, which counts against both the vector-memory and the LDS wait
+// counters and so serialises loads with LDS traffic.
+typedef __attribute__((address_space(1))) uint32_t gu32;
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) v4u gu4;
+typedef __attribute__((address_space(1))) int32_t gi32;
+typedef __attribute__((address_space(1))) uint8_t gu8;
 
 struct SysDesc {
     const uint32_t* A;
@@ -76,97 +87,302 @@ __device__ __forceinline__ uint32_t split_reduce(double s1, double s0, const Fie
     return (uint32_t)y;
 }
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// (d x - f y) mod p for residues d, x, f, y: each product is reduced exactly
+// as in mul_mod (to [-p, 2p)), then the difference (-3p, 3p) is reduced.
+__device__ __forceinline__ uint32_t mul_sub_mod(double d, uint32_t x, double f, double y,
+                                                const FieldConst& F) {
+    const double dx = (double)x;
+    const double h1 = d * dx, l1 = __fma_rn(d, dx, -h1);
+    const double h2 = f * y, l2 = __fma_rn(f, y, -h2);
+    const double r1 = __fma_rn(-floor(h1 * F.pinv), F.dp, h1) + l1;
+    const double r2 = __fma_rn(-floor(h2 * F.pinv), F.dp, h2) + l2;
+    double r = r1 - r2;
+    r = __fma_rn(-floor(r * F.pinv), F.dp, r);  // [-p, 2p)
+    if (r < 0.0) r += F.dp;
+    if (r >= F.dp) r -= F.dp;
+    return (uint32_t)r;
+}
+
+// x - (s1 2^16 + s0) mod p for x < p and the exact sums s1 < 2^50, s0 < 2^51.
+__device__ __forceinline__ uint32_t sub_split(uint32_t x, double s1, double s0, const FieldConst& F) {
+    double q = floor(s1 * F.pinv);
+    const double h = __fma_rn(-q, F.dp, s1);           // (-p, 2p)
+    double y = __fma_rn(-h, 65536.0, (double)x - s0);  // |y| < 2^52
+    q = floor(y * F.pinv);
+    y = __fma_rn(-q, F.dp, y);  // [-p, 2p)
+    if (y < 0.0) y += F.dp;
+    if (y >= F.dp) y -= F.dp;
+    return (uint32_t)y;
+}
+
 // LDS of one system: pivot state per row (0 candidate, 1 pivot of an earlier
 // pass, 2 pivot of this pass), the pivot list, the pass's panel (later the
-// rows' multipliers) and coefficient tracks, and each pass pivot's index.
+// rows' multipliers), each pass pivot's index, and the coefficients T of the
+// reduced pivot rows over the pass-start pivot rows.
 struct BatchLds {
     uint8_t piv[kMaxRows];
     int8_t pt[kMaxRows];
     int32_t pivrow[kMaxRows];
     int32_t pivcol[kMaxRows];
     uint32_t P[kMaxRows * kPB];
-    uint32_t T[kMaxRows * kPB];
+    uint32_t T[kPB * kPB];
+    uint8_t cons[kMaxCols];
     int red[4];
 };
+
+// T = M^-1 for the pass's pivot block M[s][u] = row_{q_s}[col_u] (pass-start
+// values), by one wave: Gauss-Jordan on [M | I] in the pivot order (every
+// leading block is invertible: it is what the pass eliminated), fraction-free
+// (row_r <- d_s row_r - M[r][s] row_s, no inverse per step), then each row
+// scaled by the inverse of its diagonal entry.  Lane (s, u) = (lane / 8,
+// lane % 8) holds M[s][u] and I[s][u].
+__device__ void pivot_block_inverse(const SysDesc& d, BatchLds& L, int rank, int np) {
+    const int lane = threadIdx.x & 63, s = lane >> 3, u = lane & 7;
+    const FieldConst& F = d.F;
+    const bool in = s < np && u < np;
+    const gu32* W = (const gu32*)d.W;
+    uint32_t mv = in ? W[(int64_t)L.pivrow[rank + s] * d.ldw + L.pivcol[rank + u]] : 0u;
+    uint32_t iv = s == u ? 1u : 0u;
+    for (int t = 0; t < np; ++t) {
+        const uint32_t dt = __shfl(mv, t * 9);
+        const uint32_t f = __shfl(mv, s * 8 + t);
+        const uint32_t my = __shfl(mv, t * 8 + u), iy = __shfl(iv, t * 8 + u);
+        if (s != t) {
+            mv = mul_sub_mod((double)dt, mv, (double)f, (double)my, F);
+            iv = mul_sub_mod((double)dt, iv, (double)f, (double)iy, F);
+        }
+    }
+    const uint32_t ds = __shfl(mv, s * 9);
+    if (in) L.T[s * kPB + u] = mul_mod(iv, inv_mod_fermat(ds, F), F);
+}
+
+// Step 3 of a pass: r <- r - sum_t a_r[t] PN_t for the rows with a non-zero
+// multiplier, as the transposed product (width x kPB) by (kPB x 16 rows) on
+// the 16x16x4 FP64 MFMA, the multipliers split into 16-bit halves (a = hi
+// 2^16 + lo, two products).  Lane L (j = L % 16, g = L / 16) supplies
+// PN[4 kb + g][tile column 4 (j % 4) + j / 4] and the halves of a[16 rb + j]
+// [4 kb + g]; its four results are then row 16 rb + j at the tile columns 4 g
+// .. 4 g + 3, one 16-byte load and store.  Products are below 2^47 and sums of
+// kPB of them below 2^50, so the MFMA sums are exact.  A wave takes 16 rows by
+// kStrip tiles, all loads issued first.
+constexpr int kStrip = 4;
+
+__device__ void update_rows(const SysDesc& d, const BatchLds& L, const gu32* PN, int np,
+                            int c0) {
+    gu32* W = (gu32*)d.W;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int m = d.m, ncols = d.n + d.k, ldw = d.ldw;
+    const int nrb = (m + 15) >> 4, nct = (ncols - c0 + 15) >> 4;
+    const int nst = (nct + kStrip - 1) / kStrip;
+    const int j = lane & 15, g = lane >> 4;
+    const int acol = 4 * (j & 3) + (j >> 2);
+    const int t0 = min(g, np - 1), t1 = min(4 + g, np - 1);
+    for (int item = wave; item < nrb * nst; item += kThreads / 64) {
+        const int rb = item / nst, st = item - rb * nst;
+        const int row = rb * 16 + j;
+        const bool rin = row < m;
+        // every load below is unconditional, from a clamped address (a load
+        // under a branch would be waited for before the join)
+        const int rowc = rin ? row : m - 1;
+        uint32_t a0 = L.P[rowc * kPB + g], a1 = L.P[rowc * kPB + 4 + g];
+        const bool pivot = rin && L.piv[rowc] == 2;
+        const int prow = L.pt[rowc];
+        a0 = rin ? a0 : 0u;
+        a1 = rin ? a1 : 0u;
+        if (!__any((a0 | a1) != 0u || pivot)) continue;
+        // a pivot row of the pass (zero multipliers) reads its PN row and so
+        // takes it unchanged
+        const gu32* xrow = pivot ? PN + (int64_t)prow * ldw : W + (int64_t)rowc * ldw;
+        v4u x[kStrip];
+        double b0[kStrip], b1[kStrip];
+        uint32_t pb0[kStrip], pb1[kStrip];
+#pragma unroll
+        for (int e = 0; e < kStrip; ++e) {  // PN first: the MFMAs need it first
+            const int ca = min(c0 + (st * kStrip + e) * 16 + acol, ldw - 1);
+            pb0[e] = PN[(int64_t)t0 * ldw + ca];
+            pb1[e] = PN[(int64_t)t1 * ldw + ca];
+        }
+#pragma unroll
+        for (int e = 0; e < kStrip; ++e)
+            x[e] = *(const gu4*)(xrow + min(c0 + (st * kStrip + e) * 16 + 4 * g, ldw - 4));
+#pragma unroll
+        for (int e = 0; e < kStrip; ++e) {
+            b0[e] = (double)pb0[e];
+            b1[e] = (double)pb1[e];
+        }
+        const double h0 = (double)(a0 >> 16), l0 = (double)(a0 & 0xffffu);
+        const double h1 = (double)(a1 >> 16), l1 = (double)(a1 & 0xffffu);
+#pragma unroll
+        for (int e = 0; e < kStrip; ++e) {
+            const int tc = c0 + (st * kStrip + e) * 16;
+            if (tc >= ncols) break;
+            v4d hi = (v4d){0.0, 0.0, 0.0, 0.0}, lo = (v4d){0.0, 0.0, 0.0, 0.0};
+            hi = __builtin_amdgcn_mfma_f64_16x16x4f64(b0[e], h0, hi, 0, 0, 0);
+            lo = __builtin_amdgcn_mfma_f64_16x16x4f64(b0[e], l0, lo, 0, 0, 0);
+            hi = __builtin_amdgcn_mfma_f64_16x16x4f64(b1[e], h1, hi, 0, 0, 0);
+            lo = __builtin_amdgcn_mfma_f64_16x16x4f64(b1[e], l1, lo, 0, 0, 0);
+            const int cx = tc + 4 * g;
+            if (rin && cx < ncols)
+                *(gu4*)(W + (int64_t)row * ldw + cx) =
+                    (v4u){sub_split(x[e].x, hi[0], lo[0], d.F), sub_split(x[e].y, hi[1], lo[1], d.F),
+                               sub_split(x[e].z, hi[2], lo[2], d.F), sub_split(x[e].w, hi[3], lo[3], d.F)};
+        }
+    }
+}
+
+// dst[r][c] = src[r][c] for r < rows, c < cols: a wave per row, a lane per
+// column, kStageRows rows of loads in flight before their stores.
+constexpr int kStageRows = 8;
+
+__device__ void copy_block(gu32* dst, int ldd, const gu32* src, int lds, int rows, int cols) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    constexpr int nw = kThreads / 64;
+    for (int c0 = 0; c0 < cols; c0 += 64) {
+        const int c = c0 + lane, cc = min(c, cols - 1);
+        for (int r0 = wave; r0 < rows; r0 += nw * kStageRows) {
+            uint32_t v[kStageRows];
+#pragma unroll
+            for (int u = 0; u < kStageRows; ++u)
+                v[u] = src[(int64_t)min(r0 + nw * u, rows - 1) * lds + cc];
+#pragma unroll
+            for (int u = 0; u < kStageRows; ++u)
+                if (r0 + nw * u < rows && c < cols) dst[(int64_t)(r0 + nw * u) * ldd + c] = v[u];
+        }
+    }
+}
+
+// Element c (wave-uniform, < 8) of the eight values in v.
+__device__ __forceinline__ uint32_t pick8(const v4u (&v)[2], int c) {
+    const v4u h = c < 4 ? v[0] : v[1];
+    const int e = c & 3;
+    return e == 0 ? h.x : (e == 1 ? h.y : (e == 2 ? h.z : h.w));
+}
+
+constexpr int kRowsPerThread = kMaxRows / kThreads;
 
 __device__ void solve_one(const SysDesc& d, BatchLds& L) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = d.m, n = d.n, k = d.k, ncols = n + k, ldw = d.ldw;
     const FieldConst F = d.F;
-    const uint32_t p = F.p;
-    uint32_t* PN = d.W + (int64_t)m * ldw;  // the pass's reduced pivot rows
-    // stage [A | B] (padding columns zero); one wave per row
-    for (int r = wave; r < m; r += 4) {
-        for (int c = lane; c < ldw; c += 64) {
-            d.W[(int64_t)r * ldw + c] = c < n ? d.A[(int64_t)r * d.lda + c]
-                                              : (c < ncols ? d.B[(int64_t)r * d.ldb + (c - n)] : 0u);
-        }
-    }
+    gu32* W = (gu32*)d.W;
+    gu32* PN = W + (int64_t)m * ldw;  // the pass's reduced pivot rows
+    gu32* X = (gu32*)d.X;
+    // stage [A | B] (padding columns zero)
+    if (n > 0) copy_block(W, ldw, (const gu32*)d.A, d.lda, m, n);
+    if (k > 0) copy_block(W + n, ldw, (const gu32*)d.B, d.ldb, m, k);
+    for (int r = tid; r < m; r += kThreads)
+        for (int c = ncols; c < ldw; ++c) W[(int64_t)r * ldw + c] = 0u;
     for (int r = tid; r < m; r += kThreads) L.piv[r] = 0;
+    __threadfence_block();
     __syncthreads();
+    const int nri = (m + kThreads - 1) / kThreads;  // rows per thread: tid + kThreads u
     int rank = 0;
     for (int j0 = 0; j0 < n && rank < m; j0 += kPB) {
         const int bw = min(kPB, n - j0);
-        // 1. the pass's columns of the candidate rows, and empty tracks
-        for (int i = tid; i < m * kPB; i += kThreads) {
-            const int r = i / kPB, c = i % kPB;
-            L.P[i] = (c < bw && L.piv[r] == 0) ? d.W[(int64_t)r * ldw + j0 + c] : 0u;
-            L.T[i] = 0u;
+        // 1. the pass's columns of every row (pass-start values, kept in
+        // registers for the multipliers), the candidates' copied to LDS and
+        // eliminated there.  Each thread owns rows tid, tid + kThreads, ...:
+        // it alone reads and writes their state, so between columns only the
+        // pivot row crosses threads, published by the barriers of the pivot
+        // search.  (j0 <= ldw - 4; a clamped second half is never used.)
+        v4u raw[kRowsPerThread][2];
+#pragma unroll
+        for (int u = 0; u < kRowsPerThread; ++u) {
+            if (u >= nri) break;
+            const gu32* rp = W + (int64_t)min(tid + kThreads * u, m - 1) * ldw;
+            raw[u][0] = *(const gu4*)(rp + j0);
+            raw[u][1] = *(const gu4*)(rp + min(j0 + 4, ldw - 4));
         }
-        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kRowsPerThread; ++u) {
+            const int r = tid + kThreads * u;
+            if (u >= nri || r >= m) break;
+            const bool cand = L.piv[r] == 0;
+            v4u lo = raw[u][0], hi = raw[u][1];
+            lo.x = cand ? lo.x : 0u;
+            lo.y = cand && bw > 1 ? lo.y : 0u;
+            lo.z = cand && bw > 2 ? lo.z : 0u;
+            lo.w = cand && bw > 3 ? lo.w : 0u;
+            hi.x = cand && bw > 4 ? hi.x : 0u;
+            hi.y = cand && bw > 5 ? hi.y : 0u;
+            hi.z = cand && bw > 6 ? hi.z : 0u;
+            hi.w = cand && bw > 7 ? hi.w : 0u;
+            *(v4u*)&L.P[r * kPB] = lo;
+            *(v4u*)&L.P[r * kPB + 4] = hi;
+        }
         int np = 0;
         for (int c = 0; c < bw && rank + np < m; ++c) {
             int cand = INT32_MAX;
             for (int r = tid; r < m; r += kThreads)
-                if (L.piv[r] == 0 && L.P[r * kPB + c] != 0 && r < cand) cand = r;
-            const int q = block_min(cand, L.red);  // its barriers also publish the panel
-            if (q == INT32_MAX) continue;          // free column
-            const uint32_t inv = inv_mod_fermat(__builtin_amdgcn_readfirstlane(L.P[q * kPB + c]), F);
-            // row q becomes pivot np of the pass: its own term turns into an
-            // explicit coefficient, then the row is scaled to a leading 1
-            if (tid < kPB) {
-                const uint32_t tq = tid == np ? 1u : L.T[q * kPB + tid];
-                L.T[q * kPB + tid] = mul_mod(tq, inv, F);
-                L.P[q * kPB + tid] = mul_mod(L.P[q * kPB + tid], inv, F);
-            }
-            if (tid == 0) {
+                if (L.piv[r] == 0 && L.P[r * kPB + c] != 0) {
+                    cand = r;
+                    break;
+                }
+            const int q = block_min(cand, L.red);
+            if (q == INT32_MAX) continue;  // free column
+            if (tid == (q & (kThreads - 1))) {
                 L.piv[q] = 2;
                 L.pt[q] = (int8_t)np;
                 L.pivrow[rank + np] = q;
                 L.pivcol[rank + np] = j0 + c;
             }
-            __syncthreads();
-            // column c out of the other candidates and the pass's earlier pivots
+            // column c out of the other candidates, fraction-free: r <- d r - f q
+            // on the later columns (the zero pattern is that of the normalised
+            // elimination, which is all the pivot search needs)
+            const double dq = (double)L.P[q * kPB + c];
             for (int r = tid; r < m; r += kThreads) {
-                if (r == q || L.piv[r] == 1) continue;
+                if (r == q || L.piv[r] != 0) continue;
                 const uint32_t f = L.P[r * kPB + c];
                 if (f == 0) continue;
-                for (int cc = 0; cc < kPB; ++cc)
-                    L.P[r * kPB + cc] = sub_mod(L.P[r * kPB + cc], mul_mod(f, L.P[q * kPB + cc], F), p);
-                for (int t = 0; t < kPB; ++t)
-                    L.T[r * kPB + t] = sub_mod(L.T[r * kPB + t], mul_mod(f, L.T[q * kPB + t], F), p);
+                const double df = (double)f;
+                for (int cc = c + 1; cc < bw; ++cc)
+                    L.P[r * kPB + cc] = mul_sub_mod(dq, L.P[r * kPB + cc], df,
+                                                    (double)L.P[q * kPB + cc], F);
             }
             ++np;
-            __syncthreads();
         }
         if (np == 0) continue;
-        // 2. PN_t = sum_s T[q_t][s] row_{q_s} over 4-column groups from c0 (the
+        __syncthreads();
+        // coefficients of the reduced pivot rows (wave 0), and the rows'
+        // multipliers: their pass-start values at the pass's pivot columns
+        // (zero for the pass's pivot rows)
+        if (wave == 0) pivot_block_inverse(d, L, rank, np);
+        int pc[kPB];
+#pragma unroll
+        for (int t = 0; t < kPB; ++t)
+            pc[t] = __builtin_amdgcn_readfirstlane(t < np ? L.pivcol[rank + t] - j0 : 0);
+#pragma unroll
+        for (int u = 0; u < kRowsPerThread; ++u) {
+            const int r = tid + kThreads * u;
+            if (u >= nri || r >= m) break;
+            const bool live = L.piv[r] != 2;
+            uint32_t a[kPB];
+#pragma unroll
+            for (int t = 0; t < kPB; ++t) a[t] = live && t < np ? pick8(raw[u], pc[t]) : 0u;
+            *(v4u*)&L.P[r * kPB] = (v4u){a[0], a[1], a[2], a[3]};
+            *(v4u*)&L.P[r * kPB + 4] = (v4u){a[4], a[5], a[6], a[7]};
+        }
+        __syncthreads();
+        // 2. PN_t = sum_s T[t][s] row_{q_s} over 4-column groups from c0 (the
         // rows are zero before j0, so PN is too)
-        const int c0 = j0 & ~3;
+        const int c0 = j0 & ~15;
         const int ngroups = (ncols - c0 + 3) >> 2;
         // (all kPB terms are evaluated with every load issued first: beyond np
         // the coefficients are zero and the row index is clamped to pivot 0)
         for (int i = tid; i < np * ngroups; i += kThreads) {
             const int t = i / ngroups, c = c0 + 4 * (i % ngroups);
-            const int qt = L.pivrow[rank + t];
-            uint4 wv[kPB];
+            v4u wv[kPB];
 #pragma unroll
             for (int sidx = 0; sidx < kPB; ++sidx)
-                wv[sidx] = *(const uint4*)(d.W + (int64_t)L.pivrow[rank + (sidx < np ? sidx : 0)] * ldw + c);
+                wv[sidx] = *(const gu4*)(W + (int64_t)L.pivrow[rank + (sidx < np ? sidx : 0)] * ldw + c);
             double s1[4] = {0.0, 0.0, 0.0, 0.0}, s0[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int sidx = 0; sidx < kPB; ++sidx) {
-                const uint32_t tv = L.T[qt * kPB + sidx];
+                const uint32_t tv = sidx < np ? L.T[t * kPB + sidx] : 0u;
                 const double hi = (double)(tv >> 16), lo = (double)(tv & 0xffffu);
                 const uint32_t w4[4] = {wv[sidx].x, wv[sidx].y, wv[sidx].z, wv[sidx].w};
 #pragma unroll
@@ -177,51 +393,13 @@ __device__ void solve_one(const SysDesc& d, BatchLds& L) {
             }
             uint32_t o[4];
             for (int e = 0; e < 4; ++e) o[e] = split_reduce(s1[e], s0[e], F);
-            *(uint4*)(PN + (int64_t)t * ldw + c) = make_uint4(o[0], o[1], o[2], o[3]);
-        }
-        // the rows' multipliers: their pass-start values at the pass's pivot columns
-        for (int i = tid; i < m * kPB; i += kThreads) {
-            const int r = i / kPB, t = i % kPB;
-            L.P[i] = (t < np && L.piv[r] != 2) ? d.W[(int64_t)r * ldw + L.pivcol[rank + t]] : 0u;
+            *(gu4*)(PN + (int64_t)t * ldw + c) = (v4u){o[0], o[1], o[2], o[3]};
         }
         __threadfence_block();
         __syncthreads();
-        // 3. r <- r - sum_t a_r[t] PN_t for every other row; the pivots take PN
-        for (int i = tid; i < m * ngroups; i += kThreads) {
-            const int r = i / ngroups, c = c0 + 4 * (i % ngroups);
-            uint4* dst = (uint4*)(d.W + (int64_t)r * ldw + c);
-            if (L.piv[r] == 2) {
-                *dst = *(const uint4*)(PN + (int64_t)L.pt[r] * ldw + c);
-                continue;
-            }
-            uint32_t a[kPB];  // zero beyond np
-            bool any = false;
-#pragma unroll
-            for (int t = 0; t < kPB; ++t) {
-                a[t] = L.P[r * kPB + t];
-                any |= a[t] != 0;
-            }
-            if (!any) continue;
-            uint4 pv[kPB];
-#pragma unroll
-            for (int t = 0; t < kPB; ++t) pv[t] = *(const uint4*)(PN + (int64_t)(t < np ? t : 0) * ldw + c);
-            const uint4 x = *dst;
-            double s1[4] = {0.0, 0.0, 0.0, 0.0}, s0[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int t = 0; t < kPB; ++t) {
-                const double hi = (double)(a[t] >> 16), lo = (double)(a[t] & 0xffffu);
-                const uint32_t p4[4] = {pv[t].x, pv[t].y, pv[t].z, pv[t].w};
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    s1[e] = __fma_rn(hi, (double)p4[e], s1[e]);
-                    s0[e] = __fma_rn(lo, (double)p4[e], s0[e]);
-                }
-            }
-            const uint32_t x4[4] = {x.x, x.y, x.z, x.w};
-            uint32_t o[4];
-            for (int e = 0; e < 4; ++e) o[e] = sub_mod(x4[e], split_reduce(s1[e], s0[e], F), p);
-            *dst = make_uint4(o[0], o[1], o[2], o[3]);
-        }
+        // 3. every row with a non-zero multiplier updated, the pass's pivot
+        // rows replaced by PN
+        update_rows(d, L, PN, np, c0);
         __threadfence_block();
         __syncthreads();
         for (int r = tid; r < m; r += kThreads)
@@ -231,23 +409,43 @@ __device__ void solve_one(const SysDesc& d, BatchLds& L) {
     }
     // outputs: rank, pivots (ascending by construction), consistency, X
     const int mn = min(m, n);
-    if (tid == 0) *d.rank = rank;
-    for (int s = tid; s < mn; s += kThreads) d.pivots[s] = s < rank ? L.pivcol[s] : -1;
-    for (int t = tid; t < k; t += kThreads) d.consistent[t] = 1;
-    for (int64_t i = tid; i < (int64_t)n * k; i += kThreads) d.X[(i / k) * d.ldx + (i % k)] = 0u;
+    if (tid == 0) *(gi32*)d.rank = rank;
+    for (int s = tid; s < mn; s += kThreads) ((gi32*)d.pivots)[s] = s < rank ? L.pivcol[s] : -1;
+    for (int t = tid; t < k; t += kThreads) L.cons[t] = 1;
+    for (int64_t i = tid; i < (int64_t)n * k; i += kThreads) X[(i / k) * d.ldx + (i % k)] = 0u;
     __syncthreads();
-    // a non-pivot row with a non-zero right-hand side entry makes its column inconsistent
-    for (int r = wave; r < m; r += 4) {
-        if (L.piv[r]) continue;
-        for (int t = lane; t < k; t += 64)
-            if (d.W[(int64_t)r * ldw + n + t] != 0) d.consistent[t] = 0;
+    // a non-pivot row with a non-zero right-hand side entry makes its column
+    // inconsistent (rows with loads in flight before the flags are written)
+    for (int c0 = 0; c0 < k; c0 += 64) {
+        const int t = c0 + lane, tc = min(t, k - 1);
+        for (int r0 = wave; r0 < m; r0 += 4 * kStageRows) {
+            uint32_t v[kStageRows];
+#pragma unroll
+            for (int u = 0; u < kStageRows; ++u)
+                v[u] = W[(int64_t)min(r0 + 4 * u, m - 1) * ldw + n + tc];
+#pragma unroll
+            for (int u = 0; u < kStageRows; ++u) {
+                const int r = r0 + 4 * u;
+                if (r < m && t < k && L.piv[r] == 0 && v[u] != 0) L.cons[t] = 0;
+            }
+        }
     }
     __syncthreads();
-    for (int s = wave; s < rank; s += 4) {
-        const int col = L.pivcol[s];
-        const uint32_t* row = d.W + (int64_t)L.pivrow[s] * ldw + n;
-        for (int t = lane; t < k; t += 64)
-            if (d.consistent[t]) d.X[(int64_t)col * d.ldx + t] = row[t];
+    for (int t = tid; t < k; t += kThreads) ((gu8*)d.consistent)[t] = L.cons[t];
+    // X at the pivot columns: the reduced right-hand sides of the pivot rows
+    for (int c0 = 0; c0 < k; c0 += 64) {
+        const int t = c0 + lane, tc = min(t, k - 1);
+        for (int s0 = wave; s0 < rank; s0 += 4 * kStageRows) {
+            uint32_t v[kStageRows];
+#pragma unroll
+            for (int u = 0; u < kStageRows; ++u)
+                v[u] = W[(int64_t)L.pivrow[min(s0 + 4 * u, rank - 1)] * ldw + n + tc];
+#pragma unroll
+            for (int u = 0; u < kStageRows; ++u) {
+                const int s = s0 + 4 * u;
+                if (s < rank && t < k && L.cons[t]) X[(int64_t)L.pivcol[s] * d.ldx + t] = v[u];
+            }
+        }
     }
     __syncthreads();
 }
