@@ -37,7 +37,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kMaxRows = 1024;   // LDS bookkeeping bound per system
 constexpr int kMaxCols = 2048;   // n + k bound
-constexpr int kPB = 8;           // pivot columns per pass
+constexpr int kPB = 16;          // pivot columns per pass (a multiple of 8)
 
 // Global-memory views of the descriptor's pointers.  The descriptor is read
 // from memory, so through its generic pointers every access would compile to a
@@ -136,26 +136,52 @@ struct BatchLds {
 // values), by one wave: Gauss-Jordan on [M | I] in the pivot order (every
 // leading block is invertible: it is what the pass eliminated), fraction-free
 // (row_r <- d_s row_r - M[r][s] row_s, no inverse per step), then each row
-// scaled by the inverse of its diagonal entry.  Lane (s, u) = (lane / 8,
-// lane % 8) holds M[s][u] and I[s][u].
+// scaled by the inverse of its diagonal entry.  Entry (s, u) of M and of I
+// lives in lane s * kLpr + u / kEpl, element u % kEpl.
+constexpr int kLpr = 64 / kPB;    // lanes per row of the block
+constexpr int kEpl = kPB / kLpr;  // entries per lane
+static_assert(kEpl == 4, "the block inverse keeps four entries per lane");
+
 __device__ void pivot_block_inverse(const SysDesc& d, BatchLds& L, int rank, int np) {
-    const int lane = threadIdx.x & 63, s = lane >> 3, u = lane & 7;
+    const int lane = threadIdx.x & 63, s = lane / kLpr, ub = (lane % kLpr) * kEpl;
     const FieldConst& F = d.F;
-    const bool in = s < np && u < np;
     const gu32* W = (const gu32*)d.W;
-    uint32_t mv = in ? W[(int64_t)L.pivrow[rank + s] * d.ldw + L.pivcol[rank + u]] : 0u;
-    uint32_t iv = s == u ? 1u : 0u;
+    // vectors, not arrays: an element picked by a run-time index stays in
+    // registers
+    v4u mv, iv;
+#pragma unroll
+    for (int e = 0; e < kEpl; ++e) {
+        const int u = ub + e;
+        const int rs = L.pivrow[rank + min(s, np - 1)], cu = L.pivcol[rank + min(u, np - 1)];
+        const uint32_t w = W[(int64_t)rs * d.ldw + cu];
+        mv[e] = s < np && u < np ? w : 0u;
+        iv[e] = s == u ? 1u : 0u;
+    }
     for (int t = 0; t < np; ++t) {
-        const uint32_t dt = __shfl(mv, t * 9);
-        const uint32_t f = __shfl(mv, s * 8 + t);
-        const uint32_t my = __shfl(mv, t * 8 + u), iy = __shfl(iv, t * 8 + u);
+        const int tl = t / kEpl, te = t % kEpl;  // column t: lane offset, element
+        const uint32_t colt = mv[te];
+        const uint32_t dt = __shfl(colt, t * kLpr + tl);
+        const uint32_t f = __shfl(colt, s * kLpr + tl);
+        v4u my, iy;
+#pragma unroll
+        for (int e = 0; e < kEpl; ++e) {
+            my[e] = __shfl(mv[e], t * kLpr + lane % kLpr);
+            iy[e] = __shfl(iv[e], t * kLpr + lane % kLpr);
+        }
         if (s != t) {
-            mv = mul_sub_mod((double)dt, mv, (double)f, (double)my, F);
-            iv = mul_sub_mod((double)dt, iv, (double)f, (double)iy, F);
+#pragma unroll
+            for (int e = 0; e < kEpl; ++e) {
+                mv[e] = mul_sub_mod((double)dt, mv[e], (double)f, (double)my[e], F);
+                iv[e] = mul_sub_mod((double)dt, iv[e], (double)f, (double)iy[e], F);
+            }
         }
     }
-    const uint32_t ds = __shfl(mv, s * 9);
-    if (in) L.T[s * kPB + u] = mul_mod(iv, inv_mod_fermat(ds, F), F);
+    // the diagonal entry of row s sits in lane s * kLpr + s / kEpl, element s % kEpl
+    const uint32_t ds = __shfl(mv[s % kEpl], s * kLpr + s / kEpl);
+    const uint32_t inv = inv_mod_fermat(ds, F);
+#pragma unroll
+    for (int e = 0; e < kEpl; ++e)
+        if (s < np && ub + e < np) L.T[s * kPB + ub + e] = mul_mod(iv[e], inv, F);
 }
 
 // Step 3 of a pass: r <- r - sum_t a_r[t] PN_t for the rows with a non-zero
@@ -165,12 +191,13 @@ __device__ void pivot_block_inverse(const SysDesc& d, BatchLds& L, int rank, int
 // PN[4 kb + g][tile column 4 (j % 4) + j / 4] and the halves of a[16 rb + j]
 // [4 kb + g]; its four results are then row 16 rb + j at the tile columns 4 g
 // .. 4 g + 3, one 16-byte load and store.  Products are below 2^47 and sums of
-// kPB of them below 2^50, so the MFMA sums are exact.  A wave takes 16 rows by
+// kPB = 16 of them below 2^51, so the MFMA sums are exact.  A wave takes 16 rows by
 // kStrip tiles, all loads issued first.
 constexpr int kStrip = 4;
 
 __device__ void update_rows(const SysDesc& d, const BatchLds& L, const gu32* PN, int np,
                             int c0) {
+    constexpr int KB = kPB / 4;  // k-blocks of the MFMA
     gu32* W = (gu32*)d.W;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -179,7 +206,9 @@ __device__ void update_rows(const SysDesc& d, const BatchLds& L, const gu32* PN,
     const int nst = (nct + kStrip - 1) / kStrip;
     const int j = lane & 15, g = lane >> 4;
     const int acol = 4 * (j & 3) + (j >> 2);
-    const int t0 = min(g, np - 1), t1 = min(4 + g, np - 1);
+    int tk[KB];  // the PN row of each k-block (clamped beyond np: its multiplier is 0)
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) tk[kb] = min(4 * kb + g, np - 1);
     for (int item = wave; item < nrb * nst; item += kThreads / 64) {
         const int rb = item / nst, st = item - rb * nst;
         const int row = rb * 16 + j;
@@ -187,48 +216,52 @@ __device__ void update_rows(const SysDesc& d, const BatchLds& L, const gu32* PN,
         // every load below is unconditional, from a clamped address (a load
         // under a branch would be waited for before the join)
         const int rowc = rin ? row : m - 1;
-        uint32_t a0 = L.P[rowc * kPB + g], a1 = L.P[rowc * kPB + 4 + g];
+        uint32_t a[KB];
+        uint32_t any = 0u;
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+            a[kb] = rin ? L.P[rowc * kPB + 4 * kb + g] : 0u;
+            any |= a[kb];
+        }
         const bool pivot = rin && L.piv[rowc] == 2;
         const int prow = L.pt[rowc];
-        a0 = rin ? a0 : 0u;
-        a1 = rin ? a1 : 0u;
-        if (!__any((a0 | a1) != 0u || pivot)) continue;
+        if (!__any(any != 0u || pivot)) continue;
         // a pivot row of the pass (zero multipliers) reads its PN row and so
         // takes it unchanged
         const gu32* xrow = pivot ? PN + (int64_t)prow * ldw : W + (int64_t)rowc * ldw;
-        v4u x[kStrip];
-        double b0[kStrip], b1[kStrip];
-        uint32_t pb0[kStrip], pb1[kStrip];
+        uint32_t pb[kStrip][KB];
 #pragma unroll
         for (int e = 0; e < kStrip; ++e) {  // PN first: the MFMAs need it first
             const int ca = min(c0 + (st * kStrip + e) * 16 + acol, ldw - 1);
-            pb0[e] = PN[(int64_t)t0 * ldw + ca];
-            pb1[e] = PN[(int64_t)t1 * ldw + ca];
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) pb[e][kb] = PN[(int64_t)tk[kb] * ldw + ca];
         }
+        v4u x[kStrip];
 #pragma unroll
         for (int e = 0; e < kStrip; ++e)
             x[e] = *(const gu4*)(xrow + min(c0 + (st * kStrip + e) * 16 + 4 * g, ldw - 4));
+        double ah[KB], al[KB];
 #pragma unroll
-        for (int e = 0; e < kStrip; ++e) {
-            b0[e] = (double)pb0[e];
-            b1[e] = (double)pb1[e];
+        for (int kb = 0; kb < KB; ++kb) {
+            ah[kb] = (double)(a[kb] >> 16);
+            al[kb] = (double)(a[kb] & 0xffffu);
         }
-        const double h0 = (double)(a0 >> 16), l0 = (double)(a0 & 0xffffu);
-        const double h1 = (double)(a1 >> 16), l1 = (double)(a1 & 0xffffu);
 #pragma unroll
         for (int e = 0; e < kStrip; ++e) {
             const int tc = c0 + (st * kStrip + e) * 16;
             if (tc >= ncols) break;
             v4d hi = (v4d){0.0, 0.0, 0.0, 0.0}, lo = (v4d){0.0, 0.0, 0.0, 0.0};
-            hi = __builtin_amdgcn_mfma_f64_16x16x4f64(b0[e], h0, hi, 0, 0, 0);
-            lo = __builtin_amdgcn_mfma_f64_16x16x4f64(b0[e], l0, lo, 0, 0, 0);
-            hi = __builtin_amdgcn_mfma_f64_16x16x4f64(b1[e], h1, hi, 0, 0, 0);
-            lo = __builtin_amdgcn_mfma_f64_16x16x4f64(b1[e], l1, lo, 0, 0, 0);
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+                const double b = (double)pb[e][kb];
+                hi = __builtin_amdgcn_mfma_f64_16x16x4f64(b, ah[kb], hi, 0, 0, 0);
+                lo = __builtin_amdgcn_mfma_f64_16x16x4f64(b, al[kb], lo, 0, 0, 0);
+            }
             const int cx = tc + 4 * g;
             if (rin && cx < ncols)
                 *(gu4*)(W + (int64_t)row * ldw + cx) =
                     (v4u){sub_split(x[e].x, hi[0], lo[0], d.F), sub_split(x[e].y, hi[1], lo[1], d.F),
-                               sub_split(x[e].z, hi[2], lo[2], d.F), sub_split(x[e].w, hi[3], lo[3], d.F)};
+                          sub_split(x[e].z, hi[2], lo[2], d.F), sub_split(x[e].w, hi[3], lo[3], d.F)};
         }
     }
 }
@@ -255,14 +288,33 @@ __device__ void copy_block(gu32* dst, int ldd, const gu32* src, int lds, int row
     }
 }
 
-// Element c (wave-uniform, < 8) of the eight values in v.
-__device__ __forceinline__ uint32_t pick8(const v4u (&v)[2], int c) {
-    const v4u h = c < 4 ? v[0] : v[1];
-    const int e = c & 3;
-    return e == 0 ? h.x : (e == 1 ? h.y : (e == 2 ? h.z : h.w));
-}
-
 constexpr int kRowsPerThread = kMaxRows / kThreads;
+
+// The pass columns j0 .. j0 + kPB - 1 of the thread's rows tid + kThreads u
+// (u < nri), as one vector per row (so that a column picked by a run-time
+// index stays in registers), every load issued before any is used; rows past
+// m are clamped, and a group that would start past ldw is clamped (it then
+// holds no column of the pass: j0 + 4 h < n <= ldw for every column the pass
+// has).
+typedef uint32_t vpu __attribute__((ext_vector_type(kPB)));
+static_assert(kPB == 16, "the pass columns are four 16-byte groups");
+
+__device__ __forceinline__ void load_pass_cols(const gu32* W, int ldw, int m, int nri, int j0,
+                                               vpu (&raw)[kRowsPerThread]) {
+    v4u g[kRowsPerThread][4];
+#pragma unroll
+    for (int u = 0; u < kRowsPerThread; ++u) {
+        const gu32* rp = W + (int64_t)min((int)threadIdx.x + kThreads * min(u, nri - 1), m - 1) * ldw;
+#pragma unroll
+        for (int h = 0; h < 4; ++h) g[u][h] = *(const gu4*)(rp + min(j0 + 4 * h, ldw - 4));
+    }
+#pragma unroll
+    for (int u = 0; u < kRowsPerThread; ++u)
+        raw[u] = __builtin_shufflevector(
+            __builtin_shufflevector(g[u][0], g[u][1], 0, 1, 2, 3, 4, 5, 6, 7),
+            __builtin_shufflevector(g[u][2], g[u][3], 0, 1, 2, 3, 4, 5, 6, 7), 0, 1, 2, 3, 4, 5, 6,
+            7, 8, 9, 10, 11, 12, 13, 14, 15);
+}
 
 __device__ void solve_one(const SysDesc& d, BatchLds& L) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -283,36 +335,24 @@ __device__ void solve_one(const SysDesc& d, BatchLds& L) {
     int rank = 0;
     for (int j0 = 0; j0 < n && rank < m; j0 += kPB) {
         const int bw = min(kPB, n - j0);
-        // 1. the pass's columns of every row (pass-start values, kept in
-        // registers for the multipliers), the candidates' copied to LDS and
+        // 1. the pass's columns of the candidate rows copied to LDS and
         // eliminated there.  Each thread owns rows tid, tid + kThreads, ...:
         // it alone reads and writes their state, so between columns only the
         // pivot row crosses threads, published by the barriers of the pivot
-        // search.  (j0 <= ldw - 4; a clamped second half is never used.)
-        v4u raw[kRowsPerThread][2];
+        // search.
+        {
+            vpu raw[kRowsPerThread];
+            load_pass_cols(W, ldw, m, nri, j0, raw);
 #pragma unroll
-        for (int u = 0; u < kRowsPerThread; ++u) {
-            if (u >= nri) break;
-            const gu32* rp = W + (int64_t)min(tid + kThreads * u, m - 1) * ldw;
-            raw[u][0] = *(const gu4*)(rp + j0);
-            raw[u][1] = *(const gu4*)(rp + min(j0 + 4, ldw - 4));
-        }
+            for (int u = 0; u < kRowsPerThread; ++u) {
+                const int r = tid + kThreads * u;
+                if (u >= nri || r >= m) break;
+                const bool cand = L.piv[r] == 0;
+                vpu v = raw[u];
 #pragma unroll
-        for (int u = 0; u < kRowsPerThread; ++u) {
-            const int r = tid + kThreads * u;
-            if (u >= nri || r >= m) break;
-            const bool cand = L.piv[r] == 0;
-            v4u lo = raw[u][0], hi = raw[u][1];
-            lo.x = cand ? lo.x : 0u;
-            lo.y = cand && bw > 1 ? lo.y : 0u;
-            lo.z = cand && bw > 2 ? lo.z : 0u;
-            lo.w = cand && bw > 3 ? lo.w : 0u;
-            hi.x = cand && bw > 4 ? hi.x : 0u;
-            hi.y = cand && bw > 5 ? hi.y : 0u;
-            hi.z = cand && bw > 6 ? hi.z : 0u;
-            hi.w = cand && bw > 7 ? hi.w : 0u;
-            *(v4u*)&L.P[r * kPB] = lo;
-            *(v4u*)&L.P[r * kPB + 4] = hi;
+                for (int c = 0; c < kPB; ++c) v[c] = cand && c < bw ? v[c] : 0u;
+                *(vpu*)&L.P[r * kPB] = v;
+            }
         }
         int np = 0;
         for (int c = 0; c < bw && rank + np < m; ++c) {
@@ -349,46 +389,55 @@ __device__ void solve_one(const SysDesc& d, BatchLds& L) {
         __syncthreads();
         // coefficients of the reduced pivot rows (wave 0), and the rows'
         // multipliers: their pass-start values at the pass's pivot columns
-        // (zero for the pass's pivot rows)
+        // (zero for the pass's pivot rows), loaded again rather than held in
+        // registers through the pivot search
         if (wave == 0) pivot_block_inverse(d, L, rank, np);
-        int pc[kPB];
+        {
+            int pc[kPB];
 #pragma unroll
-        for (int t = 0; t < kPB; ++t)
-            pc[t] = __builtin_amdgcn_readfirstlane(t < np ? L.pivcol[rank + t] - j0 : 0);
+            for (int t = 0; t < kPB; ++t)
+                pc[t] = __builtin_amdgcn_readfirstlane(t < np ? L.pivcol[rank + t] - j0 : 0);
+            vpu raw[kRowsPerThread];
+            load_pass_cols(W, ldw, m, nri, j0, raw);
 #pragma unroll
-        for (int u = 0; u < kRowsPerThread; ++u) {
-            const int r = tid + kThreads * u;
-            if (u >= nri || r >= m) break;
-            const bool live = L.piv[r] != 2;
-            uint32_t a[kPB];
+            for (int u = 0; u < kRowsPerThread; ++u) {
+                const int r = tid + kThreads * u;
+                if (u >= nri || r >= m) break;
+                const bool live = L.piv[r] != 2;
+                vpu a;
 #pragma unroll
-            for (int t = 0; t < kPB; ++t) a[t] = live && t < np ? pick8(raw[u], pc[t]) : 0u;
-            *(v4u*)&L.P[r * kPB] = (v4u){a[0], a[1], a[2], a[3]};
-            *(v4u*)&L.P[r * kPB + 4] = (v4u){a[4], a[5], a[6], a[7]};
+                for (int t = 0; t < kPB; ++t) a[t] = live && t < np ? raw[u][pc[t]] : 0u;
+                *(vpu*)&L.P[r * kPB] = a;
+            }
         }
         __syncthreads();
-        // 2. PN_t = sum_s T[t][s] row_{q_s} over 4-column groups from c0 (the
-        // rows are zero before j0, so PN is too)
-        const int c0 = j0 & ~15;
+        // 2. PN_t = sum_s T[t][s] row_{q_s} over 4-column groups from c0.  Only
+        // the columns after the pass are needed from here on (later passes
+        // search there; the outputs read the right-hand sides), so steps 2 and
+        // 3 start at the first 16-aligned column after the pass, or at j0 in
+        // the last pass.
+        const int c0 = min(j0 + kPB, n) & ~15;
         const int ngroups = (ncols - c0 + 3) >> 2;
-        // (all kPB terms are evaluated with every load issued first: beyond np
-        // the coefficients are zero and the row index is clamped to pivot 0)
+        // (the terms in halves of 8, every load of a half issued first: beyond
+        // np the coefficients are zero and the row index is clamped to pivot 0)
         for (int i = tid; i < np * ngroups; i += kThreads) {
             const int t = i / ngroups, c = c0 + 4 * (i % ngroups);
-            v4u wv[kPB];
-#pragma unroll
-            for (int sidx = 0; sidx < kPB; ++sidx)
-                wv[sidx] = *(const gu4*)(W + (int64_t)L.pivrow[rank + (sidx < np ? sidx : 0)] * ldw + c);
             double s1[4] = {0.0, 0.0, 0.0, 0.0}, s0[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int s8 = 0; s8 < kPB; s8 += 8) {
+                v4u wv[8];
 #pragma unroll
-            for (int sidx = 0; sidx < kPB; ++sidx) {
-                const uint32_t tv = sidx < np ? L.T[t * kPB + sidx] : 0u;
-                const double hi = (double)(tv >> 16), lo = (double)(tv & 0xffffu);
-                const uint32_t w4[4] = {wv[sidx].x, wv[sidx].y, wv[sidx].z, wv[sidx].w};
+                for (int h = 0; h < 8; ++h)
+                    wv[h] = *(const gu4*)(W + (int64_t)L.pivrow[rank + (s8 + h < np ? s8 + h : 0)] * ldw + c);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    s1[e] = __fma_rn(hi, (double)w4[e], s1[e]);
-                    s0[e] = __fma_rn(lo, (double)w4[e], s0[e]);
+                for (int h = 0; h < 8; ++h) {
+                    const uint32_t tv = s8 + h < np ? L.T[t * kPB + s8 + h] : 0u;
+                    const double hi = (double)(tv >> 16), lo = (double)(tv & 0xffffu);
+                    const uint32_t w4[4] = {wv[h].x, wv[h].y, wv[h].z, wv[h].w};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        s1[e] = __fma_rn(hi, (double)w4[e], s1[e]);
+                        s0[e] = __fma_rn(lo, (double)w4[e], s0[e]);
+                    }
                 }
             }
             uint32_t o[4];
@@ -452,7 +501,7 @@ __device__ void solve_one(const SysDesc& d, BatchLds& L) {
 
 // Persistent kernel: every workgroup takes the next system from the queue until
 // the queue is exhausted (each workgroup exits once the counter passes count).
-__global__ __launch_bounds__(kThreads) void batched_kernel(const SysDesc* sys, int32_t count,
+__global__ __launch_bounds__(kThreads, 2) void batched_kernel(const SysDesc* sys, int32_t count,
                                                            unsigned int* counter) {
     __shared__ BatchLds L;
     __shared__ uint32_t s_idx;
