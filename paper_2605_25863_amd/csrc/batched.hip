@@ -129,6 +129,7 @@ struct BatchLds {
     uint32_t P[kMaxRows * kPB];
     uint32_t T[kPB * kPB];
     uint8_t cons[kMaxCols];
+    int16_t pstart[kMaxCols / kPB + 2];  // rank at the start of each pass with pivots
     int red[4];
 };
 
@@ -184,8 +185,8 @@ __device__ void pivot_block_inverse(const SysDesc& d, BatchLds& L, int rank, int
         if (s < np && ub + e < np) L.T[s * kPB + ub + e] = mul_mod(iv[e], inv, F);
 }
 
-// Step 3 of a pass: r <- r - sum_t a_r[t] PN_t for the rows with a non-zero
-// multiplier, as the transposed product (width x kPB) by (kPB x 16 rows) on
+// Step 3 of a pass: r <- r - sum_t a_r[t] PN_t for the candidate rows with a
+// non-zero multiplier, as the transposed product (width x kPB) by (kPB x 16 rows) on
 // the 16x16x4 FP64 MFMA, the multipliers split into 16-bit halves (a = hi
 // 2^16 + lo, two products).  Lane L (j = L % 16, g = L / 16) supplies
 // PN[4 kb + g][tile column 4 (j % 4) + j / 4] and the halves of a[16 rb + j]
@@ -223,12 +224,13 @@ __device__ void update_rows(const SysDesc& d, const BatchLds& L, const gu32* PN,
             a[kb] = rin ? L.P[rowc * kPB + 4 * kb + g] : 0u;
             any |= a[kb];
         }
-        const bool pivot = rin && L.piv[rowc] == 2;
+        const int state = L.piv[rowc];
+        const bool pivot = rin && state == 2, keep = rin && state != 1;
         const int prow = L.pt[rowc];
         if (!__any(any != 0u || pivot)) continue;
         // a pivot row of the pass (zero multipliers) reads its PN row and so
-        // takes it unchanged
-        const gu32* xrow = pivot ? PN + (int64_t)prow * ldw : W + (int64_t)rowc * ldw;
+        // takes it unchanged; a pivot row of an earlier pass is not written
+        const gu32* xrow = state == 0 ? W + (int64_t)rowc * ldw : PN + (int64_t)(pivot ? prow : 0) * ldw;
         uint32_t pb[kStrip][KB];
 #pragma unroll
         for (int e = 0; e < kStrip; ++e) {  // PN first: the MFMAs need it first
@@ -258,7 +260,7 @@ __device__ void update_rows(const SysDesc& d, const BatchLds& L, const gu32* PN,
                 lo = __builtin_amdgcn_mfma_f64_16x16x4f64(b, al[kb], lo, 0, 0, 0);
             }
             const int cx = tc + 4 * g;
-            if (rin && cx < ncols)
+            if (keep && cx < ncols)
                 *(gu4*)(W + (int64_t)row * ldw + cx) =
                     (v4u){sub_split(x[e].x, hi[0], lo[0], d.F), sub_split(x[e].y, hi[1], lo[1], d.F),
                           sub_split(x[e].z, hi[2], lo[2], d.F), sub_split(x[e].w, hi[3], lo[3], d.F)};
@@ -332,7 +334,7 @@ __device__ void solve_one(const SysDesc& d, BatchLds& L) {
     __threadfence_block();
     __syncthreads();
     const int nri = (m + kThreads - 1) / kThreads;  // rows per thread: tid + kThreads u
-    int rank = 0;
+    int rank = 0, npass = 0;
     for (int j0 = 0; j0 < n && rank < m; j0 += kPB) {
         const int bw = min(kPB, n - j0);
         // 1. the pass's columns of the candidate rows copied to LDS and
@@ -386,10 +388,12 @@ __device__ void solve_one(const SysDesc& d, BatchLds& L) {
             ++np;
         }
         if (np == 0) continue;
+        if (tid == 0) L.pstart[npass] = (int16_t)rank;
+        ++npass;
         __syncthreads();
-        // coefficients of the reduced pivot rows (wave 0), and the rows'
-        // multipliers: their pass-start values at the pass's pivot columns
-        // (zero for the pass's pivot rows), loaded again rather than held in
+        // coefficients of the reduced pivot rows (wave 0), and the candidate
+        // rows' multipliers: their pass-start values at the pass's pivot
+        // columns (zero for every pivot row), loaded again rather than held in
         // registers through the pivot search
         if (wave == 0) pivot_block_inverse(d, L, rank, np);
         {
@@ -403,7 +407,7 @@ __device__ void solve_one(const SysDesc& d, BatchLds& L) {
             for (int u = 0; u < kRowsPerThread; ++u) {
                 const int r = tid + kThreads * u;
                 if (u >= nri || r >= m) break;
-                const bool live = L.piv[r] != 2;
+                const bool live = L.piv[r] == 0;
                 vpu a;
 #pragma unroll
                 for (int t = 0; t < kPB; ++t) a[t] = live && t < np ? raw[u][pc[t]] : 0u;
@@ -446,8 +450,9 @@ __device__ void solve_one(const SysDesc& d, BatchLds& L) {
         }
         __threadfence_block();
         __syncthreads();
-        // 3. every row with a non-zero multiplier updated, the pass's pivot
-        // rows replaced by PN
+        // 3. every candidate row with a non-zero multiplier updated, the
+        // pass's pivot rows replaced by PN; the pivot rows of earlier passes
+        // are left as they are (forward elimination, X by back-substitution)
         update_rows(d, L, PN, np, c0);
         __threadfence_block();
         __syncthreads();
@@ -481,22 +486,51 @@ __device__ void solve_one(const SysDesc& d, BatchLds& L) {
     }
     __syncthreads();
     for (int t = tid; t < k; t += kThreads) ((gu8*)d.consistent)[t] = L.cons[t];
-    // X at the pivot columns: the reduced right-hand sides of the pivot rows
-    for (int c0 = 0; c0 < k; c0 += 64) {
-        const int t = c0 + lane, tc = min(t, k - 1);
-        for (int s0 = wave; s0 < rank; s0 += 4 * kStageRows) {
-            uint32_t v[kStageRows];
-#pragma unroll
-            for (int u = 0; u < kStageRows; ++u)
-                v[u] = W[(int64_t)L.pivrow[min(s0 + 4 * u, rank - 1)] * ldw + n + tc];
-#pragma unroll
-            for (int u = 0; u < kStageRows; ++u) {
-                const int s = s0 + 4 * u;
-                if (s < rank && t < k && L.cons[t]) X[(int64_t)L.pivcol[s] * d.ldx + t] = v[u];
-            }
-        }
-    }
+    // X at the pivot columns, a pass at a time from the last.  A pivot row of
+    // pass P holds P's reduced row (unit vectors at P's pivot columns, zeros at
+    // earlier ones, never updated afterwards), so x_s = c_s - sum over the
+    // later pivots s' of row_s[col_s'] x_s' (the back-substitution of the
+    // echelon form, Sec. 5.2's solve).  G lanes of a wave share an output,
+    // each summing every G-th later pivot in exact chunks of 8 split products
+    // with the loads of a chunk in flight together.  Inconsistent columns of X
+    // stay zero.
+    if (tid == 0) L.pstart[npass] = (int16_t)rank;
     __syncthreads();
+    for (int P = npass - 1; P >= 0; --P) {
+        const int s0 = L.pstart[P], s1 = L.pstart[P + 1], later = rank - s1;
+        const int nout = (s1 - s0) * k;
+        int G = 64;
+        while (G > 1 && nout * G > kThreads) G >>= 1;
+        for (int o0 = 0; o0 < nout; o0 += kThreads / G) {
+            const int o = o0 + tid / G, gi = tid % G;
+            const int oc = min(o, nout - 1);
+            const int s = s0 + oc / k, t = oc - (oc / k) * k;
+            const gu32* urow = W + (int64_t)L.pivrow[s] * ldw;
+            uint32_t acc = 0u;
+            for (int i0 = gi; i0 < later; i0 += 8 * G) {
+                uint32_t uv[8], xv[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int col = L.pivcol[s1 + min(i0 + e * G, later - 1)];
+                    uv[e] = urow[col];
+                    xv[e] = X[(int64_t)col * d.ldx + t];
+                }
+                double h = 0.0, l = 0.0;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const double u = i0 + e * G < later ? (double)uv[e] : 0.0;
+                    h = __fma_rn(u, (double)(xv[e] >> 16), h);
+                    l = __fma_rn(u, (double)(xv[e] & 0xffffu), l);
+                }
+                acc = add_mod(acc, split_reduce(h, l, F), F.p);
+            }
+            for (int off = G >> 1; off > 0; off >>= 1) acc = add_mod(acc, __shfl_xor(acc, off), F.p);
+            if (gi == 0 && o < nout)
+                X[(int64_t)L.pivcol[s] * d.ldx + t] = L.cons[t] ? sub_mod(urow[n + t], acc, F.p) : 0u;
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
 }
 
 // Persistent kernel: every workgroup takes the next system from the queue until
