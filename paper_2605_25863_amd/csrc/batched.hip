@@ -64,16 +64,6 @@ struct SysDesc {
     FieldConst F;
 };
 
-__device__ __forceinline__ int block_min(int v, int* red) {
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) red[wave] = v;
-    __syncthreads();
-    v = min(min(red[0], red[1]), min(red[2], red[3]));
-    __syncthreads();
-    return v;
-}
-
 // (s1 2^16 + s0) mod p for the exact partial sums of a split dot product
 // (s1 < 2^50, s0 < 2^51).
 __device__ __forceinline__ uint32_t split_reduce(double s1, double s0, const FieldConst& F) {
@@ -124,13 +114,21 @@ __device__ __forceinline__ uint32_t sub_split(uint32_t x, double s1, double s0, 
 struct BatchLds {
     uint8_t piv[kMaxRows];
     int8_t pt[kMaxRows];
-    int32_t pivrow[kMaxRows];
-    int32_t pivcol[kMaxRows];
+    int16_t pivrow[kMaxRows];
+    int16_t pivcol[kMaxRows];
     uint32_t P[kMaxRows * kPB];
     uint32_t T[kPB * kPB];
     uint8_t cons[kMaxCols];
     int16_t pstart[kMaxCols / kPB + 2];  // rank at the start of each pass with pivots
-    int red[4];
+    // pivot search of a pass: the window's rows, and each pivot's panel row
+    // (reduced by the pass's earlier pivots), leading value and pass column
+    int32_t win[16];
+    int16_t beyond[kMaxRows];  // the other candidate rows with a non-zero pass panel
+    uint8_t nz[kMaxRows];      // candidate row with a non-zero pass panel
+    uint32_t upan[kPB * kPB];
+    uint32_t ud[kPB];
+    int32_t upc[kPB];
+    int32_t npp[2];  // the pass's pivot count, by pass parity
 };
 
 // T = M^-1 for the pass's pivot block M[s][u] = row_{q_s}[col_u] (pass-start
@@ -318,6 +316,125 @@ __device__ __forceinline__ void load_pass_cols(const gu32* W, int ldw, int m, in
             7, 8, 9, 10, 11, 12, 13, 14, 15);
 }
 
+// Pivot search of a pass by one wave; returns the number of pivots (the same
+// in every lane) and records them.  The pivot of column c is the first
+// candidate row, in row order, whose value at c after eliminating the pass's
+// earlier pivots is non-zero.  The first kWin candidate rows (the window) are
+// kept reduced in registers, fraction-free (r <- d r - f q on the later
+// columns: the zero pattern is that of the normalised elimination, which is
+// all the search needs); lane L holds columns 4 (L % 4) .. 4 (L % 4) + 3 of
+// window row L / 4, so a column costs a ballot and at most four updates per
+// lane.  Only candidates that are non-zero somewhere in the pass's columns
+// are considered (a zero row stays zero).  When every live window row is
+// zero at c and such candidates remain after the window, those are scanned
+// 64 at a time, each replaying the pass's pivots so far on its pass-start
+// values (every pivot's panel row, reduced by the pivots before it, is kept in
+// LDS); window rows are zero at c, so such a pivot changes nothing in the
+// window.
+constexpr int kWin = 16;
+static_assert(kWin * 4 == 64 && kPB == 16, "window: 16 rows by 4 groups of 4 columns");
+
+__device__ int search_pass(const SysDesc& d, BatchLds& L, int j0, int bw, int rank) {
+    const int lane = threadIdx.x & 63, slot = lane >> 2, g = lane & 3;
+    const int m = d.m, ldw = d.ldw;
+    const gu32* W = (const gu32*)d.W;
+    const FieldConst F = d.F;
+    // the candidates that can give a pivot (a row that is zero at every
+    // column of the pass stays zero), in row order: the first kWin form the
+    // window, the others are listed for the scans
+    int nlist = 0;
+    for (int r0 = 0; r0 < m; r0 += 64) {
+        const int r = r0 + lane;
+        const bool c = r < m && L.piv[r] == 0 && L.nz[r];
+        const uint64_t b = __ballot(c);
+        const int pos = nlist + (int)__popcll(b & ((1ull << lane) - 1ull));
+        if (c) {
+            if (pos < kWin)
+                L.win[pos] = r;
+            else
+                L.beyond[pos - kWin] = (int16_t)r;
+        }
+        nlist += (int)__popcll(b);
+    }
+    if (nlist == 0) return 0;
+    const int nwin = min(nlist, kWin), nbeyond = nlist - nwin;
+    bool live = slot < nwin;
+    const int wr = L.win[min(slot, nwin - 1)];
+    v4u x = *(const gu4*)(W + (int64_t)wr * ldw + min(j0 + 4 * g, ldw - 4));
+    int np = 0, nslow = 0;  // nslow: pivots taken from the listed rows
+    for (int c = 0; c < bw && rank + np < m; ++c) {
+        const int gc = c >> 2, ec = c & 3;
+        const uint32_t xc = x[ec];
+        const uint64_t b = __ballot(live && g == gc && xc != 0u);
+        int q = -1;
+        uint32_t dq = 0u;
+        if (b != 0ull) {
+            const int ql = (int)__builtin_ctzll(b), rq = ql >> 2;
+            q = L.win[rq];
+            dq = __builtin_amdgcn_readlane(xc, ql);
+            v4u U;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) U[e] = __shfl(x[e], 4 * rq + g);
+            const uint32_t f = __shfl(xc, 4 * slot + gc);
+            if (slot == rq) {
+                *(v4u*)&L.upan[np * kPB + 4 * g] = x;
+                live = false;
+            }
+            if (live && f != 0u) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (4 * g + e > c)
+                        x[e] = mul_sub_mod((double)dq, x[e], (double)f, (double)U[e], F);
+            }
+        } else if (nbeyond > nslow) {
+            {
+                for (int i0 = 0; i0 < nbeyond; i0 += 64) {
+                    const int r = L.beyond[min(i0 + lane, nbeyond - 1)];
+                    const bool cand = i0 + lane < nbeyond && L.piv[r] == 0;
+                    const gu32* rp = W + (int64_t)r * ldw;
+                    v4u y4[4];
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) y4[h] = *(const gu4*)(rp + min(j0 + 4 * h, ldw - 4));
+                    vpu y = __builtin_shufflevector(
+                        __builtin_shufflevector(y4[0], y4[1], 0, 1, 2, 3, 4, 5, 6, 7),
+                        __builtin_shufflevector(y4[2], y4[3], 0, 1, 2, 3, 4, 5, 6, 7), 0, 1, 2, 3, 4, 5,
+                        6, 7, 8, 9, 10, 11, 12, 13, 14, 15);
+                    for (int sp = 0; sp < np; ++sp) {
+                        const int ps = L.upc[sp];
+                        const uint32_t f = y[ps];
+                        if (f == 0u) continue;
+                        const double ds = (double)L.ud[sp];
+#pragma unroll
+                        for (int cc = 0; cc < kPB; ++cc)
+                            if (cc > ps)
+                                y[cc] = mul_sub_mod(ds, y[cc], (double)f, (double)L.upan[sp * kPB + cc], F);
+                    }
+                    const uint64_t b2 = __ballot(cand && y[c] != 0u);
+                    if (b2 != 0ull) {
+                        const int ql = (int)__builtin_ctzll(b2);
+                        q = __builtin_amdgcn_readlane(r, ql);
+                        dq = __builtin_amdgcn_readlane(y[c], ql);
+                        if (lane == ql) *(vpu*)&L.upan[np * kPB] = y;
+                        ++nslow;
+                        break;
+                    }
+                }
+            }
+        }
+        if (q < 0) continue;  // free column
+        if (lane == 0) {
+            L.piv[q] = 2;
+            L.pt[q] = (int8_t)np;
+            L.pivrow[rank + np] = (int16_t)q;
+            L.pivcol[rank + np] = (int16_t)(j0 + c);
+            L.upc[np] = c;
+            L.ud[np] = dq;
+        }
+        ++np;
+    }
+    return np;
+}
+
 __device__ void solve_one(const SysDesc& d, BatchLds& L) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = d.m, n = d.n, k = d.k, ncols = n + k, ldw = d.ldw;
@@ -337,11 +454,8 @@ __device__ void solve_one(const SysDesc& d, BatchLds& L) {
     int rank = 0, npass = 0;
     for (int j0 = 0; j0 < n && rank < m; j0 += kPB) {
         const int bw = min(kPB, n - j0);
-        // 1. the pass's columns of the candidate rows copied to LDS and
-        // eliminated there.  Each thread owns rows tid, tid + kThreads, ...:
-        // it alone reads and writes their state, so between columns only the
-        // pivot row crosses threads, published by the barriers of the pivot
-        // search.
+        // 1. the pass's pivots, found by wave 0, among the candidate rows that
+        // are non-zero somewhere in the pass's columns
         {
             vpu raw[kRowsPerThread];
             load_pass_cols(W, ldw, m, nri, j0, raw);
@@ -349,48 +463,22 @@ __device__ void solve_one(const SysDesc& d, BatchLds& L) {
             for (int u = 0; u < kRowsPerThread; ++u) {
                 const int r = tid + kThreads * u;
                 if (u >= nri || r >= m) break;
-                const bool cand = L.piv[r] == 0;
-                vpu v = raw[u];
+                bool nz = false;
 #pragma unroll
-                for (int c = 0; c < kPB; ++c) v[c] = cand && c < bw ? v[c] : 0u;
-                *(vpu*)&L.P[r * kPB] = v;
+                for (int c = 0; c < kPB; ++c) nz |= c < bw && raw[u][c] != 0u;
+                L.nz[r] = nz ? 1 : 0;
             }
         }
-        int np = 0;
-        for (int c = 0; c < bw && rank + np < m; ++c) {
-            int cand = INT32_MAX;
-            for (int r = tid; r < m; r += kThreads)
-                if (L.piv[r] == 0 && L.P[r * kPB + c] != 0) {
-                    cand = r;
-                    break;
-                }
-            const int q = block_min(cand, L.red);
-            if (q == INT32_MAX) continue;  // free column
-            if (tid == (q & (kThreads - 1))) {
-                L.piv[q] = 2;
-                L.pt[q] = (int8_t)np;
-                L.pivrow[rank + np] = q;
-                L.pivcol[rank + np] = j0 + c;
-            }
-            // column c out of the other candidates, fraction-free: r <- d r - f q
-            // on the later columns (the zero pattern is that of the normalised
-            // elimination, which is all the pivot search needs)
-            const double dq = (double)L.P[q * kPB + c];
-            for (int r = tid; r < m; r += kThreads) {
-                if (r == q || L.piv[r] != 0) continue;
-                const uint32_t f = L.P[r * kPB + c];
-                if (f == 0) continue;
-                const double df = (double)f;
-                for (int cc = c + 1; cc < bw; ++cc)
-                    L.P[r * kPB + cc] = mul_sub_mod(dq, L.P[r * kPB + cc], df,
-                                                    (double)L.P[q * kPB + cc], F);
-            }
-            ++np;
+        __syncthreads();
+        if (wave == 0) {
+            const int npw = search_pass(d, L, j0, bw, rank);
+            if (lane == 0) L.npp[(j0 / kPB) & 1] = npw;
         }
+        __syncthreads();
+        const int np = L.npp[(j0 / kPB) & 1];
         if (np == 0) continue;
         if (tid == 0) L.pstart[npass] = (int16_t)rank;
         ++npass;
-        __syncthreads();
         // coefficients of the reduced pivot rows (wave 0), and the candidate
         // rows' multipliers: their pass-start values at the pass's pivot
         // columns (zero for every pivot row), loaded again rather than held in
