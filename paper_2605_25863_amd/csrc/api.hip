@@ -289,7 +289,8 @@ linac_status validate_range(const uint32_t* M, int64_t rows, int64_t cols, int64
 }
 
 // Graphs of the batched launch (counter reset + persistent kernel), captured
-// once per (device, workspace, count, grid) and replayed afterwards.  The
+// once per (device, workspace, count, grid, multiplier rows) and replayed
+// afterwards.  The
 // kernel arguments point into the workspace only, so a replay on the same
 // workspace sees the descriptors uploaded by the current call.
 struct BatchedGraph {
@@ -297,15 +298,18 @@ struct BatchedGraph {
     void* ws;
     int32_t count;
     int32_t grid;
+    int32_t mult_rows;
     hipGraphExec_t exec;
 };
 std::mutex g_graph_mu;
 std::vector<BatchedGraph> g_graphs;
 
-hipError_t batched_graph(int dev, void* ws, int32_t count, int32_t grid, hipGraphExec_t* out) {
+hipError_t batched_graph(int dev, void* ws, int32_t count, int32_t grid, int32_t mult_rows,
+                         hipGraphExec_t* out) {
     std::lock_guard<std::mutex> lock(g_graph_mu);
     for (const BatchedGraph& g : g_graphs)
-        if (g.dev == dev && g.ws == ws && g.count == count && g.grid == grid) {
+        if (g.dev == dev && g.ws == ws && g.count == count && g.grid == grid &&
+            g.mult_rows == mult_rows) {
             *out = g.exec;
             return hipSuccess;
         }
@@ -315,7 +319,7 @@ hipError_t batched_graph(int dev, void* ws, int32_t count, int32_t grid, hipGrap
     hipGraph_t graph = nullptr;
     e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = batched_launch(ws, count, grid, cap);
+        hipError_t le = batched_launch(ws, count, grid, mult_rows, cap);
         e = hipStreamEndCapture(cap, &graph);
         if (le != hipSuccess) e = le;
     }
@@ -328,7 +332,7 @@ hipError_t batched_graph(int dev, void* ws, int32_t count, int32_t grid, hipGrap
         (void)hipGraphExecDestroy(g_graphs.front().exec);
         g_graphs.erase(g_graphs.begin());
     }
-    g_graphs.push_back({dev, ws, count, grid, exec});
+    g_graphs.push_back({dev, ws, count, grid, mult_rows, exec});
     *out = exec;
     return hipSuccess;
 }
@@ -522,7 +526,7 @@ linac_status linac_solve_batched(const linac_system* sys, int32_t count, void* w
     const int32_t per_cu = tuning().batched_per_cu;
     const int32_t grid = std::max(1, std::min(count, cus * per_cu));
     hipGraphExec_t exec = nullptr;
-    e = batched_graph(dev, ws, count, grid, &exec);
+    e = batched_graph(dev, ws, count, grid, batched_mult_rows(sys, count), &exec);
     if (e != hipSuccess) return hip_fail(e);
     if (opts && opts->verbose)
         fprintf(stderr, "[linac] batched count=%d grid=%d ws=%p\n", count, grid, ws);

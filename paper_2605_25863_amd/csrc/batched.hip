@@ -26,11 +26,17 @@
 // multipliers by the reduced pivot rows, runs on the FP64 matrix cores.  Rows
 // are never moved: pivot s is recorded in LDS.  Finally rank, pivots, X (free
 // variables 0) and consistency are written.
+#include <algorithm>
 #include <vector>
 
 #include "internal.h"
 
 namespace linac {
+
+// The rows' multipliers of the current pass (kPB per row), in dynamic LDS
+// sized at launch to the batch's largest system, so that batches of smaller
+// systems fit more workgroups per CU.
+extern __shared__ uint32_t g_mult[];
 
 namespace {
 
@@ -116,7 +122,6 @@ struct BatchLds {
     int8_t pt[kMaxRows];
     int16_t pivrow[kMaxRows];
     int16_t pivcol[kMaxRows];
-    uint32_t P[kMaxRows * kPB];
     uint32_t T[kPB * kPB];
     uint8_t cons[kMaxCols];
     int16_t pstart[kMaxCols / kPB + 2];  // rank at the start of each pass with pivots
@@ -126,6 +131,7 @@ struct BatchLds {
     int16_t beyond[kMaxRows];  // the other candidate rows with a non-zero pass panel
     uint8_t nz[kMaxRows];      // candidate row with a non-zero pass panel
     uint32_t upan[kPB * kPB];
+    uint32_t mst[kPB * kPB];  // each pivot's pass-start panel row
     uint32_t ud[kPB];
     int32_t upc[kPB];
     int32_t npp[2];  // the pass's pivot count, by pass parity
@@ -144,15 +150,14 @@ static_assert(kEpl == 4, "the block inverse keeps four entries per lane");
 __device__ void pivot_block_inverse(const SysDesc& d, BatchLds& L, int rank, int np) {
     const int lane = threadIdx.x & 63, s = lane / kLpr, ub = (lane % kLpr) * kEpl;
     const FieldConst& F = d.F;
-    const gu32* W = (const gu32*)d.W;
     // vectors, not arrays: an element picked by a run-time index stays in
-    // registers
+    // registers.  M comes from the pivots' pass-start panel rows, which the
+    // pivot search recorded.
     v4u mv, iv;
 #pragma unroll
     for (int e = 0; e < kEpl; ++e) {
         const int u = ub + e;
-        const int rs = L.pivrow[rank + min(s, np - 1)], cu = L.pivcol[rank + min(u, np - 1)];
-        const uint32_t w = W[(int64_t)rs * d.ldw + cu];
+        const uint32_t w = L.mst[min(s, np - 1) * kPB + L.upc[min(u, np - 1)]];
         mv[e] = s < np && u < np ? w : 0u;
         iv[e] = s == u ? 1u : 0u;
     }
@@ -219,7 +224,7 @@ __device__ void update_rows(const SysDesc& d, const BatchLds& L, const gu32* PN,
         uint32_t any = 0u;
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
-            a[kb] = rin ? L.P[rowc * kPB + 4 * kb + g] : 0u;
+            a[kb] = rin ? g_mult[rowc * kPB + 4 * kb + g] : 0u;
             any |= a[kb];
         }
         const int state = L.piv[rowc];
@@ -360,7 +365,8 @@ __device__ int search_pass(const SysDesc& d, BatchLds& L, int j0, int bw, int ra
     const int nwin = min(nlist, kWin), nbeyond = nlist - nwin;
     bool live = slot < nwin;
     const int wr = L.win[min(slot, nwin - 1)];
-    v4u x = *(const gu4*)(W + (int64_t)wr * ldw + min(j0 + 4 * g, ldw - 4));
+    const v4u x0 = *(const gu4*)(W + (int64_t)wr * ldw + min(j0 + 4 * g, ldw - 4));
+    v4u x = x0;
     int np = 0, nslow = 0;  // nslow: pivots taken from the listed rows
     for (int c = 0; c < bw && rank + np < m; ++c) {
         const int gc = c >> 2, ec = c & 3;
@@ -378,6 +384,7 @@ __device__ int search_pass(const SysDesc& d, BatchLds& L, int j0, int bw, int ra
             const uint32_t f = __shfl(xc, 4 * slot + gc);
             if (slot == rq) {
                 *(v4u*)&L.upan[np * kPB + 4 * g] = x;
+                *(v4u*)&L.mst[np * kPB + 4 * g] = x0;
                 live = false;
             }
             if (live && f != 0u) {
@@ -395,10 +402,11 @@ __device__ int search_pass(const SysDesc& d, BatchLds& L, int j0, int bw, int ra
                     v4u y4[4];
 #pragma unroll
                     for (int h = 0; h < 4; ++h) y4[h] = *(const gu4*)(rp + min(j0 + 4 * h, ldw - 4));
-                    vpu y = __builtin_shufflevector(
+                    const vpu y0 = __builtin_shufflevector(
                         __builtin_shufflevector(y4[0], y4[1], 0, 1, 2, 3, 4, 5, 6, 7),
                         __builtin_shufflevector(y4[2], y4[3], 0, 1, 2, 3, 4, 5, 6, 7), 0, 1, 2, 3, 4, 5,
                         6, 7, 8, 9, 10, 11, 12, 13, 14, 15);
+                    vpu y = y0;
                     for (int sp = 0; sp < np; ++sp) {
                         const int ps = L.upc[sp];
                         const uint32_t f = y[ps];
@@ -414,7 +422,10 @@ __device__ int search_pass(const SysDesc& d, BatchLds& L, int j0, int bw, int ra
                         const int ql = (int)__builtin_ctzll(b2);
                         q = __builtin_amdgcn_readlane(r, ql);
                         dq = __builtin_amdgcn_readlane(y[c], ql);
-                        if (lane == ql) *(vpu*)&L.upan[np * kPB] = y;
+                        if (lane == ql) {
+                            *(vpu*)&L.upan[np * kPB] = y;
+                            *(vpu*)&L.mst[np * kPB] = y0;
+                        }
                         ++nslow;
                         break;
                     }
@@ -499,7 +510,7 @@ __device__ void solve_one(const SysDesc& d, BatchLds& L) {
                 vpu a;
 #pragma unroll
                 for (int t = 0; t < kPB; ++t) a[t] = live && t < np ? raw[u][pc[t]] : 0u;
-                *(vpu*)&L.P[r * kPB] = a;
+                *(vpu*)&g_mult[r * kPB] = a;
             }
         }
         __syncthreads();
@@ -623,7 +634,10 @@ __device__ void solve_one(const SysDesc& d, BatchLds& L) {
 
 // Persistent kernel: every workgroup takes the next system from the queue until
 // the queue is exhausted (each workgroup exits once the counter passes count).
-__global__ __launch_bounds__(kThreads, 2) void batched_kernel(const SysDesc* sys, int32_t count,
+// Three waves per SIMD (at most 168 VGPRs; a few long-lived values spill
+// outside the hot loops): with systems of up to 512 rows the LDS also allows
+// three workgroups per CU, which hide each other's serial pivot chains.
+__global__ __launch_bounds__(kThreads, 3) void batched_kernel(const SysDesc* sys, int32_t count,
                                                            unsigned int* counter) {
     __shared__ BatchLds L;
     __shared__ uint32_t s_idx;
@@ -694,11 +708,21 @@ void batched_describe(const linac_system* sys, int32_t count, void* ws, void* ho
     }
 }
 
-hipError_t batched_launch(void* ws, int32_t count, int32_t grid, hipStream_t s) {
+int32_t batched_mult_rows(const linac_system* sys, int32_t count) {
+    int32_t mx = 1;
+    for (int32_t i = 0; i < count; ++i) mx = std::max(mx, sys[i].m);
+    return (int32_t)round_up(mx, 64);
+}
+
+hipError_t batched_launch(void* ws, int32_t count, int32_t grid, int32_t mult_rows, hipStream_t s) {
     unsigned int* counter = (unsigned int*)ws;
     const SysDesc* desc = (const SysDesc*)((char*)ws + 256);
+    const size_t dyn = (size_t)mult_rows * kPB * sizeof(uint32_t);
+    hipError_t e = hipFuncSetAttribute((const void*)batched_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
-    hipLaunchKernelGGL(batched_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, desc, count,
+    hipLaunchKernelGGL(batched_kernel, dim3((unsigned)grid), dim3(kThreads), dyn, s, desc, count,
                        counter);
     return hipGetLastError();
 }

@@ -186,7 +186,9 @@ size_t batched_workspace(const linac_system* sys, int32_t count);
 void batched_describe(const linac_system* sys, int32_t count, void* ws, void* host_desc,
                       int32_t* order);
 void* batched_desc_ptr(void* ws);
-hipError_t batched_launch(void* ws, int32_t count, int32_t grid, hipStream_t s);
+// Rows of the multiplier array in dynamic LDS: the largest m, rounded up to 64.
+int32_t batched_mult_rows(const linac_system* sys, int32_t count);
+hipError_t batched_launch(void* ws, int32_t count, int32_t grid, int32_t mult_rows, hipStream_t s);
 
 // Range check of residues: sets *flag to 1 when an entry is >= p.
 hipError_t launch_range_check(const uint32_t* M, int64_t rows, int64_t cols, int64_t ld, uint32_t p,
