@@ -97,7 +97,7 @@ def tune(quick: bool = False):
     systems = workloads.batched_systems(seed=4, count=512 if quick else 4096)
     prep = lx.prepare_batched(systems)
     per_cu = {}
-    for c in (1, 2, 4, 8):
+    for c in (1, 2, 3, 4, 6, 8):
         lx.load_tuning(json.dumps({"batched_per_cu": c}))
         lx.solve_batched(systems, prepared=prep)
         torch.cuda.synchronize()
