@@ -65,7 +65,7 @@ struct SysDesc {
     uint32_t* W;       // working region in the workspace (m rows, then kPB scratch rows)
     int32_t m, n, k;
     int32_t lda, ldb, ldx;
-    int32_t ldw;       // multiple of 4
+    int32_t ldw;       // words per row, a multiple of 32
     int32_t pad;
     FieldConst F;
 };
@@ -273,7 +273,7 @@ __device__ void update_rows(const SysDesc& d, const BatchLds& L, const gu32* PN,
 
 // dst[r][c] = src[r][c] for r < rows, c < cols: a wave per row, a lane per
 // column, kStageRows rows of loads in flight before their stores.
-constexpr int kStageRows = 8;
+constexpr int kStageRows = 16;
 
 __device__ void copy_block(gu32* dst, int ldd, const gu32* src, int lds, int rows, int cols) {
     const int lane = threadIdx.x & 63;
@@ -517,9 +517,10 @@ __device__ void solve_one(const SysDesc& d, BatchLds& L) {
         // 2. PN_t = sum_s T[t][s] row_{q_s} over 4-column groups from c0.  Only
         // the columns after the pass are needed from here on (later passes
         // search there; the outputs read the right-hand sides), so steps 2 and
-        // 3 start at the first 16-aligned column after the pass, or at j0 in
-        // the last pass.
-        const int c0 = min(j0 + kPB, n) & ~15;
+        // 3 start at the 32-aligned column at or before the first column after
+        // the pass (rows are 128-byte aligned, so every strip of stores covers
+        // whole cache lines).
+        const int c0 = min(j0 + kPB, n) & ~31;
         const int ngroups = (ncols - c0 + 3) >> 2;
         // (the terms in halves of 8, every load of a half issued first: beyond
         // np the coefficients are zero and the row index is clamped to pivot 0)
@@ -658,6 +659,10 @@ __global__ void reset_counter_kernel(unsigned int* counter) { *counter = 0u; }
 
 size_t batched_desc_bytes() { return sizeof(SysDesc); }
 
+// Words per workspace row: n + k rounded up to 32, so rows start on 128-byte
+// boundaries.
+static int64_t row_words(int64_t ncols) { return round_up(ncols > 0 ? ncols : 1, 32); }
+
 bool batched_fits(int64_t m, int64_t n, int64_t k) {
     return m <= kMaxRows && n + k <= kMaxCols;
 }
@@ -666,7 +671,7 @@ bool batched_fits(int64_t m, int64_t n, int64_t k) {
 size_t batched_workspace(const linac_system* sys, int32_t count) {
     size_t off = 256 + round_up((int64_t)count * sizeof(SysDesc), 256);
     for (int32_t i = 0; i < count; ++i) {
-        const int64_t ldw = round_up(sys[i].n + sys[i].k > 0 ? sys[i].n + sys[i].k : 1, 4);
+        const int64_t ldw = row_words(sys[i].n + sys[i].k);
         off += round_up(((int64_t)sys[i].m + kPB) * ldw * 4, 256);
     }
     return off + 256;
@@ -682,7 +687,7 @@ void batched_describe(const linac_system* sys, int32_t count, void* ws, void* ho
     std::vector<size_t> region(count);
     for (int32_t i = 0; i < count; ++i) {
         region[i] = off;
-        const int64_t ldw = round_up(sys[i].n + sys[i].k > 0 ? sys[i].n + sys[i].k : 1, 4);
+        const int64_t ldw = row_words(sys[i].n + sys[i].k);
         off += round_up(((int64_t)sys[i].m + kPB) * ldw * 4, 256);
     }
     for (int32_t qi = 0; qi < count; ++qi) {
@@ -702,7 +707,7 @@ void batched_describe(const linac_system* sys, int32_t count, void* ws, void* ho
         d.lda = s.lda;
         d.ldb = s.ldb;
         d.ldx = s.ldx;
-        d.ldw = (int32_t)round_up(s.n + s.k > 0 ? s.n + s.k : 1, 4);
+        d.ldw = (int32_t)row_words(s.n + s.k);
         d.pad = 0;
         d.F = make_field(s.p);
     }
