@@ -88,7 +88,7 @@ def _lowrank(rng, m, n, r, p):
 
 
 def test_passes_at_the_limits(gpu):
-    """The batched kernel reduces a system in passes of 8 pivot columns: systems
+    """The batched kernel reduces a system in passes of 16 pivot columns: systems
     at the size limits of one workgroup (1024 rows, n + k = 2048), passes that
     hold free columns, passes cut short when the rank reaches m, rank-deficient
     and inconsistent systems, p = 2 and 3, and an all-zero system."""
@@ -118,3 +118,38 @@ def test_passes_at_the_limits(gpu):
     add(workloads.uniform(rng, (7, 1500), p31), workloads.uniform(rng, (7, 1), p31), p31)
     print("limits batch", [(s["A"].shape, s["B"].shape[1], s["p"]) for s in systems], flush=True)
     _check_all(systems, lx.solve_batched(systems), tag="limits")
+
+
+def test_pivot_search_fallbacks(gpu):
+    """The pivot search keeps the first 16 candidate rows reduced in registers
+    and falls back to scanning the other candidates (each replaying the pass's
+    pivots) when every window row is zero at a column; rows zero in all of a
+    pass's columns are left out of the search.  Systems built to take each of
+    these routes: a block of top rows zero at some columns, duplicated top rows
+    (zero after the first is taken), a sparse system over F_3, rows zero in a
+    whole pass, and fewer candidates than the window."""
+    rng = np.random.default_rng(91)
+    p31 = workloads.draw_prime31(rng)
+    systems = []
+
+    def add(A, B, p):
+        systems.append(dict(A=np.ascontiguousarray(A, dtype=np.uint32),
+                            B=np.ascontiguousarray(B, dtype=np.uint32), p=int(p)))
+
+    A = workloads.uniform(rng, (300, 200), p31)
+    A[:40, [5, 21, 40, 77]] = 0  # the window is zero there; the pivot lies past it
+    add(A, workloads.uniform(rng, (300, 4), p31), p31)
+    A = workloads.uniform(rng, (200, 150), p31)
+    A[1:20] = A[0]  # duplicated top rows: zero once the first is a pivot
+    add(A, workloads.uniform(rng, (200, 3), p31), p31)
+    A = workloads.uniform(rng, (120, 100), 3) * (rng.random((120, 100)) < 0.15)
+    add(A, workloads.uniform(rng, (120, 2), 3), 3)
+    A = workloads.uniform(rng, (100, 90), p31)
+    A[16:, :32] = 0  # after the first pass, no candidate is non-zero in columns 16..31
+    add(A, workloads.uniform(rng, (100, 5), p31), p31)
+    add(workloads.uniform(rng, (10, 40), p31), workloads.uniform(rng, (10, 2), p31), p31)
+    A = workloads.uniform(rng, (64, 64), 7)
+    A[:, 20:36] = 0  # a whole pass of free columns
+    add(A, workloads.uniform(rng, (64, 1), 7), 7)
+    print("fallback batch", [(s["A"].shape, s["B"].shape[1], s["p"]) for s in systems], flush=True)
+    _check_all(systems, lx.solve_batched(systems), tag="fallbacks")
