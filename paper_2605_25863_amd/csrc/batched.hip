@@ -341,8 +341,7 @@ static_assert(kWin * 4 == 64 && kPB == 16, "window: 16 rows by 4 groups of 4 col
 
 __device__ int search_pass(const SysDesc& d, BatchLds& L, int j0, int bw, int rank) {
     const int lane = threadIdx.x & 63, slot = lane >> 2, g = lane & 3;
-    const int m = d.m, ldw = d.ldw;
-    const gu32* W = (const gu32*)d.W;
+    const int m = d.m;
     const FieldConst F = d.F;
     // the candidates that can give a pivot (a row that is zero at every
     // column of the pass stays zero), in row order: the first kWin form the
@@ -365,7 +364,7 @@ __device__ int search_pass(const SysDesc& d, BatchLds& L, int j0, int bw, int ra
     const int nwin = min(nlist, kWin), nbeyond = nlist - nwin;
     bool live = slot < nwin;
     const int wr = L.win[min(slot, nwin - 1)];
-    const v4u x0 = *(const gu4*)(W + (int64_t)wr * ldw + min(j0 + 4 * g, ldw - 4));
+    const v4u x0 = *(const v4u*)&g_mult[wr * kPB + 4 * g];  // pass-start values
     v4u x = x0;
     int np = 0, nslow = 0;  // nslow: pivots taken from the listed rows
     for (int c = 0; c < bw && rank + np < m; ++c) {
@@ -398,14 +397,7 @@ __device__ int search_pass(const SysDesc& d, BatchLds& L, int j0, int bw, int ra
                 for (int i0 = 0; i0 < nbeyond; i0 += 64) {
                     const int r = L.beyond[min(i0 + lane, nbeyond - 1)];
                     const bool cand = i0 + lane < nbeyond && L.piv[r] == 0;
-                    const gu32* rp = W + (int64_t)r * ldw;
-                    v4u y4[4];
-#pragma unroll
-                    for (int h = 0; h < 4; ++h) y4[h] = *(const gu4*)(rp + min(j0 + 4 * h, ldw - 4));
-                    const vpu y0 = __builtin_shufflevector(
-                        __builtin_shufflevector(y4[0], y4[1], 0, 1, 2, 3, 4, 5, 6, 7),
-                        __builtin_shufflevector(y4[2], y4[3], 0, 1, 2, 3, 4, 5, 6, 7), 0, 1, 2, 3, 4, 5,
-                        6, 7, 8, 9, 10, 11, 12, 13, 14, 15);
+                    const vpu y0 = *(const vpu*)&g_mult[r * kPB];  // pass-start values
                     vpu y = y0;
                     for (int sp = 0; sp < np; ++sp) {
                         const int ps = L.upc[sp];
@@ -466,7 +458,9 @@ __device__ void solve_one(const SysDesc& d, BatchLds& L) {
     for (int j0 = 0; j0 < n && rank < m; j0 += kPB) {
         const int bw = min(kPB, n - j0);
         // 1. the pass's pivots, found by wave 0, among the candidate rows that
-        // are non-zero somewhere in the pass's columns
+        // are non-zero somewhere in the pass's columns.  The pass's columns of
+        // every row are loaded once, into the multiplier array (the search
+        // reads them there, and they become the multipliers in place).
         {
             vpu raw[kRowsPerThread];
             load_pass_cols(W, ldw, m, nri, j0, raw);
@@ -478,6 +472,7 @@ __device__ void solve_one(const SysDesc& d, BatchLds& L) {
 #pragma unroll
                 for (int c = 0; c < kPB; ++c) nz |= c < bw && raw[u][c] != 0u;
                 L.nz[r] = nz ? 1 : 0;
+                *(vpu*)&g_mult[r * kPB] = raw[u];
             }
         }
         __syncthreads();
@@ -492,24 +487,23 @@ __device__ void solve_one(const SysDesc& d, BatchLds& L) {
         ++npass;
         // coefficients of the reduced pivot rows (wave 0), and the candidate
         // rows' multipliers: their pass-start values at the pass's pivot
-        // columns (zero for every pivot row), loaded again rather than held in
-        // registers through the pivot search
+        // columns (zero for every pivot row), picked in place from the pass
+        // columns each thread stored for its own rows
         if (wave == 0) pivot_block_inverse(d, L, rank, np);
         {
             int pc[kPB];
 #pragma unroll
             for (int t = 0; t < kPB; ++t)
                 pc[t] = __builtin_amdgcn_readfirstlane(t < np ? L.pivcol[rank + t] - j0 : 0);
-            vpu raw[kRowsPerThread];
-            load_pass_cols(W, ldw, m, nri, j0, raw);
 #pragma unroll
             for (int u = 0; u < kRowsPerThread; ++u) {
                 const int r = tid + kThreads * u;
                 if (u >= nri || r >= m) break;
                 const bool live = L.piv[r] == 0;
+                const vpu raw = *(const vpu*)&g_mult[r * kPB];
                 vpu a;
 #pragma unroll
-                for (int t = 0; t < kPB; ++t) a[t] = live && t < np ? raw[u][pc[t]] : 0u;
+                for (int t = 0; t < kPB; ++t) a[t] = live && t < np ? raw[pc[t]] : 0u;
                 *(vpu*)&g_mult[r * kPB] = a;
             }
         }
