@@ -183,6 +183,7 @@ struct Sel {
     int32_t nrows;
     int32_t t;
     int32_t bcast;
+    int32_t wcount[16];           // per-wave counts of a candidate scan
 };
 
 __device__ int node_id(int level, int k, int gmax) {
@@ -577,6 +578,42 @@ __device__ __forceinline__ void node_gj_pairs(const SelArgs& a, Sel& S, double v
     __syncthreads();
 }
 
+// The first kChunk candidates (in list order) that are non-zero somewhere in
+// the leaf, into S.pos and S.nrows, by a workgroup of NW waves scanning the
+// list in order.
+template <int NW>
+__device__ void pick_nonzero_rows(const SelArgs& a, Sel& S, int E) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int found = 0;
+    for (int base = 0; base < E && found < kChunk; base += 64 * NW) {
+        const int i = base + threadIdx.x;
+        bool nz = false;
+        if (i < E) {  // the leaf's columns of a row: one 128-byte aligned segment
+            const uint32_t* rp = a.PR + (int64_t)a.cand[i] * a.ldpr + a.l0;
+#pragma unroll
+            for (int h = 0; h < 8; ++h) {
+                const v4i q = *(const v4i*)(rp + 4 * h);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) nz |= 4 * h + e < a.wl && q[e] != 0;
+            }
+        }
+        const unsigned long long b = __ballot(nz);
+        if (lane == 0) S.wcount[wave] = (int)__popcll(b);
+        __syncthreads();
+        int before = found, total = 0;
+        for (int w = 0; w < NW; ++w) {
+            before += w < wave ? S.wcount[w] : 0;
+            total += S.wcount[w];
+        }
+        const int rank = before + (int)__popcll(b & ((1ull << lane) - 1ull));
+        if (nz && rank < kChunk) S.pos[rank] = i;
+        found += total;
+        __syncthreads();  // the counts are rewritten by the next round
+    }
+    if (threadIdx.x == 0) S.nrows = min(found, kChunk);
+    __syncthreads();
+}
+
 // Final node: P^-1, the leaf result, the pivot bookkeeping, and a copy of the
 // pivot rows over the columns the leaf updates (the product overwrites them).
 // R = 32: the pair layout of node_gj_pairs; R = 64: the layout of node_gj<64>.
@@ -746,6 +783,13 @@ __global__ __launch_bounds__(first ? kFirstThreads : kSelThreads, first ? 2 : 1)
         if (S.t == a.wl || nodes == 1) publish<32, kFirstWaves>(a, S, T, a.save_rows && !a.yfrag, L);
         return;  // otherwise the tree launch decides
     }
+    // Chunk 0 of the tree takes the first kChunk candidates that are non-zero
+    // in the leaf: rows that are combinations of earlier pivot rows stay
+    // candidates and gather at the front of the list, zero in every later
+    // leaf, and are what keeps the first chunk short of full rank.  A zero row
+    // adds nothing to the leaf's span, so node (level, 0) still spans what the
+    // candidates before its range span, and the tree's finality rule holds.
+    if (g == 0) pick_nonzero_rows<kSelWaves>(a, S, E);
     node_gj_pairs<kSelWaves>(a, S, v, T, L);
     int regs = 32;  // v, T hold the Gauss-Jordan of the node's basis rows in this layout (0: none)
     while (true) {
