@@ -7,25 +7,30 @@
 // an atomic queue.  The host orders the queue by decreasing estimated cost
 // (largest systems first: longest-processing-time scheduling).
 //
-// Per system, Gauss-Jordan (Sec. 3.2) in passes of kPB pivot columns, so that
-// the system streams through the memory system once per pass, not once per
-// column (with a thousand systems in flight they do not stay in cache):
-//   1. the pass's columns of every candidate row are copied to LDS and
-//      eliminated there to find the pivots: pivot = the smallest non-pivot
-//      row with a non-zero entry; the elimination is fraction-free (no
-//      inverse on this serial chain);
+// Per system, elimination with the paper's pivot rule (Sec. 3.2) in passes of
+// kPB pivot columns, so that the system streams through the memory system once
+// per pass, not once per column (with a thousand systems in flight they do not
+// stay in cache).  The outputs are X, rank, pivots and consistency, not the
+// reduced matrix, so a pass updates only the rows that are still candidates
+// (forward elimination) and X is found by back-substitution at the end: the
+// same results as Gauss-Jordan (X on the pivot variables is the unique solution
+// of the echelon system with free variables 0).  A pass:
+//   1. the pass's columns of every row are loaded once into LDS; one wave
+//      finds the pivots (pivot of a column = the first candidate row whose
+//      reduced value there is non-zero), keeping the first candidates reduced
+//      fraction-free in registers (no inverse on this serial chain);
 //   2. the pass's pivot rows fully reduced (unit vectors at the pass's pivot
 //      columns): PN_t = sum_s T[t][s] row_{q_s}, with T the inverse of the
 //      pivot block M[s][u] = row_{q_s}[col_u] (one wave, one inverse per pivot
-//      in parallel), kPB-term dot products over the full width;
-//   3. every other row r (earlier pivots included) becomes r - sum_t
-//      r[col_t] PN_t, the unique row of its coset with zeros at the pass's
-//      pivot columns, and the pivot rows become PN.
+//      in parallel), kPB-term dot products over the columns after the pass;
+//   3. every candidate row r becomes r - sum_t r[col_t] PN_t, the unique row
+//      of its coset with zeros at the pass's pivot columns, and the pass's
+//      pivot rows become PN; pivot rows of earlier passes are not touched.
 // The dot products run in FP64 with one factor split into 16-bit halves, so
 // every partial sum is exact (below 2^53); step 3, a product of the rows'
 // multipliers by the reduced pivot rows, runs on the FP64 matrix cores.  Rows
-// are never moved: pivot s is recorded in LDS.  Finally rank, pivots, X (free
-// variables 0) and consistency are written.
+// are never moved: pivot s is recorded in LDS.  Finally rank, pivots,
+// consistency and X (by back-substitution, free variables 0) are written.
 #include <algorithm>
 #include <vector>
 
