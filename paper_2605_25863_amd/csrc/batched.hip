@@ -118,10 +118,11 @@ __device__ __forceinline__ uint32_t sub_split(uint32_t x, double s1, double s0, 
     return (uint32_t)y;
 }
 
-// LDS of one system: pivot state per row (0 candidate, 1 pivot of an earlier
-// pass, 2 pivot of this pass), the pivot list, the pass's panel (later the
-// rows' multipliers), each pass pivot's index, and the coefficients T of the
-// reduced pivot rows over the pass-start pivot rows.
+// LDS of one system (the pass's panel and multipliers are in g_mult): pivot
+// state per row (0 candidate, 1 pivot of an earlier pass, 2 pivot of this
+// pass), each pass pivot's index, the pivot list, the coefficients T of the
+// reduced pivot rows over the pass-start pivot rows, the consistency flags, the
+// passes' first pivots, and the pivot search's state.
 struct BatchLds {
     uint8_t piv[kMaxRows];
     int8_t pt[kMaxRows];
