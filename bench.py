@@ -1,22 +1,31 @@
 """Benchmark: exact Gaussian elimination over F_p on one MI355X.
 
-Default workload (the one the metric is quoted on): one dense n = 8192 system
-with 16 right-hand sides over a seeded 31-bit prime field, entries uniform in
-[0, p).  A step is one full linac_solve on inputs already resident in HBM:
-pack [A | B], eliminate, extract X / rank / pivots / consistency.  The
-reported path is the library's AUTO choice (the blocked int8-MFMA path at this
-size); the plain path (one fused step kernel per pivot column) is timed on the
-same input and reported beside it.
+Headline workload (the largest single-system configuration): one dense
+n = 16384 system with 64 right-hand sides over a seeded 31-bit prime field,
+entries uniform in [0, p) (seed 3).  A step is one full linac_solve on inputs
+already resident in HBM: pack [A | B], eliminate, extract X / rank / pivots /
+consistency.  The reported path is the library's AUTO choice (the blocked
+int8-MFMA path at this size); the plain path (one fused step kernel per pivot
+column, scalar mulmod) is timed once on the same input and reported beside
+it.  The metric counts 2 n^3 / 3 operations per square system (right-hand
+sides excluded).
 
-The metric counts 2 n^3 / 3 operations per square system (right-hand sides
-excluded).  Prints one JSON line.
+Beside the headline the same JSON line carries the other workloads under
+"other_configs": c1 (n = 256, latency in microseconds per solve and per pivot
+step), c2 (n = 8192, 16 right-hand sides, AUTO and plain), c4 (4096 uneven
+systems in one persistent launch replayed from a hipGraph, systems/s, with the
+same systems solved one by one on the plain path) and c5 (64 instances of a
+12000 x 10000 shared-sparsity-pattern matrix, full RREF).  "cpu_baseline" is
+the C oracle timed on this host on a bounded sample of the headline
+distribution, plus one single-threaded n = 2048 run.
 
-    python bench.py [--config c2|c1|c3|c4|c5] [--path auto|plain|int8|fp64]
-                    [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--config c3|c1|c2|c4|c5] [--path auto|plain|int8|fp64]
+                    [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extras]
 
 Per-kernel rooflines come from one extra instrumented solve in which the
-library records a HIP event pair around every hot-kernel launch on its stream
-(outside the timed steps, so event recording does not slow them):
+library records a HIP event pair around every hot-kernel launch on the stream
+that kernel runs on (outside the timed steps, so event recording does not
+slow them):
   step          plain path, HBM-bound: 8 algorithmic bytes per element update
                 (int32 read + write), peak 8000 GB/s;
   leaf/trail    blocked path, int8 MFMA: 32 int8 operations per mod-p
@@ -39,6 +48,7 @@ library records a HIP event pair around every hot-kernel launch on its stream
                 element update (one pivot applied to one entry) is 2 FMAs of
                 an exact split product, 4 flops against 78.6 TFLOP/s.  The
                 bound reported is the nearer of the two, the other beside it.
+The headline "roofline" is the kernel with the largest total time.
 """
 
 from __future__ import annotations
@@ -151,35 +161,73 @@ def measured_traffic(kernel: str, workload: str, src_hash: str):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(target_s: float = 15.0):
-    """The C oracle (OpenMP over rows) on a bounded sample of the same workload:
-    calibrate at n = 1024, then one run sized for about target_s seconds."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_seconds(n: int, k: int, threads: int = 0) -> float:
+    """Wall time of the C oracle's Gauss-Jordan on one seeded dense n x n
+    system of the c3 distribution with k right-hand sides (generation
+    excluded)."""
     import oracle
     import workloads
+    A, B, p = workloads.config("c3", n=n)
+    M = np.concatenate([A.astype(np.uint64), B.astype(np.uint64)[:, :k]], axis=1)
+    t0 = time.perf_counter()
+    oracle.gauss_jordan(M, n, p, impl="c", threads=threads)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(target_s: float = 15.0, single_thread: bool = True):
+    """The C oracle (OpenMP over the rows of a step) on a bounded sample of the
+    headline workload: dense systems of the c3 distribution (seed 3, its
+    seeded 31-bit prime, 64 right-hand sides), calibrated at n = 1024 and then
+    run once at the size that takes about target_s seconds.  Beside it, one
+    single-threaded run at n = 2048 without right-hand sides, the size and
+    shape of the paper's single-thread CPU comparator (Sec. 4.1, Table 1)."""
+    import oracle
     threads = oracle.max_threads()
-
-    def run(n):
-        A, B, p = workloads.config("c2", n=n)
-        M = np.concatenate([A.astype(np.uint64), B.astype(np.uint64)], axis=1)
-        t0 = time.perf_counter()
-        oracle.gauss_jordan(M, n, p, impl="c")
-        return time.perf_counter() - t0
-
-    t1 = run(1024)
-    rate = gj_updates(1024, 1024, 1040) / t1
+    t1 = _oracle_seconds(1024, 64)
+    rate = gj_updates(1024, 1024, 1024 + 64) / t1
     n = 1024
-    for cand in (1536, 2048, 2560, 3072, 3584, 4096, 4608, 5120, 5632, 6144):
-        if gj_updates(cand, cand, cand + 16) / rate <= target_s:
+    for cand in range(1536, 8193, 512):
+        if gj_updates(cand, cand, cand + 64) / rate <= target_s:
             n = cand
-    t = run(n) if n != 1024 else t1
-    return {"value": round(metric_ops(n) / t / 1e9, 3), "unit": "GOP/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"C oracle Gauss-Jordan (uint64, %, OpenMP over rows) on the same seeded "
-                      f"distribution at n={n} with 16 right-hand sides; {t:.2f} s",
-            "seconds": round(t, 3), "n": n}
+    t = _oracle_seconds(n, 64) if n != 1024 else t1
+    rec = {"value": round(metric_ops(n) / t / 1e9, 3), "unit": "GOP/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"C oracle Gauss-Jordan (uint64, %, OpenMP over the rows of a step, "
+                     f"{threads} threads) on one dense n={n} system of the headline "
+                     f"distribution (seed 3, its 31-bit prime, 64 right-hand sides), "
+                     f"{t:.2f} s; the headline system itself (n=16384) would take about "
+                     f"{gj_updates(16384, 16384, 16448) / (gj_updates(n, n, n + 64) / t) / 60:.0f} "
+                     f"min at this rate",
+           "seconds": round(t, 3), "n": n, "cpu_model": _cpu_model(),
+           "affinity_cpus": len(os.sched_getaffinity(0)),
+           "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+    if single_thread:
+        ts = _oracle_seconds(2048, 0, threads=1)
+        # the paper's single-thread CPU fit (Sec. 4.1, Table 1): a3 x^3 + a2 x^2 + ...
+        fit = 1.76e-9 * 2048 ** 3 + 1.13e-6 * 2048 ** 2 + 1.92e-15 * 2048 + 7.61e-12
+        rec["single_thread_n2048"] = {
+            "seconds": round(ts, 3), "gop_per_s": round(metric_ops(2048) / ts / 1e9, 4),
+            "threads": 1, "shape": "2048 x 2048, no right-hand side (RREF)",
+            "paper_single_thread_fit_s": round(fit, 2)}
+    if threads > 1:
+        # restore the full thread count for later callers in this process
+        _oracle_seconds(64, 0, threads=threads)
+    return rec
 
 
 PATHS = {"auto": 0, "plain": 1, "int8": 2, "fp64": 3}
+KERNEL_SOURCES = ["plain.hip", "blocked.hip", "leaf.hip", "field.h"]
 
 
 def _resolved_plan(lx, m, n, path_name, panel):
@@ -237,12 +285,25 @@ def _rooflines(kinds, m, n, ncols, path_name, panel, src_hash, workload):
     return out
 
 
-def bench_dense(args):
+def _free_cuda():
+    import gc
+    import torch
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def bench_dense(config: str, steps: int, warmup: int, path_name_req: str = "auto",
+                panel_req: int = 0, n_override=None, plain_reps: int = 1, plain_warmup: int = 0,
+                instrument: bool = True):
+    """One dense system of workload c1..c3: linac_solve on the AUTO (or
+    requested) path, timed over `steps` calls after `warmup`; the plain path on
+    the same input beside it (`plain_reps` calls, 0 to skip)."""
     import torch
     import paper_2605_25863_amd as lx
     import workloads
 
-    A, B, p = workloads.config(args.config, n=args.n)
+    A, B, p = workloads.config(config, n=n_override)
     m, n = A.shape
     k = B.shape[1]
     dev = torch.device("cuda:0")
@@ -254,71 +315,105 @@ def bench_dense(args):
            torch.empty(min(m, n), dtype=torch.int32, device=dev),
            torch.empty(k, dtype=torch.uint8, device=dev))
     stream = torch.cuda.current_stream()
-    path_name, panel = _resolved_plan(lx, m, n, args.path, args.panel)
+    path_name, panel = _resolved_plan(lx, m, n, path_name_req, panel_req)
     path = PATHS[path_name]
-    ws = torch.empty(lx.solve_workspace_bytes(m, n, k, path, args.panel), dtype=torch.uint8,
+    ws = torch.empty(lx.solve_workspace_bytes(m, n, k, path, panel_req), dtype=torch.uint8,
                      device=dev)
 
     def timed_solves(path, ws, steps, warmup):
         for _ in range(warmup):
             lx.solve(At, Bt, p, path=path, out=out, workspace=ws, stream=stream,
-                     panel_width=args.panel)
+                     panel_width=panel_req)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
             lx.solve(At, Bt, p, path=path, out=out, workspace=ws, stream=stream,
-                     panel_width=args.panel)
+                     panel_width=panel_req)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
-    t_step = timed_solves(path, ws, args.steps, args.warmup)
+    t_step = timed_solves(path, ws, steps, warmup)
     rank = int(out[1].item())
     assert rank == min(m, n), f"unexpected rank {rank}"
     value = metric_ops(n) / t_step / 1e9
-
-    # instrumented pass: one event pair around every hot-kernel launch
-    cap = n + 4 * (n // 32 + 8) + 64
-    lt = lx.LaunchTimes(cap)
-    lx.solve(At, Bt, p, path=path, out=out, workspace=ws, stream=stream, panel_width=args.panel,
-             per_launch=lt)
-    kinds = lt.by_kind()
-    src_hash = kernel_source_hash(["plain.hip", "blocked.hip", "leaf.hip", "field.h"])
-    roofs = _rooflines(kinds, m, n, n + k, path_name, panel, src_hash, args.config)
-    dominant = max(roofs, key=lambda name: roofs[name]["total_ms"]) if roofs else None
-
-    rec = {
-        "metric": "mod-p elim GOP/s (2n^3/3 mulmod-add)",
-        "value": round(value, 3),
-        "unit": "GOP/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(t_step * 1e3, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32" if path_name == "plain" else ("i8-mfma/u32" if path_name == "int8"
-                                                      else "f64-mfma/u32"),
-        "data": "synthetic (seeded uniform residues)",
-        "config": {"workload": f"{args.config}: one dense n={n} system, {k} right-hand sides, "
-                               f"p={p}, {path_name} path", "n": n, "k": k, "p": p,
-                   "path": path_name, "panel": panel,
-                   "seed": {"c1": 1, "c2": 2, "c3": 3}[args.config]},
-        "roofline": roofs.get(dominant),
-        "rooflines": roofs,
-        "kernel_ms_by_kind": {kk: round(v[1], 3) for kk, v in kinds.items()},
-    }
-    if path_name != "plain" and not args.no_plain_compare:
+    rec = {"value": round(value, 3), "unit": "GOP/s", "ms_per_step": round(t_step * 1e3, 3),
+           "steps": steps, "warmup": warmup,
+           "dtype": "u32" if path_name == "plain" else ("i8-mfma/u32" if path_name == "int8"
+                                                         else "f64-mfma/u32"),
+           "config": {"workload": f"{config}: one dense n={n} system, {k} right-hand sides, "
+                                  f"p={p}, {path_name} path", "n": n, "k": k, "p": p,
+                      "path": path_name, "panel": panel,
+                      "seed": workloads.CONFIGS[config]["seed"]}}
+    if instrument:
+        # one extra solve with an event pair around every hot-kernel launch
+        cap = n + 4 * (n // 32 + 8) + 64
+        lt = lx.LaunchTimes(cap)
+        lx.solve(At, Bt, p, path=path, out=out, workspace=ws, stream=stream,
+                 panel_width=panel_req, per_launch=lt)
+        kinds = lt.by_kind()
+        src_hash = kernel_source_hash(KERNEL_SOURCES)
+        roofs = _rooflines(kinds, m, n, n + k, path_name, panel, src_hash, config)
+        dominant = max(roofs, key=lambda name: roofs[name]["total_ms"]) if roofs else None
+        rec["roofline"] = roofs.get(dominant)
+        rec["rooflines"] = roofs
+        rec["kernel_ms_by_kind"] = {kk: round(v[1], 3) for kk, v in kinds.items()}
+    if path_name != "plain" and plain_reps > 0:
+        del ws
+        _free_cuda()
         wsp = torch.empty(lx.solve_workspace_bytes(m, n, k, lx.PATH_PLAIN), dtype=torch.uint8,
                           device=dev)
-        tp = timed_solves(lx.PATH_PLAIN, wsp, max(1, min(args.steps, 3)), 1)
+        tp = timed_solves(lx.PATH_PLAIN, wsp, plain_reps, plain_warmup)
+        assert int(out[1].item()) == min(m, n)
         rec["plain"] = {"value": round(metric_ops(n) / tp / 1e9, 3), "unit": "GOP/s",
-                        "ms_per_step": round(tp * 1e3, 3),
+                        "ms_per_step": round(tp * 1e3, 3), "reps": plain_reps,
                         "speedup_of_reported_path": round(tp / t_step, 2)}
+        del wsp
+    del At, Bt, out
+    _free_cuda()
     return rec
 
 
-def bench_batched(args):
+def bench_c1_latency(reps: int = 50):
+    """c1 (n = 256, one right-hand side, p = 2^31 - 1): latency of one solve on
+    the AUTO path, in microseconds, and per pivot step."""
+    import torch
+    import paper_2605_25863_amd as lx
+    import workloads
+
+    A, B, p = workloads.config("c1")
+    n, k = A.shape[1], B.shape[1]
+    dev = torch.device("cuda:0")
+    At = torch.from_numpy(A.astype(np.int32)).to(dev)
+    Bt = torch.from_numpy(B.astype(np.int32)).to(dev)
+    out = (torch.empty((n, k), dtype=torch.int32, device=dev),
+           torch.zeros(1, dtype=torch.int32, device=dev),
+           torch.empty(n, dtype=torch.int32, device=dev),
+           torch.empty(k, dtype=torch.uint8, device=dev))
+    path_name, _ = _resolved_plan(lx, n, n, "auto", 0)
+    ws = torch.empty(lx.solve_workspace_bytes(n, n, k), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    timer = lx.HipTimer()
+    times = []
+    for i in range(reps + 5):
+        timer.record_begin(ctypes_stream(stream))
+        lx.solve(At, Bt, p, out=out, workspace=ws, stream=stream)
+        timer.record_end(ctypes_stream(stream))
+        t = timer.elapsed_ms()
+        if i >= 5:
+            times.append(t)
+    us = float(np.median(times)) * 1e3
+    return {"us_per_solve": round(us, 2), "us_per_step": round(us / n, 3),
+            "gop_per_s": round(metric_ops(n) / (us * 1e-6) / 1e9, 3), "path": path_name,
+            "reps": reps, "timing": "HIP events on the solve's stream, median",
+            "workload": "c1: one dense n=256 system, 1 right-hand side, p=2^31-1, seed 1"}
+
+
+def ctypes_stream(stream):
+    import ctypes
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def bench_batched(steps: int = 10, warmup: int = 2, plain_compare: bool = True):
     """The 4096-system workload: systems/s of the batched persistent launch
     (graph replay) next to the same systems solved one by one on the plain
     path."""
@@ -329,15 +424,15 @@ def bench_batched(args):
     systems = workloads.batched_systems()
     prep = lx.prepare_batched(systems)
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         lx.solve_batched(systems, prepared=prep, stream=stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         lx.solve_batched(systems, prepared=prep, stream=stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_per_step = wall * 1e3 / args.steps
+    ms_per_step = wall * 1e3 / steps
     sps = len(systems) / (ms_per_step / 1e3)
     ops = sum(metric_ops(s["n"]) for s in systems)
     model = [batched_pass_model(s["n"], s["n"], s["k"]) for s in systems]
@@ -363,15 +458,13 @@ def bench_batched(args):
                                              kernel_source_hash(["batched.hip", "field.h"])),
                  other["bound"]: {kk: vv for kk, vv in other.items() if kk != "bound"}})
     rec = {"metric": "systems/s batched (4096 uneven systems, one persistent launch)",
-           "value": round(sps, 1), "unit": "systems/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
-           "data": "synthetic (seeded uniform residues)",
+           "value": round(sps, 1), "unit": "systems/s", "steps": steps, "warmup": warmup,
+           "ms_per_step": round(ms_per_step, 3), "dtype": "u32",
            "config": {"workload": "c4: 4096 systems, n~U{32..512}, k~U{1..8}, a seeded 31-bit "
                                   "prime each, 205 rank deficient"},
            "gop_per_s": round(ops / (ms_per_step / 1e3) / 1e9, 2),
            "roofline": roof}
-    if not args.no_plain_compare:
+    if plain_compare:
         # the same systems, one linac_solve each on the plain path
         wss = []
         for it in prep["items"]:
@@ -388,28 +481,29 @@ def bench_batched(args):
         tp = time.perf_counter() - t0
         rec["plain_systems_per_s"] = round(len(systems) / tp, 1)
         rec["speedup_vs_plain"] = round(sps / (len(systems) / tp), 2)
+        del wss
+    del prep
+    _free_cuda()
     return rec
 
 
-def bench_sparse_pattern(args):
-    """c5: instances of a 12000 x 10000 sparse-pattern matrix (rank about 9500),
-    full RREF with pivot columns, p = 2^31 - 1, one linac_rref per instance on
-    one stream (all inputs resident in HBM)."""
+def bench_sparse_pattern(count: int = 64, steps: int = 2, warmup: int = 1,
+                         path_name: str = "int8", panel: int = 0):
+    """c5: `count` instances of a 12000 x 10000 sparse-pattern matrix (rank
+    about 9500), full RREF with pivot columns, p = 2^31 - 1, all resident in
+    HBM.  A step reduces every instance (the working copies are restored from
+    pristine device copies outside the timed region)."""
     import torch
     import paper_2605_25863_amd as lx
     import workloads
 
-    count = args.instances
-    mats = []
-    for _, A in workloads.sparse_pattern_instances(instances=range(count)):
-        mats.append(torch.from_numpy(A.view(np.int32)).to("cuda:0"))
+    dev = torch.device("cuda:0")
+    mats = [A for _, A in workloads.sparse_pattern_instances_torch(dev, count=count)]
     m, n = mats[0].shape
     p = workloads.MERSENNE31
-    path_name = "plain" if args.path == "plain" else ("fp64" if args.path == "fp64" else "int8")
     path = PATHS[path_name]
     work = [torch.empty_like(A) for A in mats]
-    ws = torch.empty(lx.rref_workspace_bytes(m, n, path, args.panel), dtype=torch.uint8,
-                     device="cuda:0")
+    ws = torch.empty(lx.rref_workspace_bytes(m, n, path, panel), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
     ranks = []
 
@@ -418,7 +512,7 @@ def bench_sparse_pattern(args):
             Wk.copy_(A)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        outs = [lx.rref(Wk, p, inplace=True, path=path, panel_width=args.panel, stream=stream,
+        outs = [lx.rref(Wk, p, inplace=True, path=path, panel_width=panel, stream=stream,
                         workspace=ws) for Wk in work]
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -426,21 +520,23 @@ def bench_sparse_pattern(args):
             ranks.extend(int(o[1].item()) for o in outs)
         return dt
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         one_pass()
-    ts = [one_pass(collect=(i == 0)) for i in range(args.steps)]
+    ts = [one_pass(collect=(i == 0)) for i in range(steps)]
     t = float(np.median(ts))
     ops = sum(rect_metric_ops(m, n, rr) for rr in ranks)
-    return {"metric": "mod-p elim GOP/s (2n^3/3 convention, rank-r rectangular)",
-            "value": round(ops / t / 1e9, 3), "unit": "GOP/s", "n_gpus": 1, "steps": args.steps,
-            "warmup": args.warmup, "ms_per_step": round(t * 1e3, 3), "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "i8-mfma/u32",
-            "data": "synthetic (seeded shared sparsity pattern, stand-in for sample-point systems)",
-            "config": {"workload": f"c5: {count} instances of {m}x{n}, 200 nnz per independent "
-                                   f"row, 2500 dependent rows, p=2^31-1, full RREF, "
-                                   f"{path_name} path",
-                       "instances": count, "ranks": sorted(set(ranks))},
-            "ms_per_instance": round(t * 1e3 / count, 3)}
+    rec = {"metric": "mod-p elim GOP/s (2n^3/3 convention, rank-r rectangular)",
+           "value": round(ops / t / 1e9, 3), "unit": "GOP/s", "steps": steps, "warmup": warmup,
+           "ms_per_step": round(t * 1e3, 3), "dtype": "i8-mfma/u32",
+           "data": "synthetic (seeded shared sparsity pattern, stand-in for sample-point systems)",
+           "config": {"workload": f"c5: {count} instances of {m}x{n}, 200 nnz per independent "
+                                  f"row, 2500 dependent rows, p=2^31-1, full RREF, "
+                                  f"{path_name} path", "instances": count,
+                      "ranks": sorted(set(ranks))},
+           "ms_per_instance": round(t * 1e3 / count, 3)}
+    del mats, work, ws
+    _free_cuda()
+    return rec
 
 
 def copy_calibration(mib: int = 1024, reps: int = 3):
@@ -457,18 +553,27 @@ def copy_calibration(mib: int = 1024, reps: int = 3):
     print(json.dumps({"copy_calibration_bytes": n * 4, "reps": reps}), flush=True)
 
 
+def _progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4", "c5"],
+                    help="workload of the headline line (default c3, the largest single "
+                         "system); c1, c2, c4 and c5 are also reported beside it unless "
+                         "--no-extras")
     ap.add_argument("--n", type=int, default=None, help="resize the dense workload")
     ap.add_argument("--path", default="auto", choices=list(PATHS))
     ap.add_argument("--panel", type=int, default=0, help="blocked panel width (0 = tuned)")
     ap.add_argument("--instances", type=int, default=64, help="c5 instances")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain-compare", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline workload (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -476,20 +581,47 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); --gpus must be 1",
+              file=sys.stderr)
         sys.exit(2)
+    plain_reps = 0 if args.no_plain_compare else 1
+    common = {"n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+              "data": "synthetic (seeded uniform residues)"}
     if args.config == "c4":
-        print(json.dumps(bench_batched(args)), flush=True)
-        return
-    if args.config == "c5":
-        print(json.dumps(bench_sparse_pattern(args)), flush=True)
-        return
-    rec = bench_dense(args)
-    if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline()
+        rec = bench_batched(args.steps, args.warmup, not args.no_plain_compare)
+    elif args.config == "c5":
+        rec = bench_sparse_pattern(args.instances, args.steps, args.warmup,
+                                   "plain" if args.path == "plain" else
+                                   ("fp64" if args.path == "fp64" else "int8"), args.panel)
     else:
-        rec["cpu_baseline"] = None
-    print(json.dumps(rec), flush=True)
+        _progress(f"{args.config} headline")
+        rec = bench_dense(args.config, args.steps, args.warmup, args.path, args.panel, args.n,
+                          plain_reps=plain_reps)
+        rec["metric"] = "mod-p elim GOP/s (2n^3/3 mulmod-add)"
+    out = {"metric": rec.pop("metric"), "value": rec.pop("value"), "unit": rec.pop("unit"),
+           "n_gpus": 1, "steps": rec.pop("steps"), "warmup": rec.pop("warmup"),
+           "ms_per_step": rec.pop("ms_per_step"), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": rec.pop("dtype"),
+           "data": rec.pop("data", common["data"]), "config": rec.pop("config")}
+    out.update(rec)
+    if args.config == "c3" and not args.no_extras and args.n is None:
+        extras = {}
+        _progress("c1 latency")
+        extras["c1"] = bench_c1_latency()
+        _progress("c2")
+        c2 = bench_dense("c2", 5, 1, plain_reps=plain_reps, instrument=False)
+        extras["c2"] = c2
+        _progress("c4 batch")
+        extras["c4"] = bench_batched(10, 2, not args.no_plain_compare)
+        _progress("c5 sparse-pattern instances")
+        extras["c5"] = bench_sparse_pattern(args.instances, 2, 1)
+        out["other_configs"] = extras
+    if not args.no_cpu_baseline and args.config in ("c1", "c2", "c3"):
+        _progress("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline()
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

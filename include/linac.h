@@ -169,7 +169,10 @@ linac_status linac_solve_batched_workspace(const linac_system* sys, int32_t coun
  * this (ws, plan) pair on first use, replaying it on later calls.  Per system the
  * results equal those of linac_solve.  Each system must fit one workgroup's
  * bookkeeping: m <= 1024 and n + k <= 2048, else LINAC_E_UNSUPPORTED (before
- * any device work; larger systems go through linac_solve).
+ * any device work; larger systems go through linac_solve).  With
+ * opts->validate every entry of every A and B is checked against its system's
+ * prime first (synchronously); an entry >= p returns LINAC_E_RANGE before the
+ * batch runs.
  */
 linac_status linac_solve_batched(const linac_system* sys, int32_t count, void* ws,
                                  size_t ws_bytes, const linac_opts* opts, hipStream_t s);

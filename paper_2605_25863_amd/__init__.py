@@ -380,7 +380,8 @@ def solve_workspace_bytes(m: int, n: int, k: int, path: int = PATH_AUTO,
 
 
 def solve_batched(systems, *, path: int = PATH_AUTO, verbose: bool = False, stream=None,
-                  events: HipTimer | None = None, launches=None, prepared=None, per_launch=None):
+                  events: HipTimer | None = None, launches=None, prepared=None, per_launch=None,
+                  validate: bool = False):
     """Solve many independent systems in one launch.
 
     ``systems``: list of dicts {A, B, p} (numpy or device int32 tensors).
@@ -391,7 +392,7 @@ def solve_batched(systems, *, path: int = PATH_AUTO, verbose: bool = False, stre
     torch = _torch()
     prep = prepared if prepared is not None else prepare_batched(systems)
     lib = _load()
-    o = _opts(path, 0, False, verbose, events, launches, per_launch)
+    o = _opts(path, 0, validate, verbose, events, launches, per_launch)
     _check(lib.linac_solve_batched(prep["desc"], len(prep["items"]), _ptr(prep["ws"]),
                                    prep["ws"].numel(), ctypes.byref(o), _stream(torch, stream)),
            "linac_solve_batched")

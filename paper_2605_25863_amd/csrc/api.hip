@@ -501,6 +501,22 @@ linac_status linac_solve_batched(const linac_system* sys, int32_t count, void* w
     }
     const size_t need = batched_workspace(sys, count);
     if (!ws || ws_bytes < need) return LINAC_E_WORKSPACE;
+    if (opts && opts->validate) {
+        // every system's A and B against its own prime; the flag borrows the
+        // queue counter's word, which the launch resets before use
+        uint32_t* flag = (uint32_t*)ws;
+        uint32_t zero = 0, host = 0;
+        hipError_t e = hipMemcpyAsync(flag, &zero, sizeof(zero), hipMemcpyHostToDevice, s);
+        for (int32_t i = 0; i < count && e == hipSuccess; ++i) {
+            const linac_system& d = sys[i];
+            e = launch_range_check(d.A, d.m, d.n, d.lda, d.p, flag, s);
+            if (e == hipSuccess) e = launch_range_check(d.B, d.m, d.k, d.ldb, d.p, flag, s);
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(&host, flag, sizeof(host), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e);
+        if (host) return LINAC_E_RANGE;
+    }
 
     // queue order: decreasing Gauss-Jordan cost m * n * (n + k)
     std::vector<int32_t> order(count);

@@ -153,3 +153,19 @@ def test_pivot_search_fallbacks(gpu):
     add(A, workloads.uniform(rng, (64, 1), 7), 7)
     print("fallback batch", [(s["A"].shape, s["B"].shape[1], s["p"]) for s in systems], flush=True)
     _check_all(systems, lx.solve_batched(systems), tag="fallbacks")
+
+
+def test_validate_rejects_out_of_range_entry(gpu):
+    """opts.validate checks every system of a batch against its own prime: one
+    entry equal to p in one system's B makes the whole call return
+    LINAC_E_RANGE before the batch runs; the same batch without it solves."""
+    systems = workloads.batched_systems(seed=44, count=12, n_lo=8, n_hi=40)
+    ref = oracle.solve_many(systems)
+    _check_all(systems, lx.solve_batched(systems, validate=True), ref, tag="validate ok")
+    bad = [dict(s) for s in systems]
+    bad[7] = dict(bad[7])
+    bad[7]["B"] = bad[7]["B"].copy()
+    bad[7]["B"][3, 0] = bad[7]["p"]
+    with pytest.raises(lx.LinacError) as e:
+        lx.solve_batched(bad, validate=True)
+    assert e.value.status == 4

@@ -3,9 +3,11 @@ product) against the CPU oracle, bit for bit.
 
 Panel widths are chosen so that panels are ragged (n not a multiple of the
 width), free columns fall inside panels, and the last panel is partial.  At the
-full n = 16384 size the solution is checked with the certificate A X = B on a
-seeded sample of rows (A is dense, so any wrong entry of X breaks almost every
-row) plus rank = n and pivots 0..n-1.
+full sizes (n = 8192 and 16384) the results are checked by certificates on
+every row: rank = n, pivots 0..n-1, A X = B (exactly at n = 8192, by
+Freivalds' check at n = 16384), and at n = 16384 also the RREF of [A | B],
+whose left block must be the identity and whose right block must solve the
+system.
 """
 
 from __future__ import annotations
@@ -15,6 +17,7 @@ import pytest
 
 import oracle
 import workloads
+from tests import certs
 import paper_2605_25863_amd as lx
 
 pytestmark = pytest.mark.gpu
@@ -64,6 +67,9 @@ def _cmp_rref(A, p, panel, tag):
     (500, 420, 0, 65521, 256),
     (129, 700, 9, None, 128),
     (600, 600, 8, None, 512),
+    (700, 650, 6, None, 192),
+    (900, 880, 5, None, 384),
+    (1000, 1000, 3, workloads.MERSENNE31, 384),
     (64, 64, 1, 2, 32),
     (100, 100, 2, 3, 64),
 ])
@@ -115,12 +121,79 @@ def test_small_cases_blocked(gpu):
         _cmp(c["A"], c["B"], c["p"], 32, tag)
 
 
-def test_blocked_equals_plain_c2_slice(gpu):
+def test_c2_slice_against_oracle(gpu):
+    """n = 1536 of the c2 distribution (16 right-hand sides, panel 256 and the
+    tuned panel), bit for bit against the oracle."""
     A, B, p = workloads.config("c2", n=1536)
-    a = _solve(A, B, p, 256, path=INT8)
-    b = _solve(A, B, p, 256, path=lx.PATH_PLAIN)
-    for x, y in zip(a, b):
-        assert np.array_equal(np.asarray(x), np.asarray(y))
+    ref = oracle.solve(A, B, p)
+    for panel in (256, 0):
+        got = _solve(A, B, p, panel, path=INT8)
+        for name, g, r in zip(("X", "rank", "pivots", "consistent"), got, ref):
+            assert np.array_equal(np.asarray(g), np.asarray(r)), f"c2 slice panel={panel}: {name}"
+
+
+@pytest.mark.parametrize("panel", [192, 384])
+def test_structured_wide_panels(gpu, panel):
+    """Free columns inside 192- and 384-wide panels, a zero block, duplicated
+    columns, inconsistent right-hand sides; solve and RREF against the oracle."""
+    rng = np.random.default_rng(panel)
+    p = workloads.draw_prime31(rng)
+    Z = workloads.uniform(rng, (820, 900), p)
+    Z[:, 30:45] = 0
+    Z[:, 200:260] = Z[:, 0:60]
+    Z[:, 383:390] = 0
+    Z[700:] = Z[:120]
+    B = workloads.uniform(rng, (820, 4), p)
+    B[:, 1] = oracle.matmul_mod(Z, workloads.uniform(rng, (900, 1), p), p)[:, 0]
+    tag = f"wide panel={panel}"
+    print(tag, flush=True)
+    _cmp(Z, B, p, panel, tag)
+    _cmp_rref(Z, p, panel, tag)
+
+
+def test_lookahead_off(gpu):
+    """The blocked int8 path with the look-ahead switched off in the tuning
+    table (the table can select it), against the oracle; the shipped table is
+    restored afterwards."""
+    rng = np.random.default_rng(5150)
+    p = workloads.draw_prime31(rng)
+    A = workloads.uniform(rng, (1100, 1000), p)
+    A[:, 100:110] = 0
+    B = workloads.uniform(rng, (1100, 3), p)
+    lx.load_tuning('{"lookahead": 0}')
+    try:
+        for panel in (128, 256):
+            tag = f"lookahead off panel={panel}"
+            print(tag, flush=True)
+            _cmp(A, B, p, panel, tag)
+            _cmp_rref(A, p, panel, tag)
+    finally:
+        lx.restore_tuning()
+
+
+def test_auto_plan_sizes_against_oracle(gpu):
+    """The AUTO path at sizes where the shipped table picks each of its panel
+    widths (and the plain/blocked crossover), against the oracle."""
+    import json
+    table = json.load(open(lx.TUNING_FILE))
+    sizes = {int(table.get("blocked_min", 1024)), int(table.get("blocked_min", 1024)) - 1}
+    prev = 0
+    for rule in table.get("panel", []):
+        lo = max(prev + 1, int(table.get("blocked_min", 1024)))
+        hi = int(rule["n_max"])
+        if lo <= hi:
+            sizes.add(min(hi, lo + 37))
+        prev = hi
+    for n in sorted(s for s in sizes if s <= 2600):
+        A, B, p = workloads.config("c2", n=n)
+        A, B = A[:, :n], B[:, :3]
+        path, panel = lx.plan(n, n)
+        tag = f"auto n={n} plan=({path},{panel})"
+        print(tag, flush=True)
+        got = _solve(A, B, p, 0, path=lx.PATH_AUTO)
+        ref = oracle.solve(A, B, p)
+        for name, g, r in zip(("X", "rank", "pivots", "consistent"), got, ref):
+            assert np.array_equal(np.asarray(g), np.asarray(r)), f"{tag}: {name}"
 
 
 def test_c1_blocked(gpu):
@@ -137,13 +210,29 @@ def test_c2_full_size_blocked(gpu):
 
 
 def test_c3_full_size_blocked(gpu):
-    """n = 16384, 64 right-hand sides: rank, pivots and A X = B on 512 seeded rows."""
+    """n = 16384, 64 right-hand sides: rank, pivots and A X = B on every row
+    (Freivalds), for the solve and for the RREF of [A | B]."""
+    import torch
     A, B, p = workloads.config("c3")
-    print("c3 blocked full size", flush=True)
-    X, r, piv, cons = _solve(A, B, p, 256)
-    assert r == 16384 and np.array_equal(piv, np.arange(16384)) and cons.all()
-    rows = np.random.default_rng(3).choice(16384, size=512, replace=False)
-    assert np.array_equal(oracle.matmul_mod(A[rows], X, p), B[rows].astype(np.uint64))
+    n = A.shape[1]
+    print("c3 blocked full size: solve", flush=True)
+    X, r, piv, cons = _solve(A, B, p, 0)
+    assert r == n and np.array_equal(piv, np.arange(n)) and cons.all()
+    assert certs.freivalds_solution(A, X, B, p), "c3 solve: A X != B"
+    print("c3 blocked full size: rref of [A | B]", flush=True)
+    M = torch.from_numpy(np.concatenate([A, B], axis=1).astype(np.int32)).cuda()
+    R, rank, pv = lx.rref(M, p, inplace=True, path=INT8)
+    torch.cuda.synchronize()
+    assert int(rank.item()) == n
+    assert np.array_equal(pv.cpu().numpy()[:n], np.arange(n))
+    R = R.cpu().numpy().view(np.uint32)
+    del M
+    left = R[:, :n]
+    assert np.count_nonzero(left) == n and np.all(np.diagonal(left) == 1), "left block is not I"
+    del left
+    XR = np.ascontiguousarray(R[:, n:])
+    assert np.array_equal(XR, X), "RREF right block differs from the solve's X"
+    assert certs.freivalds_solution(A, XR, B, p), "c3 rref: right block does not solve A X = B"
 
 
 FP64 = lx.PATH_BLOCKED_FP64

@@ -38,6 +38,7 @@ __all__ = [
     "config",
     "batched_systems",
     "sparse_pattern_instances",
+    "sparse_pattern_instances_torch",
     "small_cases",
     "vandermonde_nodes",
 ]
@@ -183,6 +184,29 @@ def batched_systems(seed: int = 4, count: int = 4096, n_lo: int = 32, n_hi: int 
     return out
 
 
+def _sparse_pattern(seed: int, count: int, m: int, n: int, base_rows: int, nnz: int):
+    """The shared structure of the c5 family: per base row its ``nnz`` column
+    positions, per dependent row its two source base rows, the shared row
+    permutation, and one seed sequence per instance."""
+    root = np.random.SeedSequence(seed)
+    pat_rng = np.random.default_rng(root.spawn(1)[0])
+    cols = np.stack([pat_rng.choice(n, size=nnz, replace=False) for _ in range(base_rows)])
+    dep = np.stack([pat_rng.choice(base_rows, size=2, replace=False)
+                    for _ in range(m - base_rows)])
+    perm = pat_rng.permutation(m)
+    children = np.random.SeedSequence([seed, 1]).spawn(count)
+    return cols, dep, perm, children
+
+
+def _instance_draws(child, m: int, base_rows: int, nnz: int, p: int):
+    """One instance's values at the shared positions and its dependent-row
+    coefficients, both uniform in [1, p)."""
+    rng = np.random.default_rng(child)
+    vals = rng.integers(1, p, size=(base_rows, nnz), dtype=np.uint64)
+    coef = rng.integers(1, p, size=(m - base_rows, 2), dtype=np.uint64)
+    return vals, coef
+
+
 def sparse_pattern_instances(seed: int = 5, count: int = 64, m: int = 12000, n: int = 10000,
                              base_rows: int = 9500, nnz: int = 200, p: int = MERSENNE31,
                              instances=None):
@@ -196,18 +220,10 @@ def sparse_pattern_instances(seed: int = 5, count: int = 64, m: int = 12000, n: 
     a subset of instance indices to materialise (default: all).
     Yields (index, A) with A an m x n uint32 array.
     """
-    root = np.random.SeedSequence(seed)
-    pat_rng = np.random.default_rng(root.spawn(1)[0])
-    cols = np.stack([pat_rng.choice(n, size=nnz, replace=False) for _ in range(base_rows)])
-    dep = np.stack([pat_rng.choice(base_rows, size=2, replace=False)
-                    for _ in range(m - base_rows)])
-    perm = pat_rng.permutation(m)
-    children = np.random.SeedSequence([seed, 1]).spawn(count)
+    cols, dep, perm, children = _sparse_pattern(seed, count, m, n, base_rows, nnz)
     wanted = range(count) if instances is None else instances
     for idx in wanted:
-        rng = np.random.default_rng(children[idx])
-        vals = rng.integers(1, p, size=(base_rows, nnz), dtype=np.uint64)
-        coef = rng.integers(1, p, size=(m - base_rows, 2), dtype=np.uint64)
+        vals, coef = _instance_draws(children[idx], m, base_rows, nnz, p)
         base = np.zeros((base_rows, n), dtype=np.uint64)
         np.put_along_axis(base, cols, vals, axis=1)
         A = np.zeros((m, n), dtype=np.uint64)
@@ -217,6 +233,38 @@ def sparse_pattern_instances(seed: int = 5, count: int = 64, m: int = 12000, n: 
             # products < 2^62 and their sum < 2^63 fit uint64
             A[base_rows + t] = (coef[t, 0] * base[a] % p + coef[t, 1] * base[b] % p) % p
         yield idx, A[perm].astype(np.uint32)
+
+
+def sparse_pattern_instances_torch(device, seed: int = 5, count: int = 64, m: int = 12000,
+                                   n: int = 10000, base_rows: int = 9500, nnz: int = 200,
+                                   p: int = MERSENNE31, instances=None):
+    """The same matrices as ``sparse_pattern_instances``, assembled with torch
+    on ``device`` (the random draws stay on the host, in the same order), so
+    that a full-size batch need not pass through host memory.  Yields
+    (index, A) with A an m x n int32 tensor (residues below 2^31)."""
+    import torch
+    cols, dep, perm, children = _sparse_pattern(seed, count, m, n, base_rows, nnz)
+    cols_t = torch.from_numpy(cols.astype(np.int64)).to(device)
+    dep_t = torch.from_numpy(dep.astype(np.int64)).to(device)
+    perm_t = torch.from_numpy(perm.astype(np.int64)).to(device)
+    wanted = range(count) if instances is None else instances
+    for idx in wanted:
+        vals, coef = _instance_draws(children[idx], m, base_rows, nnz, p)
+        vals_t = torch.from_numpy(vals.astype(np.int64)).to(device)
+        coef_t = torch.from_numpy(coef.astype(np.int64)).to(device)
+        A = torch.zeros((m, n), dtype=torch.int64, device=device)
+        A[:base_rows].scatter_(1, cols_t, vals_t)
+        step = 512
+        for t0 in range(0, m - base_rows, step):
+            t1 = min(t0 + step, m - base_rows)
+            ra = A[dep_t[t0:t1, 0]]
+            rb = A[dep_t[t0:t1, 1]]
+            # products < 2^62 and their sum < 2^63 fit int64
+            A[base_rows + t0: base_rows + t1] = (coef_t[t0:t1, :1] * ra % p
+                                                 + coef_t[t0:t1, 1:] * rb % p) % p
+            del ra, rb
+        yield idx, A[perm_t].to(torch.int32)
+        del A
 
 
 SMALL_PRIMES = (2, 3, 5, 7, 65521, (1 << 20) + 7, MERSENNE31)
