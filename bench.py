@@ -110,20 +110,23 @@ def rect_metric_ops(m: int, n: int, r: int) -> float:
     return 2.0 * (m * n * r - (m + n) * r * r / 2.0 + r ** 3 / 3.0)
 
 
-def blocked_work(m: int, n: int, ncols: int, panel: int):
-    """Algorithmic work of the two-level blocked path: mod-p multiply-adds of
-    the leaf products (K = leaf width, M = m, N = panel width + leaf width: the
-    leaf's own columns, the panel columns after it and the transform block up
-    to it) and of the trailing products (K = panel width, N = trailing
-    columns)."""
+def blocked_work(m: int, n: int, ncols: int, panel: int, forward: bool = False):
+    """Algorithmic work of the two-level blocked path on a full-rank system:
+    mod-p multiply-adds of the leaf products (K = leaf width, N = panel width +
+    leaf width: the leaf's own columns, the panel columns after it and the
+    transform block up to it) and of the trailing products (K = panel width, N
+    = trailing columns), over every row (Gauss-Jordan) or, for a solve
+    (forward elimination), over the rows that are not pivots of an earlier
+    panel: m - j0 of them at panel j0."""
     leaf_macs = 0
     trail_macs = 0
     for j0 in range(0, n, panel):
         wj = min(panel, n - j0)
+        rows = m - min(j0, m) if forward else m
         for l0 in range(0, wj, LEAF):
             wl = min(LEAF, wj - l0)
-            leaf_macs += m * (wj + wl) * wl
-        trail_macs += m * (ncols - j0 - wj) * wj
+            leaf_macs += rows * (wj + wl) * wl
+        trail_macs += rows * (ncols - j0 - wj) * wj
     return leaf_macs, trail_macs
 
 
@@ -248,7 +251,9 @@ def _rooflines(kinds, m, n, ncols, path_name, panel, src_hash, workload):
                            "achieved": 8.0 * upd / (ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s"}
     else:
-        leaf_macs, trail_macs = blocked_work(m, n, ncols, panel)
+        # a solve with right-hand sides runs forward elimination on the int8 path
+        leaf_macs, trail_macs = blocked_work(m, n, ncols, panel,
+                                             forward=path_name == "int8" and ncols > n)
         per_mac_ops, peak, unit = (32.0, I8_PEAK_TOPS, "TOP/s") if path_name == "int8" else \
             (2.0, FP64_PEAK_TFLOPS, "TFLOP/s")
         int8 = path_name == "int8"
@@ -491,8 +496,9 @@ def bench_sparse_pattern(count: int = 64, steps: int = 2, warmup: int = 1,
                          path_name: str = "int8", panel: int = 0):
     """c5: `count` instances of a 12000 x 10000 sparse-pattern matrix (rank
     about 9500), full RREF with pivot columns, p = 2^31 - 1, all resident in
-    HBM.  A step reduces every instance (the working copies are restored from
-    pristine device copies outside the timed region)."""
+    HBM.  A step is one linac_rref_batched call over every instance (the
+    working copies are restored from pristine device copies outside the timed
+    region)."""
     import torch
     import paper_2605_25863_amd as lx
     import workloads
@@ -503,7 +509,10 @@ def bench_sparse_pattern(count: int = 64, steps: int = 2, warmup: int = 1,
     p = workloads.MERSENNE31
     path = PATHS[path_name]
     work = [torch.empty_like(A) for A in mats]
-    ws = torch.empty(lx.rref_workspace_bytes(m, n, path, panel), dtype=torch.uint8, device=dev)
+    ws = torch.empty(lx.rref_batched_workspace_bytes([(m, n)] * count, path, panel),
+                     dtype=torch.uint8, device=dev)
+    outs = [(torch.zeros(1, dtype=torch.int32, device=dev),
+             torch.empty(min(m, n), dtype=torch.int32, device=dev)) for _ in range(count)]
     stream = torch.cuda.current_stream()
     ranks = []
 
@@ -512,12 +521,12 @@ def bench_sparse_pattern(count: int = 64, steps: int = 2, warmup: int = 1,
             Wk.copy_(A)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        outs = [lx.rref(Wk, p, inplace=True, path=path, panel_width=panel, stream=stream,
-                        workspace=ws) for Wk in work]
+        lx.rref_batched(work, p, inplace=True, path=path, panel_width=panel, stream=stream,
+                        workspace=ws, outs=outs)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         if collect:
-            ranks.extend(int(o[1].item()) for o in outs)
+            ranks.extend(int(r.item()) for r, _ in outs)
         return dt
 
     for _ in range(warmup):
@@ -531,12 +540,113 @@ def bench_sparse_pattern(count: int = 64, steps: int = 2, warmup: int = 1,
            "data": "synthetic (seeded shared sparsity pattern, stand-in for sample-point systems)",
            "config": {"workload": f"c5: {count} instances of {m}x{n}, 200 nnz per independent "
                                   f"row, 2500 dependent rows, p=2^31-1, full RREF, "
-                                  f"{path_name} path", "instances": count,
+                                  f"{path_name} path, one linac_rref_batched call",
+                      "instances": count, "lanes": _rref_lanes(),
                       "ranks": sorted(set(ranks))},
            "ms_per_instance": round(t * 1e3 / count, 3)}
     del mats, work, ws
     _free_cuda()
     return rec
+
+
+def bench_load_matrix(reps: int = 20):
+    """System construction (Sec. 3.3): the 20000 x 20000 monomial matrix of the
+    construction workload (48 basis variables, degrees 1..12 padded to 12), one
+    linac_load_matrix launch timed with HIP events on its stream.  Roofs: the
+    output write (4 bytes per entry) against HBM, and the FP64 chain (d - 1
+    modular products per entry, 6 FP64 instructions each) against 256 CU x 64
+    lanes x 2.4 GHz."""
+    import torch
+    import paper_2605_25863_amd as lx
+    import workloads
+    cfg = workloads.LM_CONFIG
+    bases, L, p = workloads.monomial_system(**cfg)
+    dev = torch.device("cuda:0")
+    Bt = torch.from_numpy(bases.astype(np.int32)).to(dev)
+    Lt = torch.from_numpy(L).to(dev)
+    A = torch.empty((cfg["nrows"], cfg["ncols"]), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        lx.load_matrix(Bt, Lt, p, out=A, stream=stream)
+    timer = lx.HipTimer()
+    sptr = ctypes_stream(stream)
+    timer.record_begin(sptr)
+    for _ in range(reps):
+        lx.load_matrix(Bt, Lt, p, out=A, stream=stream)
+    timer.record_end(sptr)
+    t = timer.elapsed_ms() / reps / 1e3
+    entries = cfg["nrows"] * cfg["ncols"]
+    d = cfg["d"]
+    out_bytes = 4.0 * entries + 4.0 * cfg["nrows"] * cfg["nbasis"] + 4.0 * cfg["ncols"] * d
+    mulmods = entries * (d - 1)
+    alu_peak = 256 * 64 * 2.4e9 / 6.0  # modular products per second
+    rec = {"metric": "entries/s (A[r,c] = prod_t bases[r, lindices[c,t]] mod p)",
+           "value": round(entries / t, 1), "unit": "entries/s", "ms_per_launch": round(t * 1e3, 4),
+           "reps": reps, "dtype": "f64 chain/u32",
+           "config": {"workload": f"system construction: {cfg['nrows']} sampling points x "
+                                  f"{cfg['ncols']} monomials, {cfg['nbasis']} basis variables, "
+                                  f"degree {d}, p=2^31-1, seed {cfg['seed']}"},
+           "roofline": {"bound": "alu", "kernel": "load_matrix_kernel<16, true>",
+                        "achieved": round(mulmods / t / 1e9, 2),
+                        "peak": round(alu_peak / 1e9, 1), "unit": "G modmul/s",
+                        "frac": round(mulmods / t / alu_peak, 4),
+                        "hbm": {"achieved": round(out_bytes / t / 1e9, 1), "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": round(out_bytes / t / 1e9 / HBM_PEAK_GBS, 4)},
+                        "traffic": None}}
+    del Bt, Lt, A
+    _free_cuda()
+    return rec
+
+
+def bench_colstep(n: int = 2048, k: int = 4, reps: int = 2):
+    """The column-step paths: a dense n x n solve over the 62-bit prime
+    2^62 - 57 (uint64 residues) and the LUP factorisation of a dense n x n
+    matrix over 2^31 - 1, each timed end to end with HIP events."""
+    import torch
+    import paper_2605_25863_amd as lx
+    import workloads
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(21)
+    p62 = 4611686018427387847
+    A = torch.from_numpy(rng.integers(0, p62, size=(n, n), dtype=np.int64)).to(dev)
+    B = torch.from_numpy(rng.integers(0, p62, size=(n, k), dtype=np.int64)).to(dev)
+    stream = torch.cuda.current_stream()
+    sptr = ctypes_stream(stream)
+    out = {}
+    lx.solve_u64(A, B, p62, stream=stream)
+    timer = lx.HipTimer()
+    timer.record_begin(sptr)
+    for _ in range(reps):
+        X, r, piv, cons = lx.solve_u64(A, B, p62, stream=stream)
+    timer.record_end(sptr)
+    t = timer.elapsed_ms() / reps / 1e3
+    assert int(r.item()) == n
+    out["u64_solve"] = {"value": round(metric_ops(n) / t / 1e9, 3), "unit": "GOP/s",
+                        "ms_per_solve": round(t * 1e3, 2), "reps": reps,
+                        "config": {"workload": f"one dense n={n} system, {k} right-hand sides, "
+                                               f"p=2^62-57 (uint64 residues), seed 21"}}
+    A32 = torch.from_numpy(workloads.uniform(rng, (n, n), workloads.MERSENNE31).astype(np.int32)).to(dev)
+    lx.lup(A32, workloads.MERSENNE31, stream=stream)
+    timer.record_begin(sptr)
+    for _ in range(reps):
+        LU, perm, r, piv = lx.lup(A32, workloads.MERSENNE31, stream=stream)
+    timer.record_end(sptr)
+    t = timer.elapsed_ms() / reps / 1e3
+    assert int(r.item()) == n
+    out["lup"] = {"value": round(metric_ops(n) / t / 1e9, 3), "unit": "GOP/s",
+                  "ms_per_factorisation": round(t * 1e3, 2), "reps": reps,
+                  "config": {"workload": f"LUP of one dense n={n} matrix, p=2^31-1, seed 21"}}
+    del A, B, A32
+    _free_cuda()
+    return out
+
+
+def _rref_lanes() -> int:
+    import paper_2605_25863_amd as lx
+    try:
+        return int(json.load(open(lx.TUNING_FILE)).get("rref_lanes", 4))
+    except OSError:
+        return 4
 
 
 def copy_calibration(mib: int = 1024, reps: int = 3):
@@ -615,6 +725,10 @@ def main():
         extras["c4"] = bench_batched(10, 2, not args.no_plain_compare)
         _progress("c5 sparse-pattern instances")
         extras["c5"] = bench_sparse_pattern(args.instances, 2, 1)
+        _progress("system construction")
+        extras["load_matrix"] = bench_load_matrix()
+        _progress("64-bit solve and LUP")
+        extras.update(bench_colstep())
         out["other_configs"] = extras
     if not args.no_cpu_baseline and args.config in ("c1", "c2", "c3"):
         _progress("cpu baseline")

@@ -143,6 +143,42 @@ linac_status linac_solve(const uint32_t* A, int64_t m, int64_t n, int64_t lda,
                          uint8_t* consistent, void* ws, size_t ws_bytes,
                          const linac_opts* opts, hipStream_t s);
 
+/* One matrix of a batched RREF: the linac_rref arguments, with its own prime. */
+typedef struct {
+    uint32_t* A;      /* device, m x n, reduced in place */
+    int64_t m, n, lda;
+    uint32_t p;
+    int32_t* rank;    /* device int32[1] */
+    int32_t* pivots;  /* device int32[min(m, n)] (may be NULL when min(m, n) = 0) */
+} linac_matrix;
+
+/* Workspace (bytes) for linac_rref_batched on this host array of matrices: the
+ * number of lanes (see below) times the largest single-matrix workspace. */
+linac_status linac_rref_batched_workspace(const linac_matrix* mats, int32_t count,
+                                          const linac_opts* opts, size_t* bytes);
+
+/*
+ * RREF of `count` independent matrices in one call (Sec. 2.3, Sec. 3.2 per
+ * matrix; the paper reduces one matrix per call, and its applications reduce
+ * many sample-point systems of one shape, Sec. 5.5).  Per matrix the results
+ * equal those of linac_rref.  `mats` is a HOST array read during the call only.
+ * The matrices are spread over "lanes" (tuning key rref_lanes, default 4,
+ * at most 8): each lane is an internal stream of the library with its own
+ * slice of ws, and takes its matrices one after another, largest first to the
+ * least loaded lane; one host thread per lane enqueues that lane's launches.
+ * The lanes start after the work already queued on `s` and `s` waits for all
+ * of them before its later work, so the call is ordered on `s` like any other.
+ * Concurrent lanes overlap one matrix's latency-bound pivot selections with
+ * another's matrix products.  Inside a lane the blocked path runs without its
+ * look-ahead side stream (one lane keeps it and runs on `s` itself).
+ * Calls of this function on one device are serialised by the library (they
+ * share the lanes).  opts->ev_begin / ev_end bracket the whole batch; per-launch
+ * timing is not recorded.  Errors: as linac_rref for each matrix (checked on the
+ * host before any device work); LINAC_E_WORKSPACE.
+ */
+linac_status linac_rref_batched(const linac_matrix* mats, int32_t count, void* ws, size_t ws_bytes,
+                                const linac_opts* opts, hipStream_t s);
+
 /* One system of a batch: the same meaning as the linac_solve arguments, with its
  * own prime.  Square or rectangular; all pointers are device pointers. */
 typedef struct {
@@ -177,6 +213,123 @@ linac_status linac_solve_batched_workspace(const linac_system* sys, int32_t coun
 linac_status linac_solve_batched(const linac_system* sys, int32_t count, void* ws,
                                  size_t ws_bytes, const linac_opts* opts, hipStream_t s);
 
+/*
+ * Matrix of a monomial ansatz evaluated at sampling points (Sec. 3.3, "Building
+ * linear systems on GPUs"; the bases / lindices layout of Sec. 2.3):
+ *     A[r][c] = prod_{t < d} bases[r][lindices[c][t]]  mod p.
+ *   bases     device, nrows x nbasis residues (< p), leading dimension
+ *             ldbases >= max(nbasis, 1): row r holds the basis variables at
+ *             sampling point r.
+ *   lindices  device int32, ncols x d, leading dimension ldl >= max(d, 1): row
+ *             c lists the basis variables whose product is monomial c (the
+ *             paper's kernel takes one degree d for all monomials; shorter
+ *             monomials are padded with a variable equal to 1).  An index
+ *             outside [0, nbasis) is a factor 0 (it never reads outside bases).
+ *   A         device, nrows x ncols, leading dimension lda >= max(ncols, 1).
+ * d = 0 gives A = 1 everywhere.  Entries of bases >= p give unspecified
+ * residues (no fault).  Needs no workspace.  Errors: LINAC_E_INVALID_ARG
+ * (negative size, leading dimension too small, NULL with a non-empty shape),
+ * the modulus errors of the other calls, LINAC_E_NOMEM when a size reaches
+ * 2^31, LINAC_E_HIP.
+ */
+linac_status linac_load_matrix(const uint32_t* bases, int64_t nrows, int64_t nbasis,
+                               int64_t ldbases, const int32_t* lindices, int64_t ncols, int64_t d,
+                               int64_t ldl, uint32_t p, uint32_t* A, int64_t lda, hipStream_t s);
+
+/*
+ * Canonical basis of the null space from an RREF (Sec. 5.1, "Rank
+ * factorisation and null spaces"): ker(A) = ker(R), and with the free
+ * (non-pivot) columns c_0 < c_1 < ... of R, column f of K is the solution of
+ * R x = 0 whose free variables are minus the unit vector e_f:
+ *     K[c_f][f] = p - 1,  K[pivots[s]][f] = R[s][c_f],  every other entry 0,
+ * so that A K = 0.  The basis has n - r columns, r = *rank.
+ *   R          device, m x n RREF as linac_rref returns it, leading dimension
+ *              ldr >= max(n, 1); only its first r rows are read.
+ *   rank       device int32[1] and pivots device int32[min(m, n)] as linac_rref
+ *              returns them (rank is clamped to [0, min(m, n)], so no value
+ *              makes the kernel read outside R).
+ *   K          device, n x kcols, leading dimension ldk >= max(kcols, 1), with
+ *              kcols <= n: columns f < n - r receive the basis, columns from
+ *              n - r on are set to zero.  kcols = n always holds the whole
+ *              basis (the rank is on the device, so the call never waits for
+ *              it); a smaller kcols truncates it.
+ *   free_cols  optional device int32[n]: c_f for f < n - r, then -1.
+ * Errors as for linac_rref's argument checks.
+ */
+linac_status linac_nullspace(const uint32_t* R, int64_t m, int64_t n, int64_t ldr,
+                             const int32_t* rank, const int32_t* pivots, uint32_t p, uint32_t* K,
+                             int64_t kcols, int64_t ldk, int32_t* free_cols, hipStream_t s);
+
+/*
+ * The column basis of a rank factorisation (Sec. 5.1): C = A[:, J] for the
+ * pivot columns J of A's RREF, so that A = C R with R the first r rows of the
+ * RREF.
+ *   A       device, m x n (the matrix before reduction), leading dimension
+ *           lda >= max(n, 1).
+ *   rank, pivots  device, as linac_rref returns them for A.
+ *   C       device, m x ccols, leading dimension ldc >= max(ccols, 1), with
+ *           ccols <= min(m, n): column s < r receives A's column pivots[s],
+ *           columns from r on are zero.
+ * Errors: LINAC_E_INVALID_ARG for bad sizes or NULL pointers, LINAC_E_HIP.
+ */
+linac_status linac_column_basis(const uint32_t* A, int64_t m, int64_t n, int64_t lda,
+                                const int32_t* rank, const int32_t* pivots, uint32_t* C,
+                                int64_t ccols, int64_t ldc, hipStream_t s);
+
+/*
+ * 64-bit primes (Sec. 3.2 "Number types": uint64 storage for primes beyond
+ * 32 bits).  Residues are uint64 in [0, p) with p a prime, 2 <= p < 2^63
+ * (p >= 2^63: LINAC_E_UNSUPPORTED; composite: LINAC_E_NOT_PRIME, by a
+ * deterministic Miller-Rabin test with the first twelve primes as bases).
+ * Same meaning, layouts and errors as linac_rref / linac_solve, on one
+ * column-at-a-time Gauss-Jordan path: per pivot column one search launch and
+ * one row-update launch (Sec. 3.2, Fig. 1).  opts: validate and verbose are
+ * honoured, path and panel_width ignored.  Workspaces from the matching
+ * queries.
+ */
+linac_status linac_rref_u64_workspace(int64_t m, int64_t n, size_t* bytes);
+linac_status linac_rref_u64(uint64_t* A, int64_t m, int64_t n, int64_t lda, uint64_t p,
+                            int32_t* rank, int32_t* pivots, void* ws, size_t ws_bytes,
+                            const linac_opts* opts, hipStream_t s);
+linac_status linac_solve_u64_workspace(int64_t m, int64_t n, int64_t k, size_t* bytes);
+linac_status linac_solve_u64(const uint64_t* A, int64_t m, int64_t n, int64_t lda, const uint64_t* B,
+                             int64_t k, int64_t ldb, uint64_t p, uint64_t* X, int64_t ldx,
+                             int32_t* rank, int32_t* pivots, uint8_t* consistent, void* ws,
+                             size_t ws_bytes, const linac_opts* opts, hipStream_t s);
+/* Host-only check of a 64-bit modulus: LINAC_OK for a prime below 2^63. */
+linac_status linac_check_prime_u64(uint64_t p);
+
+/*
+ * LUP factorisation P A = L U over F_p (the paper names it as future work,
+ * Sec. 6), with a fixed pivot rule so that the factors are reproducible: for
+ * each column j in turn, the pivot is the first row, in the ORIGINAL row order,
+ * that is not a pivot yet and whose current entry in column j is non-zero (a
+ * column without one is skipped).  Forward elimination only: a row that is not
+ * a pivot yet becomes row - g * (pivot row) with g = its entry / the head.
+ *   A      device, m x n, leading dimension lda >= max(n, 1), overwritten with
+ *          the packed factors in P order: row i of the output belongs to the
+ *          original row perm[i].  With r = rank and J = pivots:
+ *            L (m x m, unit lower triangular): L[i][s] = A_out[i][J[s]] for
+ *              s < min(i, r); L[i][i] = 1; every other entry 0;
+ *            U (m x n, row echelon): for i < r, U[i][c] = A_out[i][c] except
+ *              at the columns J[s], s < i, where U is 0; U[i][J[i]] is the
+ *              pivot's head (not normalised); rows i >= r of U are zero.
+ *          Then (P A)[i] = A[perm[i]] and P A = L U exactly.
+ *   perm   device int32[m]: the pivot rows in pivot order, then the other rows
+ *          in their original order.
+ *   rank, pivots  device, as for linac_rref (J = the pivot columns of the RREF).
+ * linac_lup takes 32-bit residues (p < 2^31), linac_lup_u64 64-bit ones
+ * (p < 2^63).  Workspace: linac_lup_workspace(m, n, wide = 0 or 1).  opts:
+ * validate and verbose are honoured.  Errors as for linac_rref.
+ */
+linac_status linac_lup_workspace(int64_t m, int64_t n, int wide, size_t* bytes);
+linac_status linac_lup(uint32_t* A, int64_t m, int64_t n, int64_t lda, uint32_t p, int32_t* perm,
+                       int32_t* rank, int32_t* pivots, void* ws, size_t ws_bytes,
+                       const linac_opts* opts, hipStream_t s);
+linac_status linac_lup_u64(uint64_t* A, int64_t m, int64_t n, int64_t lda, uint64_t p, int32_t* perm,
+                           int32_t* rank, int32_t* pivots, void* ws, size_t ws_bytes,
+                           const linac_opts* opts, hipStream_t s);
+
 /* Load tuned parameters for later calls (process-wide); NULL restores the
  * built-in defaults.  Tuning only selects among configurations that give the
  * same results (paths and panel widths all compute the unique RREF).  The text
@@ -188,7 +341,8 @@ linac_status linac_solve_batched(const linac_system* sys, int32_t count, void* w
  *   "batched_per_cu": resident workgroups per compute unit of the batched launch;
  *   "lookahead":      1 (default) or 0: whether the blocked int8 path overlaps the
  *                     next panel's pivot selection with the trailing update (on a
- *                     second stream that the call joins back to s).
+ *                     second stream that the call joins back to s);
+ *   "rref_lanes":     1..8, the matrices linac_rref_batched reduces concurrently.
  * Unknown keys are ignored.  Returns LINAC_E_INVALID_ARG (and keeps the current
  * table) for malformed text or out-of-range values.  Host only. */
 linac_status linac_load_tuning(const char* json);

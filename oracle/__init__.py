@@ -67,6 +67,12 @@ def _load():
         lib.oracle_powmod.restype = ctypes.c_uint64
         lib.oracle_powmod.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]
         lib.oracle_max_threads.restype = ctypes.c_int
+        lib.oracle_gauss_jordan_wide.restype = ctypes.c_int64
+        lib.oracle_gauss_jordan_wide.argtypes = [u64p, ctypes.c_int64, ctypes.c_int64,
+                                                 ctypes.c_int64, ctypes.c_uint64, i64p, ctypes.c_int]
+        lib.oracle_lup.restype = ctypes.c_int64
+        lib.oracle_lup.argtypes = [u64p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, i64p, i64p,
+                                   i64p, ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -100,6 +106,20 @@ def _gj_c(M: np.ndarray, nsearch: int, p: int, threads: int = 0, want_det: bool 
     return M, int(r), piv[: int(r)].copy(), int(det.value)
 
 
+def _gj_c_wide(M: np.ndarray, nsearch: int, p: int, threads: int = 0, want_det: bool = False):
+    """oracle/gj.c's Gauss-Jordan with 128-bit products (primes up to 2^63)."""
+    if want_det:
+        raise ValueError("the wide C oracle does not track the determinant")
+    M = np.ascontiguousarray(M, dtype=np.uint64).copy()
+    m, ncols = M.shape
+    piv = np.zeros(max(min(m, nsearch), 1), dtype=np.int64)
+    r = _load().oracle_gauss_jordan_wide(M.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), m,
+                                         ncols, nsearch, p,
+                                         piv.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                         int(threads))
+    return M, int(r), piv[: int(r)].copy(), 0
+
+
 def _choose(rows_nonzero, rule, rng):
     if rule == "first":
         return rows_nonzero[0]
@@ -111,6 +131,8 @@ def _choose(rows_nonzero, rule, rng):
 def _gj_numpy(M: np.ndarray, nsearch: int, p: int, pivot_rule: str = "first", seed: int = 0,
               want_det: bool = False):
     """int64 Gauss-Jordan: the row update is vectorised, nothing else."""
+    if p >= 1 << 31:
+        raise ValueError("the numpy oracle needs p < 2^31 (products must fit int64)")
     M = np.array(M, dtype=np.int64)
     m, ncols = M.shape
     rng = np.random.default_rng(seed)
@@ -178,7 +200,7 @@ def _gj_python(M, nsearch: int, p: int, pivot_rule: str = "first", seed: int = 0
     return arr, i, np.array(piv, dtype=np.int64), (0 if singular else det)
 
 
-_IMPLS = {"c": _gj_c, "numpy": _gj_numpy, "python": _gj_python}
+_IMPLS = {"c": _gj_c, "c_wide": _gj_c_wide, "numpy": _gj_numpy, "python": _gj_python}
 
 
 def gauss_jordan(M, nsearch: int, p: int, impl: str = "c", **kw):
@@ -192,17 +214,25 @@ def gauss_jordan(M, nsearch: int, p: int, impl: str = "c", **kw):
         raise ValueError("matrix must be 2-D")
     if M.size and int(M.max()) >= p:
         raise ValueError("entries must be canonical residues in [0, p)")
-    if impl == "c":
+    if impl == "c" and p >= 1 << 32:
+        impl = "c_wide"  # products of residues above 2^32 need 128 bits
+    if impl in ("c", "c_wide"):
         kw.pop("pivot_rule", None)
         kw.pop("seed", None)
     return _IMPLS[impl](M, nsearch, int(p), **kw)
 
 
+def _word(p: int):
+    """Storage of residues: uint32 below 2^32, uint64 above (Sec. 3.2)."""
+    return np.uint32 if p < 1 << 32 else np.uint64
+
+
 def rref(A, p: int, impl: str = "c", **kw):
-    """(R, rank, pivots): R in A's shape (uint32), zero rows at the bottom."""
+    """(R, rank, pivots): R in A's shape (uint32, or uint64 for p >= 2^32),
+    zero rows at the bottom."""
     A = np.asarray(A)
     R, r, piv, _ = gauss_jordan(A, A.shape[1], p, impl, **kw)
-    return R.astype(np.uint32), r, piv
+    return R.astype(_word(p)), r, piv
 
 
 def solve(A, B, p: int, impl: str = "c", **kw):
@@ -225,7 +255,7 @@ def solve(A, B, p: int, impl: str = "c", **kw):
     for s, c in enumerate(piv):
         X[c, :] = R[s, n:]
     X[:, consistent == 0] = 0
-    return X.astype(np.uint32), r, piv, consistent
+    return X.astype(_word(p)), r, piv, consistent
 
 
 def det(A, p: int, impl: str = "c", **kw) -> int:
@@ -329,3 +359,148 @@ def matmul_mod(A, B, p: int) -> np.ndarray:
         out = (out + (a @ lo[k0:k0 + step]) % p) % p
         out = (out + ((a @ hi[k0:k0 + step]) % p) * (1 << 16) % p) % p
     return out.astype(np.uint64)
+
+
+def rank_factor_columns(A, pivots):
+    """C = A[:, J]: the columns of A at the pivot columns J of its RREF, so that
+    A = C R with R the non-zero rows of the RREF (Sec. 5.1)."""
+    A = np.asarray(A)
+    return A[:, np.asarray(pivots, dtype=np.int64)].copy()
+
+
+# ---------------------------------------------------------------------------
+# Construction of a linear system from monomials (Sec. 3.3)
+# ---------------------------------------------------------------------------
+
+def load_matrix(bases, lindices, p: int, impl: str = "numpy"):
+    """A[r, c] = prod_t bases[r, lindices[c, t]] mod p (Sec. 3.3, the matrix
+    of a monomial ansatz evaluated at sampling points; Sec. 2.3 for the
+    bases / lindices layout).
+
+    bases: (nrows, nbasis) residues, one row per sampling point; lindices:
+    (ncols, d) integer indices into a row of bases, one row per monomial.
+    The empty product (d = 0) is 1.  An index outside [0, nbasis) is not
+    defined by the paper; it is read here as a factor 0.
+
+    ``numpy``: a running product reduced after every factor (int64; the
+    product of two residues below 2^31 is below 2^62).  ``python``: Python
+    ints, the product taken whole and reduced once (tiny sizes).
+    """
+    B = np.asarray(bases)
+    L = np.asarray(lindices)
+    if B.ndim != 2 or L.ndim != 2:
+        raise ValueError("bases and lindices must be 2-D")
+    if B.size and int(B.max()) >= p:
+        raise ValueError("bases must be canonical residues in [0, p)")
+    nrows, nb = B.shape
+    ncols, d = L.shape
+    if impl == "python":
+        Bl = [[int(x) for x in row] for row in B.tolist()]
+        Ll = [[int(x) for x in row] for row in L.tolist()]
+        out = np.zeros((nrows, ncols), dtype=np.uint32)
+        for r in range(nrows):
+            for c in range(ncols):
+                prod = 1
+                for t in range(d):
+                    i = Ll[c][t]
+                    prod *= Bl[r][i] if 0 <= i < nb else 0
+                out[r, c] = prod % p
+        return out
+    B = B.astype(np.int64)
+    L = L.astype(np.int64)
+    A = np.full((nrows, ncols), 1 % p, dtype=np.int64)
+    for t in range(d):
+        idx = L[:, t]
+        ok = (idx >= 0) & (idx < nb)
+        F = np.zeros((nrows, ncols), dtype=np.int64)
+        F[:, ok] = B[:, idx[ok]]
+        A = A * F % p
+    return A.astype(np.uint32)
+
+
+
+# ---------------------------------------------------------------------------
+# LUP factorisation (the paper's future work, Sec. 6)
+# ---------------------------------------------------------------------------
+
+def lup(A, p: int, impl: str = "c"):
+    """P A = L U over F_p by forward elimination with a fixed pivot rule.
+
+    For each column j in turn the pivot is the first row, in the original row
+    order, that is not a pivot yet and has a non-zero entry in column j;
+    every other non-pivot row q takes g = A[q][j] / head, is replaced by
+    row_q - g * (pivot row), and keeps g in column j.  Returns (LU, perm,
+    rank, pivots): perm lists the pivot rows in pivot order, then the other
+    rows in their original order, and LU = the worked matrix in that row
+    order (L's entries at the pivot columns left of each row's own pivot,
+    U's entries elsewhere; see ``lup_factors``).
+
+    ``c``: oracle/gj.c (128-bit products); ``python``: Python ints.
+    """
+    A = np.asarray(A)
+    m, n = A.shape
+    if A.size and int(A.max()) >= p:
+        raise ValueError("entries must be canonical residues in [0, p)")
+    if impl == "c":
+        M = np.ascontiguousarray(A, dtype=np.uint64).copy()
+        step = np.zeros(max(m, 1), dtype=np.int64)
+        prow = np.zeros(max(min(m, n), 1), dtype=np.int64)
+        pcol = np.zeros(max(min(m, n), 1), dtype=np.int64)
+        P64 = ctypes.POINTER(ctypes.c_int64)
+        r = int(_load().oracle_lup(M.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), m, n, p,
+                                   step.ctypes.data_as(P64), prow.ctypes.data_as(P64),
+                                   pcol.ctypes.data_as(P64), 0))
+        is_piv = step[:m] >= 0
+        pivrows, pivots = prow[:r].tolist(), pcol[:r].copy()
+        W = M
+    else:
+        W = [[int(x) for x in row] for row in A.tolist()]
+        is_piv = [False] * m
+        pivrows, piv_list = [], []
+        for j in range(n):
+            cand = [q for q in range(m) if not is_piv[q] and W[q][j] % p]
+            if not cand:
+                continue
+            r0 = cand[0]
+            inv = pow(W[r0][j], p - 2, p)
+            for q in range(m):
+                if q == r0 or is_piv[q] or W[q][j] == 0:
+                    continue
+                g = W[q][j] * inv % p
+                W[q][j] = g
+                for c in range(j + 1, n):
+                    W[q][c] = (W[q][c] - g * W[r0][c]) % p
+            is_piv[r0] = True
+            pivrows.append(r0)
+            piv_list.append(j)
+        W = np.array(W, dtype=np.uint64).reshape(m, n)
+        is_piv = np.array(is_piv, dtype=bool)
+        pivots = np.array(piv_list, dtype=np.int64)
+        r = len(pivrows)
+    perm = np.array(list(pivrows) + [q for q in range(m) if not is_piv[q]], dtype=np.int64)
+    LU = W[perm] if m else W
+    return LU.astype(np.uint64), perm, int(r), np.asarray(pivots, dtype=np.int64)
+
+
+def lup_factors(LU, perm, rank: int, pivots, p: int):
+    """(Pmat, L, U) as dense uint64 arrays from the packed LUP output: Pmat is
+    the m x m permutation with (Pmat A)[i] = A[perm[i]], L is unit lower
+    triangular (m x m) with L[i][s] = LU[i][pivots[s]] for s < min(i, rank),
+    and U (m x n) is LU with the L entries cleared and rows from the rank on
+    zero."""
+    LU = np.asarray(LU, dtype=np.uint64)
+    m, n = LU.shape
+    Pm = np.zeros((m, m), dtype=np.uint64)
+    for i, q in enumerate(perm):
+        Pm[i, int(q)] = 1
+    L = np.eye(m, dtype=np.uint64)
+    U = np.zeros((m, n), dtype=np.uint64)
+    J = [int(c) for c in pivots]
+    for i in range(m):
+        for s in range(min(i, rank)):
+            L[i, s] = LU[i, J[s]]
+        if i < rank:
+            U[i] = LU[i]
+            for s in range(i):
+                U[i, J[s]] = 0
+    return Pm, L, U

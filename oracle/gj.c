@@ -146,3 +146,103 @@ int oracle_max_threads(void)
     return 1;
 #endif
 }
+
+/*
+ * The same Gauss-Jordan for primes up to 2^63 (Sec. 3.2 "Number types": uint64
+ * storage for primes beyond 32 bits): identical steps, with every product of
+ * two residues formed in 128 bits before `%`.  The inverse is the extended
+ * Euclidean algorithm of oracle_inv (its signed 64-bit values stay below p).
+ */
+static uint64_t mulmod_wide(uint64_t a, uint64_t b, uint64_t p)
+{
+    return (uint64_t)((unsigned __int128)a * b % p);
+}
+
+int64_t oracle_gauss_jordan_wide(uint64_t *M, int64_t m, int64_t ncols, int64_t nsearch,
+                                 uint64_t p, int64_t *pivcols, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    int64_t i = 0;
+    for (int64_t j = 0; j < nsearch && i < m; ++j) {
+        int64_t r = -1;
+        for (int64_t q = i; q < m; ++q)
+            if (M[q * ncols + j] != 0) { r = q; break; }
+        if (r < 0) continue;
+        if (r != i) {
+            for (int64_t c = 0; c < ncols; ++c) {
+                uint64_t t = M[i * ncols + c];
+                M[i * ncols + c] = M[r * ncols + c];
+                M[r * ncols + c] = t;
+            }
+        }
+        uint64_t *pr = M + i * ncols;
+        uint64_t inv = oracle_inv(pr[j], p);
+        for (int64_t c = j; c < ncols; ++c) pr[c] = mulmod_wide(pr[c], inv, p);
+#pragma omp parallel for schedule(static)
+        for (int64_t q = 0; q < m; ++q) {
+            if (q == i) continue;
+            uint64_t *row = M + q * ncols;
+            uint64_t f = row[j];
+            if (f == 0) continue;
+            for (int64_t c = j; c < ncols; ++c) {
+                uint64_t t = mulmod_wide(f, pr[c], p);
+                row[c] = row[c] >= t ? row[c] - t : row[c] + (p - t);
+            }
+        }
+        pivcols[i] = j;
+        ++i;
+    }
+    return i;
+}
+
+/*
+ * LUP factorisation with the first-non-zero pivot rule in the original row
+ * order (the paper names LU factorisation as future work, Sec. 6).  Rows are
+ * never swapped in M: for each column j, the pivot is the smallest row index q
+ * not yet a pivot with M[q][j] != 0; every other non-pivot row q gets the
+ * multiplier g = M[q][j] / M[piv][j], which replaces M[q][j], and
+ * M[q][c] -= g * M[piv][c] for c > j.  The pivot row is left as it is.
+ * is_piv_step[q] receives the step at which row q became a pivot, or -1;
+ * pivrows[s] / pivcols[s] the s-th pivot row and column.  Returns the rank.
+ * Products are formed in 128 bits, so p may be any prime below 2^63.
+ */
+int64_t oracle_lup(uint64_t *M, int64_t m, int64_t n, uint64_t p, int64_t *is_piv_step,
+                   int64_t *pivrows, int64_t *pivcols, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    for (int64_t q = 0; q < m; ++q) is_piv_step[q] = -1;
+    int64_t rank = 0;
+    for (int64_t j = 0; j < n && rank < m; ++j) {
+        int64_t piv = -1;
+        for (int64_t q = 0; q < m; ++q)
+            if (is_piv_step[q] < 0 && M[q * n + j] != 0) { piv = q; break; }
+        if (piv < 0) continue;
+        const uint64_t *u = M + piv * n;
+        uint64_t inv = oracle_inv(u[j], p);
+#pragma omp parallel for schedule(static)
+        for (int64_t q = 0; q < m; ++q) {
+            if (q == piv || is_piv_step[q] >= 0) continue;
+            uint64_t *row = M + q * n;
+            if (row[j] == 0) continue;
+            uint64_t g = mulmod_wide(row[j], inv, p);
+            row[j] = g;
+            for (int64_t c = j + 1; c < n; ++c) {
+                uint64_t t = mulmod_wide(g, u[c], p);
+                row[c] = row[c] >= t ? row[c] - t : row[c] + (p - t);
+            }
+        }
+        is_piv_step[piv] = rank;
+        pivrows[rank] = piv;
+        pivcols[rank] = j;
+        ++rank;
+    }
+    return rank;
+}

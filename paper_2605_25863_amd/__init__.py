@@ -13,6 +13,16 @@ User-level calls follow the paper (Sec. 2.3 "Basic Usage", Sec. 5.1-5.2):
 * ``solve(A, B, p)`` -- (X, rank, pivots, consistent): the particular
   solution of A X = B with free variables zero;
 * ``solve_batched(systems)`` -- many independent systems in one launch;
+* ``rref_batched(matrices, p)`` -- the RREF of many matrices in one call,
+  reduced concurrently on the library's stream lanes;
+* ``load_matrix(bases, lindices, p)`` -- the matrix of a monomial ansatz at
+  sampling points (``cuda_load_matrix``, Sec. 3.3);
+* ``canonical_kernel(R, rank, pivots, p)``, ``column_basis`` and
+  ``rank_factorization(A, p)`` -- the null-space basis and the rank
+  factorisation A = C R read off the RREF (Sec. 5.1);
+* ``rref_u64`` / ``solve_u64`` -- the same for 64-bit primes below 2^63
+  (uint64 residues, Sec. 3.2 "Number types"), and ``lup(A, p)`` -- the LUP
+  factorisation P A = L U with a fixed pivot rule (future work of Sec. 6);
 * ``drop_bottom_zero_rows`` and ``pivot_columns_from_row_reduced_echelon_form``
   -- the helpers of Sec. 2.3 and Sec. 5.1.
 
@@ -33,7 +43,9 @@ __all__ = [
     "LinacError", "library_path", "row_reduce", "rref", "solve", "solve_batched",
     "drop_bottom_zero_rows", "pivot_columns_from_row_reduced_echelon_form", "HipTimer",
     "PATH_AUTO", "PATH_PLAIN", "PATH_BLOCKED_INT8", "PATH_BLOCKED_FP64", "check_prime",
-    "load_tuning", "TUNING_FILE", "LaunchTimes", "rref_workspace_bytes",
+    "load_tuning", "TUNING_FILE", "LaunchTimes", "rref_workspace_bytes", "load_matrix",
+    "canonical_kernel", "column_basis", "rank_factorization", "rref_batched", "rref_u64",
+    "solve_u64", "lup",
 ]
 
 PATH_AUTO, PATH_PLAIN, PATH_BLOCKED_INT8, PATH_BLOCKED_FP64 = 0, 1, 2, 3
@@ -69,6 +81,12 @@ KERNEL_KINDS = {1: "step", 2: "leaf_product", 3: "trail_product", 4: "batched", 
                 6: "operands"}
 
 
+class _Matrix(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("lda", ctypes.c_int64), ("p", ctypes.c_uint32), ("rank", ctypes.c_void_p),
+                ("pivots", ctypes.c_void_p)]
+
+
 class _System(ctypes.Structure):
     _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("X", ctypes.c_void_p),
                 ("m", ctypes.c_int32), ("n", ctypes.c_int32), ("k", ctypes.c_int32),
@@ -101,13 +119,33 @@ def _load():
     lib.linac_solve_batched_workspace.argtypes = [ctypes.POINTER(_System), ctypes.c_int32, optp,
                                                   szp]
     lib.linac_solve_batched.argtypes = [ctypes.POINTER(_System), ctypes.c_int32, vp, sz, optp, vp]
+    lib.linac_rref_batched_workspace.argtypes = [ctypes.POINTER(_Matrix), ctypes.c_int32, optp, szp]
+    lib.linac_rref_batched.argtypes = [ctypes.POINTER(_Matrix), ctypes.c_int32, vp, sz, optp, vp]
+    u64 = ctypes.c_uint64
+    lib.linac_rref_u64_workspace.argtypes = [i64, i64, szp]
+    lib.linac_rref_u64.argtypes = [vp, i64, i64, i64, u64, vp, vp, vp, sz, optp, vp]
+    lib.linac_solve_u64_workspace.argtypes = [i64, i64, i64, szp]
+    lib.linac_solve_u64.argtypes = [vp, i64, i64, i64, vp, i64, i64, u64, vp, i64, vp, vp, vp, vp,
+                                    sz, optp, vp]
+    lib.linac_lup_workspace.argtypes = [i64, i64, ctypes.c_int, szp]
+    lib.linac_lup.argtypes = [vp, i64, i64, i64, u32, vp, vp, vp, vp, sz, optp, vp]
+    lib.linac_lup_u64.argtypes = [vp, i64, i64, i64, u64, vp, vp, vp, vp, sz, optp, vp]
+    lib.linac_check_prime_u64.argtypes = [u64]
+    lib.linac_load_matrix.argtypes = [vp, i64, i64, i64, vp, i64, i64, i64, u32, vp, i64, vp]
+    lib.linac_nullspace.argtypes = [vp, i64, i64, i64, vp, vp, u32, vp, i64, i64, vp, vp]
+    lib.linac_column_basis.argtypes = [vp, i64, i64, i64, vp, vp, vp, i64, i64, vp]
     lib.linac_load_tuning.argtypes = [ctypes.c_char_p]
     lib.linac_check_prime.argtypes = [u32]
     lib.linac_status_string.restype = ctypes.c_char_p
     lib.linac_status_string.argtypes = [ctypes.c_int]
     for name in ("linac_plan", "linac_rref_workspace", "linac_rref", "linac_solve_workspace", "linac_solve",
                  "linac_solve_batched_workspace", "linac_solve_batched", "linac_load_tuning",
-                 "linac_check_prime", "linac_version", "linac_last_hip_error"):
+                 "linac_check_prime", "linac_version", "linac_last_hip_error",
+                 "linac_load_matrix", "linac_nullspace", "linac_column_basis",
+                 "linac_rref_batched_workspace", "linac_rref_batched",
+                 "linac_rref_u64_workspace", "linac_rref_u64", "linac_solve_u64_workspace",
+                 "linac_solve_u64", "linac_lup_workspace", "linac_lup", "linac_lup_u64",
+                 "linac_check_prime_u64"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     if os.path.exists(TUNING_FILE):
@@ -409,6 +447,70 @@ def solve_batched(systems, *, path: int = PATH_AUTO, verbose: bool = False, stre
     return out
 
 
+def rref_batched(matrices, p, *, inplace: bool = False, path: int = PATH_AUTO,
+                 panel_width: int = 0, validate: bool = False, verbose: bool = False,
+                 stream=None, events: HipTimer | None = None, workspace=None, outs=None):
+    """RREF of every matrix in ``matrices`` (numpy arrays or int32 CUDA
+    tensors) in one linac_rref_batched call; ``p`` is one prime or one per
+    matrix.  Returns a list of (R, rank, pivots) device tensors like ``rref``
+    (numpy in -> numpy R and int rank / pivots out).  With ``inplace`` device
+    inputs are overwritten; ``workspace`` may be a preallocated uint8 tensor
+    and ``outs`` preallocated (rank, pivots) pairs."""
+    torch = _torch()
+    lib = _load()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    count = len(matrices)
+    ps = list(p) if isinstance(p, (list, tuple)) else [int(p)] * count
+    desc = (_Matrix * max(count, 1))()
+    items = []
+    any_np = False
+    for i, M in enumerate(matrices):
+        At, was_np = _to_dev(torch, M, dev)
+        any_np |= was_np
+        if not inplace and not was_np:
+            At = At.clone()
+        m, n = At.shape
+        if outs is not None:
+            rank, piv = outs[i]
+        else:
+            rank = torch.zeros(1, dtype=torch.int32, device=dev)
+            piv = torch.empty(min(m, n), dtype=torch.int32, device=dev)
+        items.append((At, rank, piv))
+        d = desc[i]
+        d.A, d.m, d.n, d.lda, d.p = _ptr(At), m, n, max(n, 1), int(ps[i])
+        d.rank, d.pivots = _ptr(rank), _ptr(piv)
+    o = _opts(path, panel_width, validate, verbose, events)
+    if workspace is None:
+        need = ctypes.c_size_t()
+        _check(lib.linac_rref_batched_workspace(desc, count, ctypes.byref(o), ctypes.byref(need)),
+               "rref_batched_workspace")
+        workspace = _workspace(torch, need.value, dev)
+    _check(lib.linac_rref_batched(desc, count, _ptr(workspace), workspace.numel(), ctypes.byref(o),
+                                  _stream(torch, stream)), "linac_rref_batched")
+    if any_np:
+        torch.cuda.synchronize()
+        out = []
+        for (At, rank, piv), M in zip(items, matrices):
+            r = int(rank.item())
+            out.append((At.cpu().numpy().astype(np.uint32), r,
+                        piv.cpu().numpy()[:r].astype(np.int64)))
+        return out
+    return items
+
+
+def rref_batched_workspace_bytes(shapes, path: int = PATH_AUTO, panel_width: int = 0) -> int:
+    """Workspace of linac_rref_batched for matrices of these (m, n) shapes."""
+    lib = _load()
+    desc = (_Matrix * max(len(shapes), 1))()
+    for i, (m, n) in enumerate(shapes):
+        desc[i].m, desc[i].n, desc[i].lda = m, n, max(n, 1)
+    o = _opts(path, panel_width)
+    need = ctypes.c_size_t()
+    _check(lib.linac_rref_batched_workspace(desc, len(shapes), ctypes.byref(o), ctypes.byref(need)),
+           "rref_batched_workspace")
+    return int(need.value)
+
+
 def prepare_batched(systems, path: int = PATH_AUTO):
     """Device copies, output buffers, descriptors and workspace for a batch."""
     torch = _torch()
@@ -456,3 +558,194 @@ def pivot_columns_from_row_reduced_echelon_form(R):
         if len(nz):
             out.append(int(nz[0]))
     return out
+
+
+def _to_dev_index(torch, L, device):
+    if isinstance(L, np.ndarray):
+        arr = np.ascontiguousarray(L)
+        if arr.size and (int(arr.max()) >= (1 << 31) or int(arr.min()) < -(1 << 31)):
+            raise ValueError("indices must fit int32")
+        return torch.from_numpy(arr.astype(np.int32)).to(device), True
+    if not L.is_cuda or L.dtype != torch.int32:
+        raise ValueError("torch lindices must be an int32 CUDA tensor")
+    return L.contiguous(), False
+
+
+def load_matrix(bases, lindices, p: int, *, stream=None, out=None):
+    """A[r, c] = prod_t bases[r, lindices[c, t]] mod p (the paper's
+    cuda_load_matrix, Sec. 3.3): one row per sampling point, one column per
+    monomial.  numpy in -> numpy out; torch int32 CUDA tensors -> device
+    tensor.  ``out`` may supply the nrows x ncols int32 result tensor."""
+    torch = _torch()
+    lib = _load()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    Bt, was_np = _to_dev(torch, bases, dev)
+    Lt, _ = _to_dev_index(torch, lindices, dev)
+    nrows, nb = Bt.shape
+    ncols, d = Lt.shape
+    A = out if out is not None else torch.empty((nrows, ncols), dtype=torch.int32, device=dev)
+    _check(lib.linac_load_matrix(_ptr(Bt), nrows, nb, max(nb, 1), _ptr(Lt), ncols, d, max(d, 1),
+                                 int(p), _ptr(A), max(ncols, 1), _stream(torch, stream)),
+           "linac_load_matrix")
+    if was_np:
+        torch.cuda.synchronize()
+        return A.cpu().numpy().astype(np.uint32)
+    return A
+
+
+def canonical_kernel(R, rank, pivots, p: int, *, kcols=None, stream=None, with_free=False):
+    """Null-space basis K (n x kcols device tensor, kcols = n by default) of the
+    RREF R (device int32, as ``rref`` returns it, with its device rank and
+    pivots): columns f < n - r hold the canonical basis (free variables -I),
+    later columns are zero (linac_nullspace, Sec. 5.1).  With ``with_free``
+    also returns the free columns (int32[n], -1 padded)."""
+    torch = _torch()
+    lib = _load()
+    m, n = R.shape
+    kc = n if kcols is None else int(kcols)
+    K = torch.empty((n, kc), dtype=torch.int32, device=R.device)
+    free = torch.empty(max(n, 1), dtype=torch.int32, device=R.device) if with_free else None
+    _check(lib.linac_nullspace(_ptr(R), m, n, max(n, 1), _ptr(rank), _ptr(pivots), int(p), _ptr(K),
+                               kc, max(kc, 1), _ptr(free), _stream(torch, stream)),
+           "linac_nullspace")
+    return (K, free) if with_free else K
+
+
+def column_basis(A, rank, pivots, *, ccols=None, stream=None):
+    """C = A[:, J] (m x ccols device tensor, ccols = min(m, n) by default,
+    columns from the rank on zero) for the pivot columns J of A's RREF
+    (linac_column_basis, Sec. 5.1)."""
+    torch = _torch()
+    lib = _load()
+    m, n = A.shape
+    cc = min(m, n) if ccols is None else int(ccols)
+    C = torch.empty((m, cc), dtype=torch.int32, device=A.device)
+    _check(lib.linac_column_basis(_ptr(A), m, n, max(n, 1), _ptr(rank), _ptr(pivots), _ptr(C), cc,
+                                  max(cc, 1), _stream(torch, stream)), "linac_column_basis")
+    return C
+
+
+def rank_factorization(A, p: int, **kw):
+    """(C, R, K, rank): A = C R with C = A[:, J] (m x r) and R the r non-zero
+    rows of the RREF (r x n), and K (n x (n - r)) with A K = 0 (Sec. 5.1).
+    numpy in -> numpy out; a torch int32 CUDA tensor -> device tensors (the
+    rank is read back once to trim the shapes)."""
+    torch = _torch()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    At, was_np = _to_dev(torch, A, dev)
+    R, rank, piv = rref(At, p, **kw)
+    C = column_basis(At, rank, piv)
+    K = canonical_kernel(R, rank, piv, p)
+    r = int(rank.item())
+    n = At.shape[1]
+    C, R, K = C[:, :r], R[:r], K[:, : n - r]
+    if was_np:
+        return (C.cpu().numpy().astype(np.uint32), R.cpu().numpy().astype(np.uint32),
+                K.cpu().numpy().astype(np.uint32), r)
+    return C, R, K, r
+
+
+
+def _to_dev64(torch, M, device):
+    """(int64 tensor on device, was_numpy): 64-bit residues below 2^63 have the
+    same bits as int64."""
+    if isinstance(M, np.ndarray):
+        arr = np.ascontiguousarray(M)
+        if arr.size and int(arr.max()) >= (1 << 63):
+            raise ValueError("entries must be residues below 2^63")
+        return torch.from_numpy(arr.astype(np.uint64).view(np.int64)).to(device), True
+    if not M.is_cuda or M.dtype != torch.int64:
+        raise ValueError("torch inputs of the 64-bit calls must be int64 CUDA tensors")
+    return M.contiguous(), False
+
+
+def _u64_out(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def rref_u64(A, p: int, *, inplace: bool = False, validate: bool = False, stream=None):
+    """RREF over F_p for a prime p < 2^63 (linac_rref_u64).  numpy uint64 in ->
+    (R uint64, rank, pivots) numpy out; int64 CUDA tensors -> device tensors."""
+    torch = _torch()
+    lib = _load()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    At, was_np = _to_dev64(torch, A, dev)
+    if not inplace and not was_np:
+        At = At.clone()
+    m, n = At.shape
+    rank = torch.zeros(1, dtype=torch.int32, device=dev)
+    piv = torch.empty(min(m, n), dtype=torch.int32, device=dev)
+    need = ctypes.c_size_t()
+    _check(lib.linac_rref_u64_workspace(m, n, ctypes.byref(need)), "rref_u64_workspace")
+    ws = _workspace(torch, need.value, dev)
+    o = _opts(validate=validate)
+    _check(lib.linac_rref_u64(_ptr(At), m, n, max(n, 1), int(p), _ptr(rank), _ptr(piv), _ptr(ws),
+                              ws.numel(), ctypes.byref(o), _stream(torch, stream)), "linac_rref_u64")
+    if was_np:
+        torch.cuda.synchronize()
+        r = int(rank.item())
+        return _u64_out(At), r, piv.cpu().numpy()[:r].astype(np.int64)
+    return At, rank, piv
+
+
+def solve_u64(A, B, p: int, *, validate: bool = False, stream=None):
+    """Solve A X = B over F_p for a prime p < 2^63 (linac_solve_u64).  numpy
+    in -> (X uint64, rank, pivots, consistent) numpy out."""
+    torch = _torch()
+    lib = _load()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    At, was_np = _to_dev64(torch, A, dev)
+    Bt, _ = _to_dev64(torch, B, dev)
+    m, n = At.shape
+    k = Bt.shape[1]
+    X = torch.empty((n, k), dtype=torch.int64, device=dev)
+    rank = torch.zeros(1, dtype=torch.int32, device=dev)
+    piv = torch.empty(min(m, n), dtype=torch.int32, device=dev)
+    cons = torch.empty(k, dtype=torch.uint8, device=dev)
+    need = ctypes.c_size_t()
+    _check(lib.linac_solve_u64_workspace(m, n, k, ctypes.byref(need)), "solve_u64_workspace")
+    ws = _workspace(torch, need.value, dev)
+    o = _opts(validate=validate)
+    _check(lib.linac_solve_u64(_ptr(At), m, n, max(n, 1), _ptr(Bt), k, max(k, 1), int(p), _ptr(X),
+                               max(k, 1), _ptr(rank), _ptr(piv), _ptr(cons), _ptr(ws), ws.numel(),
+                               ctypes.byref(o), _stream(torch, stream)), "linac_solve_u64")
+    if was_np:
+        torch.cuda.synchronize()
+        r = int(rank.item())
+        return (_u64_out(X), r, piv.cpu().numpy()[:r].astype(np.int64),
+                cons.cpu().numpy().astype(np.uint8))
+    return X, rank, piv, cons
+
+
+def lup(A, p: int, *, wide: bool | None = None, inplace: bool = False, validate: bool = False,
+        stream=None):
+    """P A = L U (linac_lup / linac_lup_u64): returns (LU, perm, rank, pivots)
+    with LU the packed factors in P order (see include/linac.h).  ``wide``
+    selects the 64-bit call (default: when p >= 2^31 or the input is uint64 /
+    int64).  numpy in -> numpy out (LU uint32 or uint64)."""
+    torch = _torch()
+    lib = _load()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if wide is None:
+        wide = p >= (1 << 31) or (isinstance(A, np.ndarray) and A.dtype in (np.uint64, np.int64)) \
+            or (not isinstance(A, np.ndarray) and A.dtype == torch.int64)
+    At, was_np = (_to_dev64 if wide else _to_dev)(torch, A, dev)
+    if not inplace and not was_np:
+        At = At.clone()
+    m, n = At.shape
+    perm = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    rank = torch.zeros(1, dtype=torch.int32, device=dev)
+    piv = torch.empty(min(m, n), dtype=torch.int32, device=dev)
+    need = ctypes.c_size_t()
+    _check(lib.linac_lup_workspace(m, n, int(wide), ctypes.byref(need)), "lup_workspace")
+    ws = _workspace(torch, need.value, dev)
+    o = _opts(validate=validate)
+    fn = lib.linac_lup_u64 if wide else lib.linac_lup
+    _check(fn(_ptr(At), m, n, max(n, 1), int(p), _ptr(perm), _ptr(rank), _ptr(piv), _ptr(ws),
+              ws.numel(), ctypes.byref(o), _stream(torch, stream)), "linac_lup")
+    if was_np:
+        torch.cuda.synchronize()
+        r = int(rank.item())
+        LU = _u64_out(At) if wide else At.cpu().numpy().astype(np.uint32)
+        return LU, perm.cpu().numpy()[:m].astype(np.int64), r, piv.cpu().numpy()[:r].astype(np.int64)
+    return At, perm, rank, piv

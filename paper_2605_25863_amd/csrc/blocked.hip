@@ -59,6 +59,15 @@ __device__ __forceinline__ void digits4(int32_t x, int8_t d[4]) {
     }
 }
 
+// Forward elimination (the solve): a row that became a pivot in an earlier
+// panel (its pivot column below skip_below, the panel start) takes no part in
+// a panel -- not in the leaf products, not in the trailing product, not in the
+// write-back -- so it keeps its entries right of its own panel (the U part
+// that back-substitution reads).  skip_below = 0 is Gauss-Jordan.
+__device__ __forceinline__ bool earlier_pivot(int32_t rowcol, int32_t skip_below) {
+    return rowcol >= 0 && rowcol < skip_below;
+}
+
 // A row-major matrix view (device pointer and leading dimension).
 struct Mat {
     uint32_t* M;
@@ -228,12 +237,18 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
                                                               int64_t N, const int8_t* Afrag,
                                                               const int8_t* Bfrag, int32_t KB,
                                                               int32_t fresh_lo, int32_t fresh_hi,
-                                                              double c32) {
+                                                              double c32, int32_t skip_below) {
     __shared__ v4i sB[2][4 * 64];  // 2 x 4 KB
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t mtiles = ceil_div(w.m, 128);
     const int64_t ntiles = mtiles * ceil_div(N, 32);
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        if (skip_below > 0) {  // forward elimination: a tile of earlier pivot rows only is skipped
+            const int64_t row = (tile % mtiles) * 128 + (threadIdx.x >> 1);
+            int keep = 0;
+            if ((threadIdx.x & 1) == 0 && row < w.m) keep = !earlier_pivot(w.rowcol[row], skip_below);
+            if (__syncthreads_or(keep) == 0) continue;
+        }
         const int64_t rb = (tile % mtiles) * 4 + wave;
         const int64_t cb = tile / mtiles;
         const int8_t* bsrc = Bfrag + (cb * KB * 4 + wave) * 1024 + lane * 16;  // wave v moves plane v
@@ -284,7 +299,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
         if (col < N) {
             for (int r = 0; r < 16; ++r) {
                 const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                if (row >= w.m) continue;
+                if (row >= w.m || earlier_pivot(rcv[r], skip_below)) continue;
                 const bool fresh = rcv[r] >= fresh_lo && rcv[r] < fresh_hi;  // a pivot row of this panel
                 dst.M[row * dst.ld + col0 + col] = fold7(acc, r, fresh ? 0u : cur[r], c32, w.F);
             }
@@ -315,7 +330,8 @@ constexpr int kLeafBlocks = 2;  // 16-column blocks per workgroup
 __global__ __launch_bounds__(kThreads, 4) void leaf_product_i8_kernel(
     PlainArgs w, Mat pr, int32_t l0, int32_t wl, int32_t wj, int32_t gcol0, int64_t N,
     const LeafOut* out, const uint32_t* rsave, int64_t ldr, double c32, const int32_t* cand,
-    int32_t* cand_next, const int32_t* count, int32_t* count_next, const int8_t* yfrag) {
+    int32_t* cand_next, const int32_t* count, int32_t* count_next, const int8_t* yfrag,
+    int32_t skip_below) {
     __shared__ uint32_t sP[32][33];
     __shared__ uint32_t sR[32][17];
     __shared__ __attribute__((aligned(16))) int8_t sB[4][64][8];
@@ -330,6 +346,12 @@ __global__ __launch_bounds__(kThreads, 4) void leaf_product_i8_kernel(
         const int E = *count;
         if (i == 0) *count_next = E - t;
         leaf_compact_entry(out, t, cand, cand_next, E, i);
+    }
+    if (skip_below > 0) {  // forward elimination: 64 earlier pivot rows need nothing
+        const int64_t row = (int64_t)blockIdx.x * 64 + tid;
+        int keep = 0;
+        if (tid < 64 && row < w.m) keep = !earlier_pivot(w.rowcol[row], skip_below);
+        if (__syncthreads_or(keep) == 0) return;
     }
     // All loads below use addresses clamped into their arrays and are issued
     // unconditionally (values out of range are discarded afterwards), so they
@@ -459,7 +481,7 @@ __global__ __launch_bounds__(kThreads, 4) void leaf_product_i8_kernel(
         if (col < N && !pivcol) {
             for (int r = 0; r < 4; ++r) {
                 const int64_t row = rb * 16 + 4 * (lane >> 4) + r;
-                if (row >= w.m) continue;
+                if (row >= w.m || earlier_pivot(rcv[r], skip_below)) continue;
                 const bool fresh = rcv[r] >= gcol0 && rcv[r] < gcol0 + wl;  // a pivot row of this leaf
                 pr.M[row * pr.ld + l0 + col] = fold7(acc, r, fresh ? 0u : cur[cbi][r], c32, w.F);
             }
@@ -565,16 +587,100 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(PlainArgs w, Mat dst
 // Write columns [0, width) of src into dst columns [d0, d0 + width); pivot
 // columns (bookkeeping columns gcol0 + js) become unit vectors.
 __global__ void panel_writeback_kernel(PlainArgs w, Mat src, Mat dst, int64_t d0, int32_t width,
-                                       int32_t gcol0) {
+                                       int32_t gcol0, int32_t skip_below) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= (int64_t)w.m * width) return;
     const int64_t r = gid / width;
+    if (earlier_pivot(w.rowcol[r], skip_below)) return;
     const int js = (int)(gid % width);
     const int s = w.colpiv[gcol0 + js];
     uint32_t v;
     if (s >= 0) v = (w.pivrow[s] == r) ? 1u : 0u;
     else v = src.M[r * src.ld + js];
     dst.M[r * dst.ld + d0 + js] = v;
+}
+
+// Back-substitution after forward elimination (the solve).  The pivot row q of
+// a column c in panel [j0, j0 + wj) is 1 at c and 0 at every other pivot column
+// of its panel and of the panels before it; right of its panel it keeps
+// entries U[q][c'].  So, panel by panel from the last,
+//    x(c, t) = W[q][n + t] - sum over c' >= j0 + wj of U[q][c'] x(c', t),
+// with x(c', t) = W[pivot row of c'][n + t] once its panel is done and 0 for a
+// free column c'.  bs_partial_kernel: a workgroup takes 64 columns c' and 16
+// panel columns (4 per wave, lane = right-hand side t); each product is exact
+// and lazily reduced (lz_prod, in [-p, 2p)), 64 of them sum below 2^38, and
+// the sums of at most 2^15 workgroups meet in FP64 atomics below 2^53 (exact,
+// so the order of the additions does not matter).  bs_finish_kernel writes
+// x = W[q][n + t] - acc mod p into the pivot row and clears acc.
+__device__ __forceinline__ double lz_prod(double a, double b, const FieldConst& F) {
+    const double h = a * b;
+    const double l = __fma_rn(a, b, -h);
+    const double q = floor(h * F.pinv);
+    return __fma_rn(-q, F.dp, h) + l;
+}
+
+constexpr int kBsCols = 64;  // columns c' per workgroup
+
+__global__ __launch_bounds__(kThreads) void bs_partial_kernel(PlainArgs w, int32_t n, int32_t k,
+                                                              int32_t j0, int32_t wj, double* acc) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t c_lo = j0 + wj + blockIdx.x * kBsCols;
+    const int32_t c_hi = min(c_lo + kBsCols, n);
+    const int32_t cl0 = blockIdx.y * 16 + wave * 4;  // the wave's first panel column
+    int64_t prow[4];
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int32_t cl = cl0 + i;
+        const int32_t sp = cl < wj ? w.colpiv[j0 + cl] : -1;
+        prow[i] = sp >= 0 ? (int64_t)w.pivrow[sp] : -1;
+        any = any || prow[i] >= 0;
+    }
+    if (!any) return;  // uniform over the wave; no barrier below
+    for (int32_t t0 = 0; t0 < k; t0 += 64) {
+        const int32_t t = t0 + lane;
+        const int32_t tc = t < k ? t : k - 1;
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int32_t c = c_lo; c < c_hi; ++c) {
+            const int32_t sp = w.colpiv[c];
+            if (sp < 0) continue;  // a free column: x = 0
+            const double xv = (double)w.W[(int64_t)w.pivrow[sp] * w.ld + n + tc];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (prow[i] < 0) continue;
+                const double u = (double)w.W[prow[i] * w.ld + c];
+                a[i] += lz_prod(u, xv, w.F);
+            }
+        }
+        if (t < k) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (prow[i] >= 0) atomicAdd(&acc[(int64_t)(cl0 + i) * k + t], a[i]);
+        }
+    }
+}
+
+__global__ void bs_finish_kernel(PlainArgs w, int32_t n, int32_t k, int32_t j0, int32_t wj, double* acc) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (int64_t)wj * k) return;
+    const int32_t cl = (int32_t)(gid / k), t = (int32_t)(gid % k);
+    const double sum = acc[gid];
+    acc[gid] = 0.0;
+    const int32_t sp = w.colpiv[j0 + cl];
+    if (sp < 0) return;
+    uint32_t* x = w.W + (int64_t)w.pivrow[sp] * w.ld + n + t;
+    // sum is an integer below 2^53 in magnitude: two lazy quotient steps bring
+    // it into [-p, 2p) (the first quotient is within 2^-20 of exact), then canonical
+    double r = __fma_rn(-floor(sum * w.F.pinv), w.F.dp, sum);
+    r = __fma_rn(-floor(r * w.F.pinv), w.F.dp, r);
+    if (r < 0.0) r += w.F.dp;
+    if (r >= w.F.dp) r -= w.F.dp;
+    *x = sub_mod(*x, (uint32_t)r, w.F.p);
+}
+
+__global__ void bs_clear_kernel(double* acc, int64_t count) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid < count) acc[gid] = 0.0;
 }
 
 constexpr int32_t kLeaf = 32;  // inner panel width of the two-level reduction
@@ -585,6 +691,7 @@ struct Blocked {
     int8_t* Afrag;
     int8_t* Bfrag;
     int8_t* Yfrag;  // the int8 leaf products' right operand (kept apart from the trailing one)
+    double* bs_acc; // back-substitution sums of one panel: panel x max(k, 1)
     LeafState leaf;
     int32_t panel;
 };
@@ -607,6 +714,7 @@ size_t carve_blocked(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, B
     int8_t* A = c.take<int8_t>(abytes);
     int8_t* B = c.take<int8_t>(bbytes);
     int8_t* Y = c.take<int8_t>(Nl * kLeaf * 4);
+    double* acc = c.take<double>((int64_t)panel * (k > 0 ? k : 1));
     LeafState ls;
     leaf_carve(c, m, Nl, &ls);
     if (b) {
@@ -615,6 +723,7 @@ size_t carve_blocked(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, B
         b->Afrag = A;
         b->Bfrag = B;
         b->Yfrag = Y;
+        b->bs_acc = acc;
         b->leaf = ls;
         b->panel = panel;
     }
@@ -627,7 +736,8 @@ size_t carve_blocked(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, B
 // whose pivot column lies in [fresh_lo, fresh_hi).
 hipError_t run_product(const PlainArgs& w, bool fp64, const int8_t* Af, const int8_t* Bf, Mat dst,
                        int64_t col0, int64_t N, int32_t KB, int32_t fresh_lo, int32_t fresh_hi,
-                       hipStream_t s, LaunchTimer& lt, int kind, int64_t max_wgs = 0) {
+                       hipStream_t s, LaunchTimer& lt, int kind, int64_t max_wgs = 0,
+                       int32_t skip_below = 0) {
     const int64_t m = w.m;
     lt.before(kind, s);
     if (fp64) {
@@ -639,7 +749,7 @@ hipError_t run_product(const PlainArgs& w, bool fp64, const int8_t* Af, const in
         const int64_t tiles = ceil_div(m, 128) * ceil_div(N, 32);
         const int64_t grid = max_wgs > 0 && max_wgs < tiles ? max_wgs : tiles;
         hipLaunchKernelGGL(gemm_i8_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, w, dst, col0, N,
-                           Af, Bf, KB, fresh_lo, fresh_hi, c32);
+                           Af, Bf, KB, fresh_lo, fresh_hi, c32, skip_below);
     }
     lt.after();
     return hipGetLastError();
@@ -675,6 +785,25 @@ int32_t trailing_operands(const Blocked& b, const PlainArgs& w, bool fp64, Mat d
     return KB;
 }
 
+// Panels from the last to the first (see bs_partial_kernel).
+hipError_t back_substitute(const Blocked& b, int64_t n, int64_t k, int32_t panel, hipStream_t s) {
+    const PlainArgs& w = b.w;
+    const int64_t cnt = (int64_t)panel * k;
+    hipLaunchKernelGGL(bs_clear_kernel, dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, s, b.bs_acc, cnt);
+    const int64_t last = (n - 1) / panel * panel;
+    for (int64_t j0 = last; j0 >= 0; j0 -= panel) {
+        const int32_t wj = (int32_t)(n - j0 < panel ? n - j0 : panel);
+        const int64_t after = n - j0 - wj;
+        if (after <= 0) continue;  // the last panel: nothing to its right
+        hipLaunchKernelGGL(bs_partial_kernel,
+                           dim3((unsigned)ceil_div(after, kBsCols), (unsigned)ceil_div(wj, 16)),
+                           dim3(kThreads), 0, s, w, (int32_t)n, (int32_t)k, (int32_t)j0, wj, b.bs_acc);
+        hipLaunchKernelGGL(bs_finish_kernel, dim3((unsigned)ceil_div((int64_t)wj * k, 256)), dim3(256),
+                           0, s, w, (int32_t)n, (int32_t)k, (int32_t)j0, wj, b.bs_acc);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
 
 size_t blocked_workspace(int64_t m, int64_t n, int64_t k, int32_t panel) {
@@ -698,7 +827,8 @@ size_t blocked_workspace(int64_t m, int64_t n, int64_t k, int32_t panel) {
 // the remainder reads only rowcol, to spot the previous panel's pivot rows,
 // which new pivot rows (from -1 to a later column) never are either way.
 hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, bool fp64,
-                             bool overlap, PlainArgs& out, const linac_opts* opts, hipStream_t s) {
+                             bool overlap, bool forward, PlainArgs& out, const linac_opts* opts,
+                             hipStream_t s) {
     Blocked b;
     carve_blocked(ws, m, n, k, panel, &b);
     b.w.F = out.F;
@@ -714,6 +844,7 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
     hipStream_t side = nullptr;
     hipEvent_t ev_t1 = nullptr, ev_t2 = nullptr;
     const bool lookahead = overlap && !fp64 && n > panel;
+    forward = forward && !fp64 && k > 0;  // the int8 path with right-hand sides to solve for
     // Y built by the selection's second launch when the first one decided the
     // leaf (faster than a rebuild in every product workgroup)
     const bool select_y = true;
@@ -735,6 +866,7 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
     int32_t leaf_index = 0;
     for (int32_t j0 = 0; j0 < n && e == hipSuccess; j0 += panel) {
         const int32_t wj = (int32_t)(n - j0 < panel ? n - j0 : panel);
+        const int32_t skip_below = forward ? j0 : 0;
         hipLaunchKernelGGL(panel_extract_kernel, dim3(tiles, (unsigned)ceil_div(b.PR.ld, 256)),
                            dim3(kThreads), 0, s, w.m, Wm, (int64_t)j0, b.PR, wj);
         for (int32_t l0 = 0; l0 < wj && e == hipSuccess; l0 += kLeaf) {
@@ -766,7 +898,7 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
                                    (const LeafOut*)b.leaf.out, (const uint32_t*)b.leaf.rsave,
                                    b.leaf.ldr, c32, (const int32_t*)b.leaf.cand[parity],
                                    b.leaf.cand[parity ^ 1], (const int32_t*)(b.leaf.count + parity),
-                                   b.leaf.count + (parity ^ 1), (const int8_t*)b.Yfrag);
+                                   b.leaf.count + (parity ^ 1), (const int8_t*)b.Yfrag, skip_below);
                 lt.after();
                 e = hipGetLastError();
             }
@@ -788,27 +920,28 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
             const int64_t n1 = lookahead && N > panel ? panel : N;
             if (e == hipSuccess)
                 e = run_product(w, fp64, b.Afrag, b.Bfrag, Wm, col0, n1, KB, j0, j0 + wj, s, lt,
-                                LINAC_KERNEL_TRAIL_PRODUCT);
+                                LINAC_KERNEL_TRAIL_PRODUCT, 0, skip_below);
             if (e == hipSuccess && n1 < N) {
                 e = hipEventRecord(ev_t1, s);
                 if (e == hipSuccess) e = hipStreamWaitEvent(side, ev_t1, 0);
                 if (e == hipSuccess)
                     e = run_product(w, fp64, b.Afrag, b.Bfrag + (n1 / 32) * KB * 4 * 1024, Wm,
                                     col0 + n1, N - n1, KB, j0, j0 + wj, side, lt,
-                                    LINAC_KERNEL_TRAIL_PRODUCT, side_wgs);
+                                    LINAC_KERNEL_TRAIL_PRODUCT, side_wgs, skip_below);
                 if (e == hipSuccess) e = hipEventRecord(ev_t2, side);
                 t2_pending = e == hipSuccess;
             }
             ++outer_products;
         }
         hipLaunchKernelGGL(panel_writeback_kernel, dim3((unsigned)ceil_div(m * wj, 256)), dim3(256),
-                           0, s, w, b.PR, Wm, (int64_t)j0, wj, j0);
+                           0, s, w, b.PR, Wm, (int64_t)j0, wj, j0, skip_below);
         if (e == hipSuccess) e = hipGetLastError();
     }
     if (t2_pending) {
         const hipError_t e2 = hipStreamWaitEvent(s, ev_t2, 0);
         if (e == hipSuccess) e = e2;
     }
+    if (forward && e == hipSuccess) e = back_substitute(b, n, k, panel, s);
     if (ev_t1) (void)hipEventDestroy(ev_t1);
     if (ev_t2) (void)hipEventDestroy(ev_t2);
     if (opts && opts->ev_end && outer_products > 0) (void)hipEventRecord(opts->ev_end, s);

@@ -175,8 +175,12 @@ hipError_t leaf_operands(const PlainArgs& w, const LeafState& ls, const uint32_t
 // buffer and the MFMA operand fragments.  `a` carries the field in and the
 // carved bookkeeping out (for the shared extraction kernels).
 size_t blocked_workspace(int64_t m, int64_t n, int64_t k, int32_t panel);
+// forward = true (solves with right-hand sides, int8 path): forward elimination
+// then back-substitution into the pivot rows' right-hand sides, instead of
+// Gauss-Jordan (the reduced matrix is then not an RREF; only X is read).
 hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, bool fp64,
-                             bool lookahead, PlainArgs& a, const linac_opts* opts, hipStream_t s);
+                             bool lookahead, bool forward, PlainArgs& a, const linac_opts* opts,
+                             hipStream_t s);
 
 // Batched path (batched.hip): workspace = [queue counter | descriptors | one
 // working region per system].
@@ -189,6 +193,51 @@ void* batched_desc_ptr(void* ws);
 // Rows of the multiplier array in dynamic LDS: the largest m, rounded up to 64.
 int32_t batched_mult_rows(const linac_system* sys, int32_t count);
 hipError_t batched_launch(void* ws, int32_t count, int32_t grid, int32_t mult_rows, hipStream_t s);
+
+// Around the elimination (apps.hip): the system construction from monomials,
+// the canonical null-space basis of an RREF and the pivot columns of A.
+hipError_t launch_load_matrix(const uint32_t* bases, int64_t nrows, int64_t nb, int64_t ldbases,
+                              const int32_t* lind, int64_t ncols, int64_t d, int64_t ldl,
+                              const FieldConst& F, uint32_t* A, int64_t lda, hipStream_t s);
+hipError_t launch_nullspace(const uint32_t* R, int64_t m, int64_t n, int64_t ldr, const int32_t* rank,
+                            const int32_t* pivots, uint32_t p, uint32_t* K, int64_t kcols, int64_t ldk,
+                            int32_t* free_cols, hipStream_t s);
+hipError_t launch_column_basis(const uint32_t* A, int64_t m, int64_t n, int64_t lda, const int32_t* rank,
+                               const int32_t* pivots, uint32_t* C, int64_t ccols, int64_t ldc,
+                               hipStream_t s);
+
+// Column-step engine (colstep.hip): Gauss-Jordan for 64-bit primes and the
+// LUP factorisation, one search and one update launch per pivot column.
+size_t colstep_workspace(int64_t m, int64_t n, int64_t k, bool wide);
+template <typename W>
+hipError_t colstep_range(const W* M, int64_t rows, int64_t cols, int64_t ld, W p, uint32_t* flag,
+                         hipStream_t s);
+template <typename W>
+hipError_t colstep_rref(W* A, int64_t m, int64_t n, int64_t lda, W p, int32_t* rank, int32_t* pivots,
+                        void* ws, hipStream_t s);
+template <typename W>
+hipError_t colstep_solve(const W* A, int64_t m, int64_t n, int64_t lda, const W* B, int64_t k,
+                         int64_t ldb, W p, W* X, int64_t ldx, int32_t* rank, int32_t* pivots,
+                         uint8_t* consistent, void* ws, hipStream_t s);
+template <typename W>
+hipError_t colstep_lup(W* A, int64_t m, int64_t n, int64_t lda, W p, int32_t* perm, int32_t* rank,
+                       int32_t* pivots, void* ws, hipStream_t s);
+
+// linac_solve split in two (api.hip): the host checks (on success *path and
+// *need, the workspace bytes, are set), and the launches on a workspace of at
+// least that size.  allow_overlap = false keeps the blocked int8 path on `s`
+// (no side stream, no events created).  hip_status records a HIP error for
+// linac_last_hip_error and maps it to a status.
+linac_status solve_check(const uint32_t* A, int64_t m, int64_t n, int64_t lda, const uint32_t* B,
+                         int64_t k, int64_t ldb, uint32_t p, const uint32_t* X, int64_t ldx,
+                         const int32_t* rank, const int32_t* pivots, const uint8_t* consistent,
+                         const linac_opts* opts, int* path, size_t* need);
+linac_status solve_launch(const uint32_t* A, int64_t m, int64_t n, int64_t lda, const uint32_t* B,
+                          int64_t k, int64_t ldb, uint32_t p, uint32_t* X, int64_t ldx,
+                          int32_t* rank, int32_t* pivots, uint8_t* consistent, void* ws, int path,
+                          const linac_opts* opts, hipStream_t s, bool allow_overlap,
+                          const char* name);
+linac_status hip_status(hipError_t e);
 
 // Range check of residues: sets *flag to 1 when an entry is >= p.
 hipError_t launch_range_check(const uint32_t* M, int64_t rows, int64_t cols, int64_t ld, uint32_t p,

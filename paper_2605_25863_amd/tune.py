@@ -9,8 +9,10 @@ prime, 16 right-hand sides):
     crossover "blocked_min";
   * the blocked path at each candidate panel width, per size bucket ("panel");
   * the look-ahead switch of the blocked path at the largest size ("lookahead");
-  * the batched launch at 1, 2, 4 and 8 resident workgroups per compute unit on
-    a batch of uneven systems ("batched_per_cu").
+  * the batched launch at 1, 2, 3, 4, 6 and 8 resident workgroups per compute
+    unit on a batch of uneven systems ("batched_per_cu");
+  * the batched RREF (linac_rref_batched) at 1, 2, 3, 4, 6 and 8 stream lanes
+    on a batch of sparse-pattern matrices ("rref_lanes").
 Every candidate configuration computes the same unique RREF, so the table only
 changes speed.  The written file (default: tuning_gfx950.json next to this
 module) is loaded by the Python binding at import.
@@ -108,10 +110,43 @@ def tune(quick: bool = False):
         per_cu[c] = (time.perf_counter() - t0) / reps
         print(f"batched per_cu={c}: {per_cu[c] * 1e3:.2f} ms", flush=True)
     best_cu = min(per_cu, key=per_cu.get)
+    # batched RREF: stream lanes, on sparse-pattern matrices (the tuned panels)
+    count = 8 if quick else 16
+    mats = [A for _, A in workloads.sparse_pattern_instances_torch(torch.device("cuda"), count=count)]
+    pm = workloads.MERSENNE31
+    work = [torch.empty_like(A) for A in mats]
+    base = {"blocked_min": blocked_min or sizes[-1] * 2, "panel": rules, "lookahead": lookahead}
+    per_lanes = {}
+    for lanes in (1, 2, 3, 4, 6, 8):
+        lx.load_tuning(json.dumps(dict(base, rref_lanes=lanes)))
+        ws = torch.empty(lx.rref_batched_workspace_bytes([tuple(A.shape)] * count), dtype=torch.uint8,
+                         device="cuda")
+        ts = []
+        for rep in range(reps + 1):
+            for A, Wk in zip(mats, work):
+                Wk.copy_(A)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lx.rref_batched(work, pm, inplace=True, workspace=ws)
+            torch.cuda.synchronize()
+            if rep:  # the first pass warms up
+                ts.append(time.perf_counter() - t0)
+        per_lanes[lanes] = float(np.median(ts))
+        del ws
+        print(f"rref_batched lanes={lanes}: {per_lanes[lanes] * 1e3:.2f} ms "
+              f"({count} matrices)", flush=True)
+    best_lanes = min(per_lanes, key=per_lanes.get)
+    del mats, work
     table = {"arch": "gfx950", "blocked_min": blocked_min or sizes[-1] * 2,
              "panel": rules, "batched_per_cu": best_cu, "lookahead": lookahead,
+             "rref_lanes": best_lanes,
              "measured": {"crossover_s": report["crossover"], "panel_s": report["panels"],
-                          "lookahead_s": per_la, "batched_s": per_cu}}
+                          "lookahead_s": per_la, "batched_s": per_cu,
+                          "rref_lanes_s": per_lanes,
+                          "batched_workload": f"{len(systems)} uneven systems of the c4 "
+                                              f"distribution (seed 4), mean of {reps} launches",
+                          "rref_lanes_workload": f"{count} sparse-pattern matrices of "
+                                                 f"12000 x 10000 (seed 5), median of {reps}"}}
     lx.restore_tuning()
     return table
 
@@ -125,7 +160,7 @@ def main():
     with open(args.out, "w") as f:
         json.dump(table, f, indent=1)
     print(json.dumps({k: table[k] for k in ("blocked_min", "panel", "batched_per_cu",
-                                             "lookahead")}))
+                                             "lookahead", "rref_lanes")}))
 
 
 if __name__ == "__main__":

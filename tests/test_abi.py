@@ -194,3 +194,86 @@ def test_plan(lib):
         assert plan(5, 5, lx._opts(7))[0] == UNSUP
     finally:
         lx.restore_tuning()
+
+
+def test_load_matrix_argument_errors(lib):
+    f = _fake
+    lm = lib.linac_load_matrix
+    # (bases, nrows, nbasis, ldbases, lindices, ncols, d, ldl, p, A, lda, stream)
+    assert lm(f(1), -1, 4, 4, f(2), 5, 2, 2, 7, f(3), 5, None) == INVALID
+    assert lm(f(1), 3, 4, 3, f(2), 5, 2, 2, 7, f(3), 5, None) == INVALID  # ldbases < nbasis
+    assert lm(f(1), 3, 4, 4, f(2), 5, 2, 1, 7, f(3), 5, None) == INVALID  # ldl < d
+    assert lm(f(1), 3, 4, 4, f(2), 5, 2, 2, 7, f(3), 4, None) == INVALID  # lda < ncols
+    assert lm(None, 3, 4, 4, f(2), 5, 2, 2, 7, f(3), 5, None) == INVALID
+    assert lm(f(1), 3, 4, 4, None, 5, 2, 2, 7, f(3), 5, None) == INVALID
+    assert lm(f(1), 3, 4, 4, f(2), 5, 2, 2, 7, None, 5, None) == INVALID
+    assert lm(f(1), 3, 4, 4, f(2), 5, -1, 1, 7, f(3), 5, None) == INVALID
+    assert lm(f(1), 3, 4, 4, f(2), 5, 2, 2, 15, f(3), 5, None) == NOTPRIME
+    assert lm(f(1), 3, 4, 4, f(2), 5, 2, 2, 0, f(3), 5, None) == UNSUP
+    assert lm(f(1), 1 << 31, 4, 4, f(2), 5, 2, 2, 7, f(3), 5, None) == NOMEM
+    # empty shapes need no pointers and launch nothing
+    assert lm(None, 0, 4, 4, None, 0, 2, 2, 7, None, 1, None) == OK
+    assert lm(None, 0, 0, 1, f(2), 5, 2, 2, 7, None, 5, None) == OK
+
+
+def test_nullspace_and_column_basis_argument_errors(lib):
+    f = _fake
+    ns = lib.linac_nullspace
+    # (R, m, n, ldr, rank, pivots, p, K, kcols, ldk, free_cols, stream)
+    assert ns(f(1), 3, 4, 4, f(2), f(3), 7, f(4), 5, 5, None, None) == INVALID  # kcols > n
+    assert ns(f(1), 3, 4, 3, f(2), f(3), 7, f(4), 4, 4, None, None) == INVALID  # ldr < n
+    assert ns(f(1), 3, 4, 4, f(2), f(3), 7, f(4), 4, 3, None, None) == INVALID  # ldk < kcols
+    assert ns(f(1), 3, 4, 4, None, f(3), 7, f(4), 4, 4, None, None) == INVALID
+    assert ns(None, 3, 4, 4, f(2), f(3), 7, f(4), 4, 4, None, None) == INVALID
+    assert ns(f(1), 3, 4, 4, f(2), None, 7, f(4), 4, 4, None, None) == INVALID
+    assert ns(f(1), 3, 4, 4, f(2), f(3), 7, None, 4, 4, None, None) == INVALID
+    assert ns(f(1), 3, 4, 4, f(2), f(3), 9, f(4), 4, 4, None, None) == NOTPRIME
+    assert ns(None, 0, 0, 1, f(2), None, 7, None, 0, 1, None, None) == OK
+    cb = lib.linac_column_basis
+    # (A, m, n, lda, rank, pivots, C, ccols, ldc, stream)
+    assert cb(f(1), 3, 4, 4, f(2), f(3), f(4), 4, 4, None) == INVALID  # ccols > min(m, n)
+    assert cb(f(1), 3, 4, 3, f(2), f(3), f(4), 3, 3, None) == INVALID  # lda < n
+    assert cb(f(1), 3, 4, 4, f(2), f(3), f(4), 3, 2, None) == INVALID  # ldc < ccols
+    assert cb(f(1), 3, 4, 4, None, f(3), f(4), 3, 3, None) == INVALID
+    assert cb(None, 3, 4, 4, f(2), f(3), f(4), 3, 3, None) == INVALID
+    assert cb(f(1), 3, 4, 4, f(2), f(3), None, 3, 3, None) == INVALID
+    assert cb(None, 0, 4, 4, f(2), None, None, 0, 1, None) == OK
+
+
+def test_u64_and_lup_host_checks(lib):
+    f = _fake
+    OKP = 9223372036854775783  # 2^63 - 25
+    assert lib.linac_check_prime_u64(OKP) == OK
+    assert lib.linac_check_prime_u64(4611686018427387847) == OK
+    assert lib.linac_check_prime_u64(4294967311) == OK
+    assert lib.linac_check_prime_u64(2) == OK
+    assert lib.linac_check_prime_u64(1 << 63) == UNSUP
+    assert lib.linac_check_prime_u64((1 << 64) - 59) == UNSUP  # prime, but above 2^63
+    assert lib.linac_check_prime_u64(0) == UNSUP
+    assert lib.linac_check_prime_u64(3215031751) == NOTPRIME  # spsp(2,3,5,7)
+    assert lib.linac_check_prime_u64(3825123056546413051) == NOTPRIME  # spsp to bases 2..23
+    assert lib.linac_check_prime_u64(4294967297) == NOTPRIME  # 641 * 6700417
+    for v in range(1, 2000):
+        prime = v > 1 and all(v % q for q in range(2, int(v ** 0.5) + 1))
+        assert lib.linac_check_prime_u64(v) == (OK if prime else (UNSUP if v == 0 else NOTPRIME)), v
+    ws = ctypes.c_size_t()
+    assert lib.linac_rref_u64_workspace(100, 50, ctypes.byref(ws)) == OK and ws.value > 100 * 50 * 8
+    assert lib.linac_lup_workspace(100, 50, 0, ctypes.byref(ws)) == OK
+    # (A, m, n, lda, p, rank, pivots, ws, ws_bytes, opts, stream)
+    ru = lib.linac_rref_u64
+    assert ru(f(1), 3, 4, 3, OKP, f(2), f(3), f(4), 1 << 20, None, None) == INVALID
+    assert ru(f(1), 3, 4, 4, OKP, None, f(3), f(4), 1 << 20, None, None) == INVALID
+    assert ru(f(1), 3, 4, 4, 1 << 63, f(2), f(3), f(4), 1 << 20, None, None) == UNSUP
+    assert ru(f(1), 3, 4, 4, OKP - 2, f(2), f(3), f(4), 1 << 20, None, None) == NOTPRIME
+    assert ru(f(1), 3, 4, 4, OKP, f(2), f(3), f(4), 16, None, None) == WS
+    su = lib.linac_solve_u64
+    assert su(f(1), 3, 4, 4, f(2), 2, 1, OKP, f(3), 2, f(4), f(5), f(6), f(7), 1 << 20, None,
+              None) == INVALID
+    assert su(f(1), 3, 4, 4, f(2), 2, 2, OKP, f(3), 2, f(4), f(5), None, f(7), 1 << 20, None,
+              None) == INVALID
+    lu = lib.linac_lup
+    # (A, m, n, lda, p, perm, rank, pivots, ws, ws_bytes, opts, stream)
+    assert lu(f(1), 3, 4, 4, 7, None, f(2), f(3), f(4), 1 << 20, None, None) == INVALID
+    assert lu(f(1), 3, 4, 4, (1 << 31) + 11, f(5), f(2), f(3), f(4), 1 << 20, None, None) == UNSUP
+    assert lib.linac_lup_u64(f(1), 3, 4, 4, 9, f(5), f(2), f(3), f(4), 1 << 20, None,
+                             None) == NOTPRIME

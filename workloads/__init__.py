@@ -20,6 +20,11 @@ square matrices with entries uniform in [0, p).  The five named workloads are
   pattern (200 non-zeros per independent row, 2500 dependent rows), p = 2^31-1
   (seed 5).  It stands in for the sample-point systems of the paper's
   applications (Sec. 5.5), whose data are not available.
+
+Beside them, ``monomial_system`` draws the inputs of the system construction
+(Sec. 3.3): the basis variables at each sampling point and the index lists of
+the monomials of an ansatz (workload ``lm``: 20000 sampling points and 20000
+monomials, the largest size the paper times for construction, Sec. 4.2).
 """
 
 from __future__ import annotations
@@ -41,6 +46,8 @@ __all__ = [
     "sparse_pattern_instances_torch",
     "small_cases",
     "vandermonde_nodes",
+    "monomial_system",
+    "LM_CONFIG",
 ]
 
 
@@ -338,3 +345,29 @@ def vandermonde_nodes(seed: int, count: int, p: int, distinct: bool = True) -> n
                 seen.append(x)
         return np.array(seen, dtype=np.uint64)
     return rng.integers(0, p, size=count, dtype=np.uint64)
+
+
+# System construction (Sec. 3.3): square, like the paper's timings (Sec. 4.2).
+LM_CONFIG = dict(seed=6, nrows=20000, ncols=20000, nbasis=48, d=12, p=MERSENNE31)
+
+
+def monomial_system(seed: int = 6, nrows: int = 20000, ncols: int = 20000, nbasis: int = 48,
+                    d: int = 12, p: int = MERSENNE31):
+    """(bases, lindices, p) for the system construction.
+
+    bases (nrows x nbasis, uint32): column 0 is the dummy variable 1 that pads
+    shorter monomials (the paper's helper pads to one uniform degree); the
+    other basis variables are uniform in [1, p) at each sampling point.
+    lindices (ncols x d, int32): monomial c has a degree uniform in [1, d];
+    its variables are uniform in [1, nbasis) and the remaining d - degree
+    slots name the dummy variable 0.
+    """
+    rng = np.random.default_rng(seed)
+    bases = uniform(rng, (nrows, nbasis), p, low=1)
+    if nbasis:
+        bases[:, 0] = 1
+    deg = rng.integers(1, d + 1, size=ncols) if d else np.zeros(ncols, np.int64)
+    hi = max(nbasis, 2)
+    L = rng.integers(1, hi, size=(ncols, d)).astype(np.int32)
+    L[np.arange(d)[None, :] >= deg[:, None]] = 0
+    return bases, L, int(p)
