@@ -23,7 +23,12 @@
  *     query.  No pointer is kept after a call returns.
  *   - Calls are asynchronous on the HIP stream `s` (NULL = the null stream);
  *     outputs are valid once the stream has been synchronised.  Calls on
- *     distinct streams with distinct workspaces may run concurrently.
+ *     distinct streams with distinct workspaces may run concurrently and give
+ *     the same results.  Two library-internal resources are shared per
+ *     device: the blocked int8 path overlaps a panel's trailing update with
+ *     the next panel on one side stream per device, so the trailing parts of
+ *     concurrent blocked calls on one device queue behind each other there;
+ *     and linac_rref_batched calls on one device take turns on its lanes.
  *   - Errors are returned, never thrown.  All argument checks run on the host
  *     before any device work, so a non-OK return from a check leaves every
  *     buffer untouched.  On LINAC_E_HIP the outputs are unspecified and

@@ -46,19 +46,6 @@ constexpr int kTileRows = 32;
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ int32_t centre(uint32_t v, uint32_t p) {
-    return v > (p - 1) / 2 ? (int32_t)v - (int32_t)p : (int32_t)v;
-}
-
-// Four signed base-256 digits of x (|x| <= 2^30), least significant first.
-__device__ __forceinline__ void digits4(int32_t x, int8_t d[4]) {
-    for (int l = 0; l < 4; ++l) {
-        int8_t lo = (int8_t)(x & 0xff);
-        d[l] = lo;
-        x = (x - lo) >> 8;
-    }
-}
-
 // Forward elimination (the solve): a row that became a pivot in an earlier
 // panel (its pivot column below skip_below, the panel start) takes no part in
 // a panel -- not in the leaf products, not in the trailing product, not in the

@@ -149,4 +149,20 @@ __device__ inline uint32_t inv_mod(uint32_t a, uint32_t p) {
     return (uint32_t)t;
 }
 
+// The balanced representative of a residue: v - p when v > (p - 1) / 2, so
+// |result| <= (p - 1) / 2 (below 2^30 for p < 2^31).
+__device__ __forceinline__ int32_t centre(uint32_t v, uint32_t p) {
+    return v > (p - 1) / 2 ? (int32_t)v - (int32_t)p : (int32_t)v;
+}
+
+// Four signed base-256 digits of x (|x| <= 2^30), least significant first:
+// x = sum_l 256^l d[l] with every d[l] in [-128, 127].
+__device__ __forceinline__ void digits4(int32_t x, int8_t d[4]) {
+    for (int l = 0; l < 4; ++l) {
+        const int8_t lo = (int8_t)(x & 0xff);
+        d[l] = lo;
+        x = (x - lo) >> 8;
+    }
+}
+
 }  // namespace linac

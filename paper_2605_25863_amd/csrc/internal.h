@@ -15,15 +15,24 @@ static constexpr unsigned long long kNoPivot = ~0ull;
 __host__ __device__ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 __host__ __device__ inline int64_t ceil_div(int64_t x, int64_t m) { return (x + m - 1) / m; }
 
-// Carve aligned regions out of a caller-owned workspace.  With base == NULL it
-// only measures.
+// Carve regions out of a caller-owned workspace, each starting at a 256-byte
+// aligned ADDRESS (64-bit atomics and 128-bit accesses need their natural
+// alignment, and a region may start at an arbitrary offset of the caller's
+// buffer).  With base == NULL it only measures, aligning offsets; a real carve
+// then uses at most 255 bytes more, which the 256 bytes every workspace query
+// adds at the end cover.
 struct Carver {
     char* base;
     size_t off = 0;
     explicit Carver(void* b) : base((char*)b) {}
     template <class T>
     T* take(int64_t count) {
-        off = (size_t)round_up((int64_t)off, 256);
+        if (base) {
+            const uintptr_t at = (uintptr_t)(base + off);
+            off += (size_t)(((at + 255) & ~(uintptr_t)255) - at);
+        } else {
+            off = (size_t)round_up((int64_t)off, 256);
+        }
         T* p = base ? (T*)(base + off) : nullptr;
         off += (size_t)count * sizeof(T);
         return p;

@@ -876,18 +876,6 @@ __global__ void leaf_init_kernel(int32_t* cand, int32_t* count, int32_t* cnt, in
     if (tid == 0) count[0] = m;
 }
 
-__device__ __forceinline__ int32_t centre(uint32_t v, uint32_t p) {
-    return v > (p - 1) / 2 ? (int32_t)v - (int32_t)p : (int32_t)v;
-}
-
-__device__ __forceinline__ void digits4(int32_t x, int8_t d[4]) {
-    for (int l = 0; l < 4; ++l) {
-        const int8_t lo = (int8_t)(x & 0xff);
-        d[l] = lo;
-        x = (x - lo) >> 8;
-    }
-}
-
 struct OpArgs {
     PlainArgs w;
     const uint32_t* PR;
