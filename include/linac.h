@@ -184,6 +184,33 @@ linac_status linac_rref_batched_workspace(const linac_matrix* mats, int32_t coun
 linac_status linac_rref_batched(const linac_matrix* mats, int32_t count, void* ws, size_t ws_bytes,
                                 const linac_opts* opts, hipStream_t s);
 
+/* Size of the fixed scratch array behind linac_solve_noalloc (per GPU). */
+#define LINAC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/*
+ * linac_solve for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results and argument checks as linac_solve, without ws/ws_bytes:
+ * the scratch space is a fixed array of LINAC_NOALLOC_SCRATCH_BYTES inside the
+ * library, one per GPU, held from the first call on that GPU until the process
+ * ends.  The call allocates nothing (no hipMalloc or hipFree, no stream or
+ * event created): the blocked int8 path runs without its look-ahead side
+ * stream.  The caller still owns A, B and every output.
+ *   - LINAC_E_WORKSPACE when the system needs more scratch than the array holds
+ *     (linac_solve_workspace with the same opts gives the need; about
+ *     n (n + k) * 4 bytes on the plain path, so up to n of about 4000);
+ *   - LINAC_E_UNSUPPORTED with opts->validate (the range check reads a flag
+ *     back through a host copy).
+ * Every call on a GPU shares that GPU's array and leaves its contents behind;
+ * each call initialises what it reads.  Calls that overlap in time on one GPU
+ * (different streams, or different host threads without ordering) race on the
+ * array: serialise them.
+ */
+linac_status linac_solve_noalloc(const uint32_t* A, int64_t m, int64_t n, int64_t lda,
+                                 const uint32_t* B, int64_t k, int64_t ldb, uint32_t p, uint32_t* X,
+                                 int64_t ldx, int32_t* rank, int32_t* pivots, uint8_t* consistent,
+                                 const linac_opts* opts, hipStream_t s);
+
 /* One system of a batch: the same meaning as the linac_solve arguments, with its
  * own prime.  Square or rectangular; all pointers are device pointers. */
 typedef struct {

@@ -45,8 +45,11 @@ __all__ = [
     "PATH_AUTO", "PATH_PLAIN", "PATH_BLOCKED_INT8", "PATH_BLOCKED_FP64", "check_prime",
     "load_tuning", "TUNING_FILE", "LaunchTimes", "rref_workspace_bytes", "load_matrix",
     "canonical_kernel", "column_basis", "rank_factorization", "rref_batched", "rref_u64",
-    "solve_u64", "lup",
+    "solve_u64", "lup", "solve_noalloc",
+    "NOALLOC_SCRATCH_BYTES",
 ]
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # LINAC_NOALLOC_SCRATCH_BYTES in include/linac.h
 
 PATH_AUTO, PATH_PLAIN, PATH_BLOCKED_INT8, PATH_BLOCKED_FP64 = 0, 1, 2, 3
 
@@ -119,6 +122,8 @@ def _load():
     lib.linac_solve_batched_workspace.argtypes = [ctypes.POINTER(_System), ctypes.c_int32, optp,
                                                   szp]
     lib.linac_solve_batched.argtypes = [ctypes.POINTER(_System), ctypes.c_int32, vp, sz, optp, vp]
+    lib.linac_solve_noalloc.argtypes = [vp, i64, i64, i64, vp, i64, i64, u32, vp, i64, vp, vp, vp,
+                                        optp, vp]
     lib.linac_rref_batched_workspace.argtypes = [ctypes.POINTER(_Matrix), ctypes.c_int32, optp, szp]
     lib.linac_rref_batched.argtypes = [ctypes.POINTER(_Matrix), ctypes.c_int32, vp, sz, optp, vp]
     u64 = ctypes.c_uint64
@@ -145,7 +150,8 @@ def _load():
                  "linac_rref_batched_workspace", "linac_rref_batched",
                  "linac_rref_u64_workspace", "linac_rref_u64", "linac_solve_u64_workspace",
                  "linac_solve_u64", "linac_lup_workspace", "linac_lup", "linac_lup_u64",
-                 "linac_check_prime_u64"):
+                 "linac_check_prime_u64",
+                 "linac_solve_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     if os.path.exists(TUNING_FILE):
@@ -381,6 +387,40 @@ def solve(A, B, p: int, *, path: int = PATH_AUTO, validate: bool = False, verbos
     _check(lib.linac_solve(_ptr(At), m, n, max(n, 1), _ptr(Bt), k, max(k, 1), int(p), _ptr(X),
                            max(k, 1), _ptr(rank), _ptr(pivots), _ptr(cons), _ptr(ws),
                            ws.numel(), ctypes.byref(o), _stream(torch, stream)), "linac_solve")
+    if was_np:
+        torch.cuda.synchronize()
+        return (X.cpu().numpy().astype(np.uint32), int(rank.item()),
+                pivots.cpu().numpy()[: int(rank.item())].astype(np.int64),
+                cons.cpu().numpy().astype(np.uint8))
+    return X, rank, pivots, cons
+
+
+def solve_noalloc(A, B, p: int, *, path: int = PATH_AUTO, verbose: bool = False, stream=None,
+                  out=None, panel_width: int = 0):
+    """``solve`` through linac_solve_noalloc: the library's fixed scratch
+    array instead of a workspace (for callers that cannot allocate).  With
+    ``out`` = preallocated (X, rank, pivots, consistent) tensors and device
+    inputs the call allocates nothing.  Calls that overlap on one GPU race."""
+    torch = _torch()
+    lib = _load()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    At, was_np = _to_dev(torch, A, dev)
+    Bt, _ = _to_dev(torch, B, dev)
+    m, n = At.shape
+    k = Bt.shape[1]
+    if Bt.shape[0] != m:
+        raise ValueError("A and B must have the same number of rows")
+    if out is None:
+        X = torch.empty((n, k), dtype=torch.int32, device=dev)
+        rank = torch.zeros(1, dtype=torch.int32, device=dev)
+        pivots = torch.empty(min(m, n), dtype=torch.int32, device=dev)
+        cons = torch.empty(k, dtype=torch.uint8, device=dev)
+    else:
+        X, rank, pivots, cons = out
+    o = _opts(path, panel_width, False, verbose)
+    _check(lib.linac_solve_noalloc(_ptr(At), m, n, max(n, 1), _ptr(Bt), k, max(k, 1), int(p),
+                                   _ptr(X), max(k, 1), _ptr(rank), _ptr(pivots), _ptr(cons),
+                                   ctypes.byref(o), _stream(torch, stream)), "linac_solve_noalloc")
     if was_np:
         torch.cuda.synchronize()
         return (X.cpu().numpy().astype(np.uint32), int(rank.item()),
