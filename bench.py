@@ -252,8 +252,9 @@ def _rooflines(kinds, m, n, ncols, path_name, panel, src_hash, workload):
                            "unit": "GB/s"}
     else:
         # a solve with right-hand sides runs forward elimination on the int8 path
-        leaf_macs, trail_macs = blocked_work(m, n, ncols, panel,
-                                             forward=path_name == "int8" and ncols > n)
+        # from the tuned size on
+        fwd = path_name == "int8" and ncols > n and min(m, n) >= _tuned("forward_min", 12288)
+        leaf_macs, trail_macs = blocked_work(m, n, ncols, panel, forward=fwd)
         per_mac_ops, peak, unit = (32.0, I8_PEAK_TOPS, "TOP/s") if path_name == "int8" else \
             (2.0, FP64_PEAK_TFLOPS, "TFLOP/s")
         int8 = path_name == "int8"
@@ -639,6 +640,14 @@ def bench_colstep(n: int = 2048, k: int = 4, reps: int = 2):
     del A, B, A32
     _free_cuda()
     return out
+
+
+def _tuned(key: str, default: int) -> int:
+    import paper_2605_25863_amd as lx
+    try:
+        return int(json.load(open(lx.TUNING_FILE)).get(key, default))
+    except OSError:
+        return default
 
 
 def _rref_lanes() -> int:

@@ -374,7 +374,10 @@ linac_status linac_lup_u64(uint64_t* A, int64_t m, int64_t n, int64_t lda, uint6
  *   "lookahead":      1 (default) or 0: whether the blocked int8 path overlaps the
  *                     next panel's pivot selection with the trailing update (on a
  *                     second stream that the call joins back to s);
- *   "rref_lanes":     1..8, the matrices linac_rref_batched reduces concurrently.
+ *   "rref_lanes":     1..8, the matrices linac_rref_batched reduces concurrently;
+ *   "forward_min":    solves on the blocked int8 path eliminate forward and
+ *                     back-substitute once min(m, n) >= this (below it, and for
+ *                     every RREF, they run Gauss-Jordan).
  * Unknown keys are ignored.  Returns LINAC_E_INVALID_ARG (and keeps the current
  * table) for malformed text or out-of-range values.  Host only. */
 linac_status linac_load_tuning(const char* json);

@@ -167,6 +167,7 @@ struct Tuning {
     int32_t batched_per_cu = 4;
     int32_t lookahead = 1;       // blocked int8: overlap the next panel with the trailing update
     int32_t rref_lanes = 4;      // linac_rref_batched: instances reduced concurrently
+    int64_t forward_min = 12288; // solves on the blocked int8 path eliminate forward from min(m, n) >= this
     std::vector<PanelRule> panels{{1 << 30, 256}};
 };
 std::mutex g_tune_mu;
@@ -260,6 +261,7 @@ linac_status parse_tuning(const char* json, Tuning* t) {
         else if (k == "batched_per_cu") nt.batched_per_cu = (int32_t)v;
         else if (k == "lookahead") nt.lookahead = (int32_t)v;
         else if (k == "rref_lanes") nt.rref_lanes = (int32_t)v;
+        else if (k == "forward_min") nt.forward_min = (int64_t)v;
         else if (k.rfind("panel.", 0) == 0) {
             size_t dot = k.find('.', 6);
             if (dot == std::string::npos) return LINAC_E_INVALID_ARG;
@@ -273,7 +275,8 @@ linac_status parse_tuning(const char* json, Tuning* t) {
     for (const PanelRule& pr : rules)
         if (pr.n_max <= 0 || pr.panel < 32 || pr.panel > 512 || pr.panel % 32) return LINAC_E_INVALID_ARG;
     if (nt.blocked_min < 1 || nt.batched_per_cu < 1 || nt.batched_per_cu > 16 ||
-        (nt.lookahead != 0 && nt.lookahead != 1) || nt.rref_lanes < 1 || nt.rref_lanes > 8)
+        (nt.lookahead != 0 && nt.lookahead != 1) || nt.rref_lanes < 1 || nt.rref_lanes > 8 ||
+        nt.forward_min < 0)
         return LINAC_E_INVALID_ARG;
     std::sort(rules.begin(), rules.end(),
               [](const PanelRule& a, const PanelRule& b) { return a.n_max < b.n_max; });
@@ -324,13 +327,18 @@ linac_status path_workspace(int path, int64_t m, int64_t n, int64_t k, const lin
 // allow_overlap = false keeps the blocked int8 path on the caller's stream (no
 // side stream, no events: nothing is created).
 // forward = true: a solve (only X, rank, pivots and consistency are read), so
-// the blocked int8 path may eliminate forward and back-substitute.
+// the blocked int8 path may eliminate forward and back-substitute; it does so
+// from the tuned size forward_min on (below it Gauss-Jordan is faster: the
+// leaf chain, not the trailing product, bounds the time, and back-substitution
+// adds launches).
 hipError_t run_path(int path, void* ws, int64_t m, int64_t n, int64_t k, PlainArgs& a,
                     const linac_opts* opts, hipStream_t s, bool allow_overlap = true,
                     bool forward = false) {
     if (path == LINAC_PATH_PLAIN) return plain_eliminate(a, opts, s);
+    const Tuning t = tuning();
+    forward = forward && (m < n ? m : n) >= t.forward_min;
     return blocked_eliminate(ws, m, n, k, panel_width(opts, m, n), path == LINAC_PATH_BLOCKED_FP64,
-                             allow_overlap && tuning().lookahead != 0, forward, a, opts, s);
+                             allow_overlap && t.lookahead != 0, forward, a, opts, s);
 }
 
 bool size_ok(int64_t m, int64_t n, int64_t k) {

@@ -594,8 +594,10 @@ __global__ void panel_writeback_kernel(PlainArgs w, Mat src, Mat dst, int64_t d0
 //    x(c, t) = W[q][n + t] - sum over c' >= j0 + wj of U[q][c'] x(c', t),
 // with x(c', t) = W[pivot row of c'][n + t] once its panel is done and 0 for a
 // free column c'.  bs_partial_kernel: a workgroup takes 64 columns c' and 16
-// panel columns (4 per wave, lane = right-hand side t); each product is exact
-// and lazily reduced (lz_prod, in [-p, 2p)), 64 of them sum below 2^38, and
+// panel columns (4 per wave, lane = right-hand side t); the columns' pivot rows
+// and U entries are loaded once, lane by column, and broadcast across the wave
+// while the x loads of eight columns are in flight together; each product is
+// exact and lazily reduced (lz_prod, in [-p, 2p)), 64 of them sum below 2^38, and
 // the sums of at most 2^15 workgroups meet in FP64 atomics below 2^53 (exact,
 // so the order of the additions does not matter).  bs_finish_kernel writes
 // x = W[q][n + t] - acc mod p into the pivot row and clears acc.
@@ -612,7 +614,6 @@ __global__ __launch_bounds__(kThreads) void bs_partial_kernel(PlainArgs w, int32
                                                               int32_t j0, int32_t wj, double* acc) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int32_t c_lo = j0 + wj + blockIdx.x * kBsCols;
-    const int32_t c_hi = min(c_lo + kBsCols, n);
     const int32_t cl0 = blockIdx.y * 16 + wave * 4;  // the wave's first panel column
     int64_t prow[4];
     bool any = false;
@@ -624,19 +625,35 @@ __global__ __launch_bounds__(kThreads) void bs_partial_kernel(PlainArgs w, int32
         any = any || prow[i] >= 0;
     }
     if (!any) return;  // uniform over the wave; no barrier below
+    // lane L describes column c_lo + L: the row holding its x (-1: free or past
+    // n) and the four U entries of this wave's rows, all loaded at once
+    const int32_t cc = c_lo + lane;
+    const bool cin = cc < n;
+    const int32_t spc = cin ? w.colpiv[cc] : -1;
+    const int32_t xr_l = spc >= 0 ? w.pivrow[spc] : -1;
+    double u_l[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        u_l[i] = (cin && prow[i] >= 0) ? (double)w.W[prow[i] * w.ld + cc] : 0.0;
     for (int32_t t0 = 0; t0 < k; t0 += 64) {
         const int32_t t = t0 + lane;
         const int32_t tc = t < k ? t : k - 1;
         double a[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int32_t c = c_lo; c < c_hi; ++c) {
-            const int32_t sp = w.colpiv[c];
-            if (sp < 0) continue;  // a free column: x = 0
-            const double xv = (double)w.W[(int64_t)w.pivrow[sp] * w.ld + n + tc];
+        // eight columns per round: their x loads are issued together
+        for (int c8 = 0; c8 < kBsCols; c8 += 8) {
+            double xv[8];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                if (prow[i] < 0) continue;
-                const double u = (double)w.W[prow[i] * w.ld + c];
-                a[i] += lz_prod(u, xv, w.F);
+            for (int e = 0; e < 8; ++e) {
+                const int32_t xr = __builtin_amdgcn_readlane(xr_l, c8 + e);
+                xv[e] = xr >= 0 ? (double)w.W[(int64_t)xr * w.ld + n + tc] : 0.0;
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const double u = __shfl(u_l[i], c8 + e);
+                    a[i] += lz_prod(u, xv[e], w.F);
+                }
             }
         }
         if (t < k) {

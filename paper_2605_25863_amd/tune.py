@@ -9,6 +9,9 @@ prime, 16 right-hand sides):
     crossover "blocked_min";
   * the blocked path at each candidate panel width, per size bucket ("panel");
   * the look-ahead switch of the blocked path at the largest size ("lookahead");
+  * forward elimination with back-substitution against Gauss-Jordan for blocked
+    solves at n = 8192 and 16384 ("forward_min": the smallest size where
+    forward elimination wins);
   * the batched launch at 1, 2, 3, 4, 6 and 8 resident workgroups per compute
     unit on a batch of uneven systems ("batched_per_cu");
   * the batched RREF (linac_rref_batched) at 1, 2, 3, 4, 6 and 8 stream lanes
@@ -95,6 +98,26 @@ def tune(quick: bool = False):
                                  reps)
         print(f"n={n} lookahead={la}: {per_la[la] * 1e3:.2f} ms", flush=True)
     lookahead = min(per_la, key=per_la.get)
+    # forward elimination + back-substitution against Gauss-Jordan (solves only)
+    fwd_sizes = (4096, 8192) if quick else (8192, 16384)
+    per_fwd = {}
+    forward_min = 1 << 30
+    for n in fwd_sizes:
+        A, B, p = workloads.dense_system(seed=2000 + n, n=n, k=16)
+        At = torch.from_numpy(A.astype(np.int32)).cuda()
+        Bt = torch.from_numpy(B.astype(np.int32)).cuda()
+        panel = next(r["panel"] for r in rules if n <= r["n_max"])
+        res = {}
+        for fm in (0, 1 << 30):
+            lx.load_tuning(json.dumps({"lookahead": lookahead, "forward_min": fm}))
+            res["forward" if fm == 0 else "gauss_jordan"] = _time_solve(
+                lx, torch, At, Bt, p, lx.PATH_BLOCKED_INT8, panel, reps)
+        per_fwd[n] = res
+        print(f"n={n}: forward {res['forward'] * 1e3:.2f} ms, Gauss-Jordan "
+              f"{res['gauss_jordan'] * 1e3:.2f} ms", flush=True)
+        if res["forward"] < res["gauss_jordan"] and forward_min == 1 << 30:
+            forward_min = n
+        del At, Bt
     # batched: resident workgroups per CU
     systems = workloads.batched_systems(seed=4, count=512 if quick else 4096)
     prep = lx.prepare_batched(systems)
@@ -115,7 +138,8 @@ def tune(quick: bool = False):
     mats = [A for _, A in workloads.sparse_pattern_instances_torch(torch.device("cuda"), count=count)]
     pm = workloads.MERSENNE31
     work = [torch.empty_like(A) for A in mats]
-    base = {"blocked_min": blocked_min or sizes[-1] * 2, "panel": rules, "lookahead": lookahead}
+    base = {"blocked_min": blocked_min or sizes[-1] * 2, "panel": rules, "lookahead": lookahead,
+            "forward_min": forward_min}
     per_lanes = {}
     for lanes in (1, 2, 3, 4, 6, 8):
         lx.load_tuning(json.dumps(dict(base, rref_lanes=lanes)))
@@ -139,9 +163,9 @@ def tune(quick: bool = False):
     del mats, work
     table = {"arch": "gfx950", "blocked_min": blocked_min or sizes[-1] * 2,
              "panel": rules, "batched_per_cu": best_cu, "lookahead": lookahead,
-             "rref_lanes": best_lanes,
+             "rref_lanes": best_lanes, "forward_min": forward_min,
              "measured": {"crossover_s": report["crossover"], "panel_s": report["panels"],
-                          "lookahead_s": per_la, "batched_s": per_cu,
+                          "lookahead_s": per_la, "forward_s": per_fwd, "batched_s": per_cu,
                           "rref_lanes_s": per_lanes,
                           "batched_workload": f"{len(systems)} uneven systems of the c4 "
                                               f"distribution (seed 4), mean of {reps} launches",
@@ -160,7 +184,7 @@ def main():
     with open(args.out, "w") as f:
         json.dump(table, f, indent=1)
     print(json.dumps({k: table[k] for k in ("blocked_min", "panel", "batched_per_cu",
-                                             "lookahead", "rref_lanes")}))
+                                             "lookahead", "rref_lanes", "forward_min")}))
 
 
 if __name__ == "__main__":

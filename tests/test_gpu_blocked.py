@@ -322,3 +322,37 @@ def test_selection_trees(gpu, m, n, panel, kind):
     got = _solve(Aq, Bq, q, panel, path=FP64)
     for name, g, r in zip(("X", "rank", "pivots", "consistent"), got, ref):
         assert np.array_equal(np.asarray(g), np.asarray(r)), f"{tag} fp64: {name}"
+
+
+def test_forward_elimination_small_systems(gpu):
+    """Solves with forward elimination and back-substitution (forced from
+    every size through the tuning table) on ragged panels, rectangular, rank
+    deficient and free-column systems, against the oracle.  The same results
+    as Gauss-Jordan, which the rest of this file checks."""
+    import json
+    table = json.load(open(lx.TUNING_FILE))
+    table["forward_min"] = 1
+    lx.load_tuning(json.dumps(table))
+    try:
+        rng = np.random.default_rng(321)
+        for m, n, k, panel in [(300, 300, 5, 64), (257, 333, 17, 96), (700, 650, 6, 192),
+                               (900, 880, 5, 384), (600, 600, 8, 512), (129, 700, 9, 128),
+                               (800, 300, 3, 64), (64, 64, 1, 32)]:
+            A, B, p = workloads.dense_system(seed=m * 7 + n, n=n, k=k, m=m)
+            if m > 10:
+                A[m // 3] = A[1]          # rank deficient, consistent or not
+                A[:, n // 2] = 0          # a free column inside a panel
+                A[:, min(n - 1, 2 * panel + 5)] = A[:, 3]
+            tag = f"forward m={m} n={n} k={k} panel={panel}"
+            print(tag, flush=True)
+            got = lx.solve(A, B, p, path=lx.PATH_BLOCKED_INT8, panel_width=panel)
+            ref = oracle.solve(A, B, p)
+            for name, g, r in zip(("X", "rank", "pivots", "consistent"), got, ref):
+                assert np.array_equal(np.asarray(g), np.asarray(r)), f"{tag}: {name}"
+        for i, c in enumerate(workloads.small_cases(seed=4321, count=40, max_dim=90, max_k=6)):
+            got = lx.solve(c["A"], c["B"], c["p"], path=lx.PATH_BLOCKED_INT8, panel_width=32)
+            ref = oracle.solve(c["A"], c["B"], c["p"])
+            for name, g, r in zip(("X", "rank", "pivots", "consistent"), got, ref):
+                assert np.array_equal(np.asarray(g), np.asarray(r)), f"small case {i}: {name}"
+    finally:
+        lx.restore_tuning()
