@@ -377,7 +377,9 @@ linac_status linac_lup_u64(uint64_t* A, int64_t m, int64_t n, int64_t lda, uint6
  *   "rref_lanes":     1..8, the matrices linac_rref_batched reduces concurrently;
  *   "forward_min":    solves on the blocked int8 path eliminate forward and
  *                     back-substitute once min(m, n) >= this (below it, and for
- *                     every RREF, they run Gauss-Jordan).
+ *                     every RREF, they run Gauss-Jordan);
+ *   "leaf_blocks":    2, 3, 6 or 9: 16-column blocks per workgroup of the blocked
+ *                     int8 path's leaf product (a tile shape).
  * Unknown keys are ignored.  Returns LINAC_E_INVALID_ARG (and keeps the current
  * table) for malformed text or out-of-range values.  Host only. */
 linac_status linac_load_tuning(const char* json);

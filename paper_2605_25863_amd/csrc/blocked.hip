@@ -312,8 +312,10 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
 // implied by the bookkeeping), so no multiplier is overwritten while other
 // blocks still read it.  The launch also builds the next leaf's candidate list
 // (one entry per thread).
-constexpr int kLeafBlocks = 2;  // 16-column blocks per workgroup
-
+// kLeafBlocks: 16-column blocks per workgroup (a tuned shape: 2, 3, 6 or 9;
+// the multipliers' digits are built once and reused across the blocks, and
+// every block's current values are loaded up front).
+template <int kLeafBlocks>
 __global__ __launch_bounds__(kThreads, 4) void leaf_product_i8_kernel(
     PlainArgs w, Mat pr, int32_t l0, int32_t wl, int32_t wj, int32_t gcol0, int64_t N,
     const LeafOut* out, const uint32_t* rsave, int64_t ldr, double c32, const int32_t* cand,
@@ -831,8 +833,8 @@ size_t blocked_workspace(int64_t m, int64_t n, int64_t k, int32_t panel) {
 // the remainder reads only rowcol, to spot the previous panel's pivot rows,
 // which new pivot rows (from -1 to a later column) never are either way.
 hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, bool fp64,
-                             bool overlap, bool forward, PlainArgs& out, const linac_opts* opts,
-                             hipStream_t s) {
+                             bool overlap, bool forward, int32_t leaf_blocks, PlainArgs& out,
+                             const linac_opts* opts, hipStream_t s) {
     Blocked b;
     carve_blocked(ws, m, n, k, panel, &b);
     b.w.F = out.F;
@@ -895,14 +897,19 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
             } else {
                 const double c32 = (double)((((uint64_t)1) << 32) % w.F.p);
                 lt.before(LINAC_KERNEL_LEAF_PRODUCT);
-                hipLaunchKernelGGL(leaf_product_i8_kernel,
-                                   dim3((unsigned)ceil_div(m, 64),
-                                        (unsigned)ceil_div(N, 16 * kLeafBlocks)),
-                                   dim3(kThreads), 0, s, w, b.PR, l0, wl, wj, j0 + l0, N,
-                                   (const LeafOut*)b.leaf.out, (const uint32_t*)b.leaf.rsave,
-                                   b.leaf.ldr, c32, (const int32_t*)b.leaf.cand[parity],
-                                   b.leaf.cand[parity ^ 1], (const int32_t*)(b.leaf.count + parity),
-                                   b.leaf.count + (parity ^ 1), (const int8_t*)b.Yfrag, skip_below);
+#define LEAF_PRODUCT(LB)                                                                          \
+    hipLaunchKernelGGL(leaf_product_i8_kernel<LB>,                                                \
+                       dim3((unsigned)ceil_div(m, 64), (unsigned)ceil_div(N, 16 * (LB))),        \
+                       dim3(kThreads), 0, s, w, b.PR, l0, wl, wj, j0 + l0, N,                     \
+                       (const LeafOut*)b.leaf.out, (const uint32_t*)b.leaf.rsave, b.leaf.ldr, c32, \
+                       (const int32_t*)b.leaf.cand[parity], b.leaf.cand[parity ^ 1],              \
+                       (const int32_t*)(b.leaf.count + parity), b.leaf.count + (parity ^ 1),     \
+                       (const int8_t*)b.Yfrag, skip_below)
+                if (leaf_blocks >= 9) LEAF_PRODUCT(9);
+                else if (leaf_blocks >= 6) LEAF_PRODUCT(6);
+                else if (leaf_blocks >= 3) LEAF_PRODUCT(3);
+                else LEAF_PRODUCT(2);
+#undef LEAF_PRODUCT
                 lt.after();
                 e = hipGetLastError();
             }

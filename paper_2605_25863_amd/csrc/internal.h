@@ -187,9 +187,11 @@ size_t blocked_workspace(int64_t m, int64_t n, int64_t k, int32_t panel);
 // forward = true (solves with right-hand sides, int8 path): forward elimination
 // then back-substitution into the pivot rows' right-hand sides, instead of
 // Gauss-Jordan (the reduced matrix is then not an RREF; only X is read).
+// leaf_blocks: 16-column blocks per workgroup of the int8 leaf product (2, 3,
+// 6 or 9; a tuned shape, results identical).
 hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, bool fp64,
-                             bool lookahead, bool forward, PlainArgs& a, const linac_opts* opts,
-                             hipStream_t s);
+                             bool lookahead, bool forward, int32_t leaf_blocks, PlainArgs& a,
+                             const linac_opts* opts, hipStream_t s);
 
 // Batched path (batched.hip): workspace = [queue counter | descriptors | one
 // working region per system].

@@ -356,3 +356,34 @@ def test_forward_elimination_small_systems(gpu):
                 assert np.array_equal(np.asarray(g), np.asarray(r)), f"small case {i}: {name}"
     finally:
         lx.restore_tuning()
+
+
+@pytest.mark.parametrize("leaf_blocks", [3, 6, 9])
+def test_leaf_product_shapes(gpu, leaf_blocks):
+    """Every workgroup shape of the int8 leaf product the tuning table can pick
+    (16-column blocks per workgroup), on ragged panels, a selection tree and
+    free columns, against the oracle."""
+    import json
+    table = json.load(open(lx.TUNING_FILE))
+    table["leaf_blocks"] = leaf_blocks
+    lx.load_tuning(json.dumps(table))
+    try:
+        for m, n, k, panel in [(300, 300, 5, 64), (700, 650, 6, 192), (900, 880, 5, 384),
+                               (257, 333, 17, 96)]:
+            A, B, p = workloads.dense_system(seed=m + 11 * n, n=n, k=k, m=m)
+            A[m // 2] = A[5]
+            A[:, n // 3] = 0
+            A[40:80] = 0  # zero rows inside the first candidate chunks: the selection tree
+            tag = f"leaf_blocks={leaf_blocks} m={m} n={n} panel={panel}"
+            print(tag, flush=True)
+            got = lx.solve(A, B, p, path=lx.PATH_BLOCKED_INT8, panel_width=panel)
+            ref = oracle.solve(A, B, p)
+            for name, g, r in zip(("X", "rank", "pivots", "consistent"), got, ref):
+                assert np.array_equal(np.asarray(g), np.asarray(r)), f"{tag}: {name}"
+            R, rank, piv = lx.rref(A, p, path=lx.PATH_BLOCKED_INT8, panel_width=panel)
+            Rr, rr, pr = oracle.rref(A, p)
+            import torch
+            torch.cuda.synchronize()
+            assert int(rank.item()) == rr and np.array_equal(R.cpu().numpy().astype(np.uint32), Rr)
+    finally:
+        lx.restore_tuning()
