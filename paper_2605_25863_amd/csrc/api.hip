@@ -19,22 +19,24 @@
 
 using namespace linac;
 
-hipError_t linac::side_stream(hipStream_t* out) {
+hipError_t linac::side_stream(hipStream_t* out, int which) {
     static std::mutex mu;
-    static std::vector<hipStream_t> streams;
+    static std::vector<hipStream_t> streams;  // two per device
+    if (which != 0 && which != 1) return hipErrorInvalidValue;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     std::lock_guard<std::mutex> lock(mu);
-    if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
-    if (!streams[dev]) {
-        e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking);
+    const size_t slot = 2 * (size_t)dev + (size_t)which;
+    if (streams.size() <= slot) streams.resize(2 * (size_t)dev + 2, nullptr);
+    if (!streams[slot]) {
+        e = hipStreamCreateWithFlags(&streams[slot], hipStreamNonBlocking);
         if (e != hipSuccess) {
-            streams[dev] = nullptr;
+            streams[slot] = nullptr;
             return e;
         }
     }
-    *out = streams[dev];
+    *out = streams[slot];
     return hipSuccess;
 }
 
@@ -169,6 +171,7 @@ struct Tuning {
     int32_t rref_lanes = 4;      // linac_rref_batched: instances reduced concurrently
     int64_t forward_min = 12288; // solves on the blocked int8 path eliminate forward from min(m, n) >= this
     int32_t leaf_blocks = 2;     // 16-column blocks per workgroup of the int8 leaf product
+    int32_t leaf_pipeline = 1;   // blocked int8: overlap each leaf's product with the next selection
     std::vector<PanelRule> panels{{1 << 30, 256}};
 };
 std::mutex g_tune_mu;
@@ -264,6 +267,7 @@ linac_status parse_tuning(const char* json, Tuning* t) {
         else if (k == "rref_lanes") nt.rref_lanes = (int32_t)v;
         else if (k == "forward_min") nt.forward_min = (int64_t)v;
         else if (k == "leaf_blocks") nt.leaf_blocks = (int32_t)v;
+        else if (k == "leaf_pipeline") nt.leaf_pipeline = (int32_t)v;
         else if (k.rfind("panel.", 0) == 0) {
             size_t dot = k.find('.', 6);
             if (dot == std::string::npos) return LINAC_E_INVALID_ARG;
@@ -278,7 +282,7 @@ linac_status parse_tuning(const char* json, Tuning* t) {
         if (pr.n_max <= 0 || pr.panel < 32 || pr.panel > 512 || pr.panel % 32) return LINAC_E_INVALID_ARG;
     if (nt.blocked_min < 1 || nt.batched_per_cu < 1 || nt.batched_per_cu > 16 ||
         (nt.lookahead != 0 && nt.lookahead != 1) || nt.rref_lanes < 1 || nt.rref_lanes > 8 ||
-        nt.forward_min < 0 ||
+        nt.forward_min < 0 || (nt.leaf_pipeline != 0 && nt.leaf_pipeline != 1) ||
         (nt.leaf_blocks != 2 && nt.leaf_blocks != 3 && nt.leaf_blocks != 6 && nt.leaf_blocks != 9))
         return LINAC_E_INVALID_ARG;
     std::sort(rules.begin(), rules.end(),
@@ -341,7 +345,8 @@ hipError_t run_path(int path, void* ws, int64_t m, int64_t n, int64_t k, PlainAr
     const Tuning t = tuning();
     forward = forward && (m < n ? m : n) >= t.forward_min;
     return blocked_eliminate(ws, m, n, k, panel_width(opts, m, n), path == LINAC_PATH_BLOCKED_FP64,
-                             allow_overlap && t.lookahead != 0, forward, t.leaf_blocks, a, opts, s);
+                             allow_overlap && t.lookahead != 0, forward, t.leaf_blocks,
+                             allow_overlap && t.leaf_pipeline != 0, a, opts, s);
 }
 
 bool size_ok(int64_t m, int64_t n, int64_t k) {

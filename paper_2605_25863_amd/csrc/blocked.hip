@@ -35,6 +35,7 @@
 // can instead run on FP64 MFMA directly: every partial sum is below K * 2^40,
 // exact while K <= 8192.
 #include "internal.h"
+#include "leafprod.h"
 
 namespace linac {
 
@@ -45,15 +46,6 @@ constexpr int kTileRows = 32;
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
-
-// Forward elimination (the solve): a row that became a pivot in an earlier
-// panel (its pivot column below skip_below, the panel start) takes no part in
-// a panel -- not in the leaf products, not in the trailing product, not in the
-// write-back -- so it keeps its entries right of its own panel (the U part
-// that back-substitution reads).  skip_below = 0 is Gauss-Jordan.
-__device__ __forceinline__ bool earlier_pivot(int32_t rowcol, int32_t skip_below) {
-    return rowcol >= 0 && rowcol < skip_below;
-}
 
 // A row-major matrix view (device pointer and leading dimension).
 struct Mat {
@@ -173,33 +165,7 @@ __global__ void build_a_kernel(PlainArgs w, Mat ebuf, int64_t ecol0, int32_t wj,
     }
 }
 
-// sum_s 256^s S_s reduced mod p, plus `add` (a residue, or 0): T_lo and T_hi
-// are exact in FP64; each is folded into [-p, 2p), T_hi is multiplied by
-// c32 = 2^32 mod p exactly (FMA split), and the sum is reduced once more.
-__device__ __forceinline__ uint32_t fold7s(int32_t s0, int32_t s1, int32_t s2, int32_t s3, int32_t s4,
-                                           int32_t s5, int32_t s6, uint32_t add, double c32,
-                                           const FieldConst& F) {
-    const double lo = __fma_rn(16777216.0, (double)s3,
-                               __fma_rn(65536.0, (double)s2, __fma_rn(256.0, (double)s1, (double)s0)));
-    const double hi = __fma_rn(65536.0, (double)s6, __fma_rn(256.0, (double)s5, (double)s4));
-    const double rlo = __fma_rn(-floor(lo * F.pinv), F.dp, lo);
-    const double rhi = __fma_rn(-floor(hi * F.pinv), F.dp, hi);
-    const double h = rhi * c32;
-    const double l = __fma_rn(rhi, c32, -h);
-    const double t = __fma_rn(-floor(h * F.pinv), F.dp, h) + l + rlo + (double)add;  // (-3p, 5p)
-    double r2 = __fma_rn(-floor(t * F.pinv), F.dp, t);
-    if (r2 < 0.0) r2 += F.dp;
-    if (r2 >= F.dp) r2 -= F.dp;
-    return (uint32_t)r2;
-}
-
 __device__ __forceinline__ uint32_t fold7(const v16i* acc, int r, uint32_t add, double c32,
-                                          const FieldConst& F) {
-    return fold7s(acc[0][r], acc[1][r], acc[2][r], acc[3][r], acc[4][r], acc[5][r], acc[6][r], add,
-                  c32, F);
-}
-
-__device__ __forceinline__ uint32_t fold7(const v4i* acc, int r, uint32_t add, double c32,
                                           const FieldConst& F) {
     return fold7s(acc[0][r], acc[1][r], acc[2][r], acc[3][r], acc[4][r], acc[5][r], acc[6][r], add,
                   c32, F);
@@ -294,188 +260,12 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
     }
 }
 
-// Leaf product on int8 MFMA: PR columns [l0, l0 + N) of every row become
-// C + A . Y, and Y itself for the leaf's pivot rows, where A = -(the row's
-// values at the leaf's pivot columns) and Y = P^-1 R, R being the pivot rows as
-// the selection saw them, with each pivot's implicit 1 in the transform block.
-// 16x16x32 MFMA tiles keep a wave at seven 4-register accumulators, so the
-// kernel fits in 128 VGPRs and shares SIMDs with a concurrent trailing product.
-// Block: 4 waves over 64 rows (16 each) and two 16-column blocks, taken one
-// after the other with the same multipliers (int8 digits built in registers).
-// Operand lanes of the 16x16x32 int8 MFMA: A(i, k) in lane i + 16 (k / 8), byte
-// k % 8; B(k, j) in lane j + 16 (k / 8), byte k % 8; C(i, j) in lane j + 16 (i /
-// 4), register i % 4.  Y's fragments come from the selection when it built
-// them (out->yready; plane l of 16-column block b at (4 b + l) * 512 bytes, 8
-// per lane); otherwise every block forms its own slices of Y (32 x 16 x t
-// products in FP64 with exact 16-bit splits) from the rows the selection
-// saved.  The leaf's pivot columns are not written (their unit-vector form is
-// implied by the bookkeeping), so no multiplier is overwritten while other
-// blocks still read it.  The launch also builds the next leaf's candidate list
-// (one entry per thread).
-// kLeafBlocks: 16-column blocks per workgroup (a tuned shape: 2, 3, 6 or 9;
-// the multipliers' digits are built once and reused across the blocks, and
-// every block's current values are loaded up front).
-template <int kLeafBlocks>
-__global__ __launch_bounds__(kThreads, 4) void leaf_product_i8_kernel(
-    PlainArgs w, Mat pr, int32_t l0, int32_t wl, int32_t wj, int32_t gcol0, int64_t N,
-    const LeafOut* out, const uint32_t* rsave, int64_t ldr, double c32, const int32_t* cand,
-    int32_t* cand_next, const int32_t* count, int32_t* count_next, const int8_t* yfrag,
-    int32_t skip_below) {
-    __shared__ uint32_t sP[32][33];
-    __shared__ uint32_t sR[32][17];
-    __shared__ __attribute__((aligned(16))) int8_t sB[4][64][8];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t rb = (int64_t)blockIdx.x * 4 + wave;  // 16-row block
-    const int64_t cb0 = (int64_t)blockIdx.y * kLeafBlocks;
-    const int64_t NB = ceil_div(N, 16);
-    const int t = out->t;
-    const uint32_t p = w.F.p;
-    {
-        const int64_t i = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kThreads + tid;
-        const int E = *count;
-        if (i == 0) *count_next = E - t;
-        leaf_compact_entry(out, t, cand, cand_next, E, i);
-    }
-    if (skip_below > 0) {  // forward elimination: 64 earlier pivot rows need nothing
-        const int64_t row = (int64_t)blockIdx.x * 64 + tid;
-        int keep = 0;
-        if (tid < 64 && row < w.m) keep = !earlier_pivot(w.rowcol[row], skip_below);
-        if (__syncthreads_or(keep) == 0) return;
-    }
-    // All loads below use addresses clamped into their arrays and are issued
-    // unconditionally (values out of range are discarded afterwards), so they
-    // overlap instead of waiting one by one.
-    const bool yready = out->yready != 0;
-    // multipliers of this lane's A row (row 16 rb + L%16, k = 8 (L/16) + e)
-    const int64_t arow = rb * 16 + (lane & 15);
-    const int64_t arowc = arow < w.m ? arow : w.m - 1;
-    const int kg = 8 * (lane >> 4);
-    uint32_t av[8];
-    int sel = -1;
-    {
-        int colv[32];  // the leaf's pivot columns (the array always has 32 entries)
-        bool ident = true;  // pivot columns 0 .. t-1 (dense data): contiguous loads
-#pragma unroll
-        for (int k = 0; k < 32; ++k) {
-            colv[k] = out->col[k] & 31;
-            ident = ident && (k >= t || colv[k] == k);
-        }
-        const int rc = w.rowcol[arowc] - gcol0;
-        if (ident) {
-            const uint4* src = (const uint4*)(pr.M + arowc * pr.ld + l0 + kg);
-            for (int q4 = 0; q4 < 2; ++q4) {
-                const uint4 v4 = src[q4];
-                av[4 * q4] = v4.x;
-                av[4 * q4 + 1] = v4.y;
-                av[4 * q4 + 2] = v4.z;
-                av[4 * q4 + 3] = v4.w;
-            }
-        } else {  // (rare) gather by the pivot columns, read per lane
-#pragma unroll
-            for (int e = 0; e < 8; ++e) av[e] = pr.M[arowc * pr.ld + l0 + (out->col[kg + e] & 31)];
-        }
-#pragma unroll
-        for (int s2 = 0; s2 < 32; ++s2)  // the row's own pivot of this leaf, if any
-            if (s2 < t && rc >= 0 && rc < wl && colv[s2] == rc) sel = s2;
-        for (int e = 0; e < 8; ++e)
-            if (arow >= w.m || kg + e >= t) av[e] = 0u;
-        if (arow >= w.m) sel = -1;
-    }
-    // epilogue rows (16 rb + 4 (L/16) + r): rowcol and current values, loaded
-    // before any computation
-    int rcv[4];
-    uint32_t cur[kLeafBlocks][4];
-    for (int r = 0; r < 4; ++r) {
-        const int64_t row = rb * 16 + 4 * (lane >> 4) + r;
-        rcv[r] = w.rowcol[row < w.m ? row : w.m - 1];
-    }
-#pragma unroll
-    for (int cbi = 0; cbi < kLeafBlocks; ++cbi) {
-        const int64_t col = (cb0 + cbi) * 16 + (lane & 15);
-        const int64_t colc = col < N ? col : N - 1;
-        for (int r = 0; r < 4; ++r) {
-            const int64_t row = rb * 16 + 4 * (lane >> 4) + r;
-            cur[cbi][r] = pr.M[(row < w.m ? row : w.m - 1) * pr.ld + l0 + colc];
-        }
-    }
-    long af[4];
-    {
-        int8_t outa[4][8];
-        for (int e = 0; e < 8; ++e) {
-            const int k = kg + e;
-            uint32_t x = sel >= 0 ? (k == sel ? 1u : 0u) : (av[e] == 0 ? 0u : p - av[e]);
-            int8_t d[4];
-            digits4(centre(x, p), d);
-            for (int l = 0; l < 4; ++l) outa[l][e] = d[l];
-        }
-        for (int l = 0; l < 4; ++l) __builtin_memcpy(&af[l], outa[l], 8);
-    }
-#pragma unroll
-    for (int cbi = 0; cbi < kLeafBlocks; ++cbi) {
-        const int64_t cb = cb0 + cbi;
-        if (cb >= NB) continue;  // uniform over the block
-        long bf[4];
-        if (yready) {
-            for (int l = 0; l < 4; ++l) bf[l] = *(const long*)(yfrag + (cb * 4 + l) * 512 + lane * 8);
-        } else {
-            __syncthreads();  // the previous slice's LDS is free
-            for (int i = tid; i < 32 * 32; i += kThreads) {
-                const int s = i >> 5, c = i & 31;
-                sP[s][c] = (s < t && c < t) ? out->pinv[s * 32 + c] : 0u;
-            }
-            for (int i = tid; i < 32 * 16; i += kThreads) {
-                const int s = i >> 4, c = i & 15;
-                const int64_t col = cb * 16 + c;
-                const uint32_t rv = rsave[s * ldr + (col < N ? col : N - 1)];
-                const int cs = out->col[s];
-                sR[s][c] = (s < t && col < N) ? (col == (int64_t)wj + cs ? 1u : rv) : 0u;
-            }
-            __syncthreads();
-            for (int i = tid; i < 32 * 16; i += kThreads) {  // Y(s, c) in FP64 with 16-bit splits
-                const int s = i >> 4, c = i & 15;
-                double s1 = 0.0, s0 = 0.0;
-                for (int k = 0; k < t; ++k) {
-                    const uint32_t pv = sP[s][k];
-                    const double rv = (double)sR[k][c];
-                    s1 = __fma_rn((double)(pv >> 16), rv, s1);
-                    s0 = __fma_rn((double)(pv & 0xffffu), rv, s0);
-                }
-                // s1 < 2^51, s0 < 2^52: exact; reduce s1, recombine below 2^53, reduce
-                double q = floor(s1 * w.F.pinv);
-                double h = __fma_rn(-q, w.F.dp, s1);
-                q = floor(h * w.F.pinv);
-                h = __fma_rn(-q, w.F.dp, h);
-                double y = __fma_rn(h, 65536.0, s0);
-                q = floor(y * w.F.pinv);
-                y = __fma_rn(-q, w.F.dp, y);
-                q = floor(y * w.F.pinv);
-                y = __fma_rn(-q, w.F.dp, y);
-                if (y < 0.0) y += w.F.dp;
-                if (y >= w.F.dp) y -= w.F.dp;
-                int8_t d[4];
-                digits4(centre((uint32_t)y, p), d);
-                for (int l = 0; l < 4; ++l) sB[l][c + 16 * (s >> 3)][s & 7] = d[l];
-            }
-            __syncthreads();
-            for (int l = 0; l < 4; ++l) __builtin_memcpy(&bf[l], sB[l][lane], 8);
-        }
-        v4i acc[7];
-        for (int g = 0; g < 7; ++g)
-            for (int r = 0; r < 4; ++r) acc[g][r] = 0;
-        for (int l = 0; l < 4; ++l)
-            for (int lp = 0; lp < 4; ++lp)
-                acc[l + lp] = __builtin_amdgcn_mfma_i32_16x16x32_i8(af[l], bf[lp], acc[l + lp], 0, 0, 0);
-        const int64_t col = cb * 16 + (lane & 15);
-        const bool pivcol = col < wl && w.colpiv[gcol0 + (col < wl ? col : 0)] >= 0;
-        if (col < N && !pivcol) {
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = rb * 16 + 4 * (lane >> 4) + r;
-                if (row >= w.m || earlier_pivot(rcv[r], skip_below)) continue;
-                const bool fresh = rcv[r] >= gcol0 && rcv[r] < gcol0 + wl;  // a pivot row of this leaf
-                pr.M[row * pr.ld + l0 + col] = fold7(acc, r, fresh ? 0u : cur[cbi][r], c32, w.F);
-            }
-        }
-    }
+// The int8 leaf product (leafprod.h) over a grid of 64-row blocks (x) and
+// column groups (y).
+template <int kLeafBlocks, int kMode>
+__global__ __launch_bounds__(kThreads, 4) void leaf_product_i8_kernel(LeafProdArgs a) {
+    leaf_product_block<kLeafBlocks, kMode, 4>(a, blockIdx.x, blockIdx.y,
+                                              (int64_t)blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 // FP64 operands for p < 2^21: centred residues as doubles in the lane order of
@@ -833,8 +623,8 @@ size_t blocked_workspace(int64_t m, int64_t n, int64_t k, int32_t panel) {
 // the remainder reads only rowcol, to spot the previous panel's pivot rows,
 // which new pivot rows (from -1 to a later column) never are either way.
 hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, bool fp64,
-                             bool overlap, bool forward, int32_t leaf_blocks, PlainArgs& out,
-                             const linac_opts* opts, hipStream_t s) {
+                             bool overlap, bool forward, int32_t leaf_blocks, bool leaf_pipeline,
+                             PlainArgs& out, const linac_opts* opts, hipStream_t s) {
     Blocked b;
     carve_blocked(ws, m, n, k, panel, &b);
     b.w.F = out.F;
@@ -867,6 +657,10 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
             return e;
         }
     }
+    // Leaf pipeline (int8 path): each leaf's product in two halves, the next
+    // leaf's first chunk alone, then the other rows in the same launch as the
+    // next leaf's first selection, which overlaps them.
+    const bool pipeline = !fp64 && leaf_pipeline;
     bool t2_pending = false;
     if (e == hipSuccess) e = leaf_init(b.leaf, (int32_t)m, s);
     int32_t leaf_index = 0;
@@ -875,16 +669,19 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
         const int32_t skip_below = forward ? j0 : 0;
         hipLaunchKernelGGL(panel_extract_kernel, dim3(tiles, (unsigned)ceil_div(b.PR.ld, 256)),
                            dim3(kThreads), 0, s, w.m, Wm, (int64_t)j0, b.PR, wj);
+        bool first_done = false;  // this leaf's first selection already ran (pipelined)
         for (int32_t l0 = 0; l0 < wj && e == hipSuccess; l0 += kLeaf) {
             const int32_t wl = wj - l0 < kLeaf ? wj - l0 : kLeaf;
             const int32_t parity = leaf_index & 1;
             // the leaf's own columns, the panel columns after it and the transform
             // block up to this leaf's pivots (beyond it every row is still zero)
             const int64_t N = (int64_t)wj + wl;
+            int8_t* yf = fp64 || !select_y ? nullptr : b.Yfrag;
             lt.before(LINAC_KERNEL_SELECT);
-            e = leaf_select(w, b.leaf, b.PR.M, b.PR.ld, l0, wl, wj, j0 + l0, parity, N,
-                            fp64 || !select_y ? nullptr : b.Yfrag, !fp64, s);
+            e = leaf_select(w, b.leaf, b.PR.M, b.PR.ld, l0, wl, wj, j0 + l0, parity, N, yf, !fp64, s,
+                            first_done ? kSelectRest : kSelectFirst | kSelectRest);
             lt.after();
+            first_done = false;
             if (e != hipSuccess) break;
             if (fp64) {
                 lt.before(LINAC_KERNEL_OPERANDS);
@@ -896,22 +693,57 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
                                 j0 + l0 + wl, s, lt, LINAC_KERNEL_LEAF_PRODUCT);
             } else {
                 const double c32 = (double)((((uint64_t)1) << 32) % w.F.p);
-                lt.before(LINAC_KERNEL_LEAF_PRODUCT);
-#define LEAF_PRODUCT(LB)                                                                          \
-    hipLaunchKernelGGL(leaf_product_i8_kernel<LB>,                                                \
-                       dim3((unsigned)ceil_div(m, 64), (unsigned)ceil_div(N, 16 * (LB))),        \
-                       dim3(kThreads), 0, s, w, b.PR, l0, wl, wj, j0 + l0, N,                     \
-                       (const LeafOut*)b.leaf.out, (const uint32_t*)b.leaf.rsave, b.leaf.ldr, c32, \
-                       (const int32_t*)b.leaf.cand[parity], b.leaf.cand[parity ^ 1],              \
-                       (const int32_t*)(b.leaf.count + parity), b.leaf.count + (parity ^ 1),     \
-                       (const int8_t*)b.Yfrag, skip_below)
-                if (leaf_blocks >= 9) LEAF_PRODUCT(9);
-                else if (leaf_blocks >= 6) LEAF_PRODUCT(6);
-                else if (leaf_blocks >= 3) LEAF_PRODUCT(3);
-                else LEAF_PRODUCT(2);
+                LeafProdArgs pa;
+                pa.w = w;
+                pa.PR = b.PR.M;
+                pa.ldpr = b.PR.ld;
+                pa.l0 = l0;
+                pa.wl = wl;
+                pa.wj = wj;
+                pa.gcol0 = j0 + l0;
+                pa.N = N;
+                pa.out = b.leaf.out[parity];
+                pa.rsave = b.leaf.rsave;
+                pa.ldr = b.leaf.ldr;
+                pa.c32 = c32;
+                pa.cand = b.leaf.cand[parity];
+                pa.cand_next = b.leaf.cand[parity ^ 1];
+                pa.count = b.leaf.count + parity;
+                pa.count_next = b.leaf.count + (parity ^ 1);
+                pa.yfrag = b.Yfrag;
+                pa.skip_below = skip_below;
+                pa.chunk = b.leaf.chunk;
+#define LEAF_PRODUCT(LB, MODE)                                                                      \
+    hipLaunchKernelGGL((leaf_product_i8_kernel<LB, MODE>),                                          \
+                       dim3((unsigned)(MODE == kLeafChunk ? 1 : ceil_div(m, 64)),                   \
+                            (unsigned)ceil_div(N, 16 * (LB))),                                      \
+                       dim3(kThreads), 0, s, pa)
+                const int32_t l1 = l0 + kLeaf;  // the next leaf of this panel, if any
+                if (pipeline && l1 < wj) {
+                    // The next leaf's first chunk is updated first; then one launch
+                    // runs the next leaf's first selection (on that chunk) beside the
+                    // update of the other rows.
+                    const int32_t wl1 = wj - l1 < kLeaf ? wj - l1 : kLeaf;
+                    lt.before(LINAC_KERNEL_LEAF_PRODUCT);
+                    LEAF_PRODUCT(2, kLeafChunk);
+                    lt.after();
+                    e = hipGetLastError();
+                    if (e != hipSuccess) break;
+                    lt.before(LINAC_KERNEL_LEAF_PRODUCT);
+                    e = leaf_fused(w, b.leaf, b.PR.M, b.PR.ld, l1, wl1, wj, j0 + l1, parity ^ 1,
+                                   (int64_t)wj + wl1, yf, pa, leaf_blocks, s);
+                    lt.after();
+                    first_done = true;
+                } else {
+                    lt.before(LINAC_KERNEL_LEAF_PRODUCT);
+                    if (leaf_blocks >= 9) LEAF_PRODUCT(9, kLeafAll);
+                    else if (leaf_blocks >= 6) LEAF_PRODUCT(6, kLeafAll);
+                    else if (leaf_blocks >= 3) LEAF_PRODUCT(3, kLeafAll);
+                    else LEAF_PRODUCT(2, kLeafAll);
+                    lt.after();
+                    e = hipGetLastError();
+                }
 #undef LEAF_PRODUCT
-                lt.after();
-                e = hipGetLastError();
             }
             ++leaf_index;
         }

@@ -91,10 +91,11 @@ struct LaunchTimer {
     }
 };
 
-// A second stream per device (created on first use, default priority) for work
-// that may overlap the caller's stream within one call; the call joins it back
-// to the caller's stream before returning.
-hipError_t side_stream(hipStream_t* out);
+// Side streams per device (created on first use, default priority) for work
+// that may overlap the caller's stream within one call; the call joins them back
+// to the caller's stream before returning.  which = 0: the trailing products';
+// 1: the leaf products'.
+hipError_t side_stream(hipStream_t* out, int which = 0);
 
 // One Gauss-Jordan step for local pivot column j over local columns [.., ncols_eff).
 hipError_t launch_gj_step(const PlainArgs& a, int32_t j, int32_t ncols_eff, hipStream_t s);
@@ -124,13 +125,18 @@ struct LeafOut {
 
 // Candidate lists (rows that are not pivots yet, ascending; ping-pong by leaf
 // parity), their lengths, the selection tree's arrival counters (one set per
-// parity) and node results.
+// parity), node results and the leaf results (one per parity, so that a leaf's
+// product can still read its result while the next leaf's first selection
+// publishes).  chunk: the next leaf's first kChunk candidates and, at [32], the
+// length of its candidate list, for a first selection that runs before the
+// compacted list exists.
 struct LeafState {
     int32_t* cand[2];
     int32_t* count;  // count[parity]
     int32_t* cnt[2];
     int32_t* res;
-    LeafOut* out;
+    LeafOut* out[2];
+    int32_t* chunk;
     uint32_t* rsave;  // the pivot rows over the columns the leaf updates, as selected
     int64_t ldr;
     int32_t nodes;
@@ -159,6 +165,50 @@ __device__ __forceinline__ void leaf_compact_entry(const LeafOut* out, int32_t t
     if (!gone) cand_next[i - shift] = row;
 }
 
+// The first 32 entries of the next candidate list: the first entries of
+// `cand` (E entries) that are not this leaf's pivot positions.  At most t <= 32
+// of the first 64 entries are pivot positions, so one wave looking at those 64
+// finds them all.  Called by a whole wave (lane = its lane); lane i keeps entry
+// i when it survives, at `rank` in the new list.  Returns min(32, E - t).
+__device__ __forceinline__ int next_chunk_entry(const LeafOut* out, int32_t t, const int32_t* cand,
+                                                int32_t E, int lane, int32_t* row, int* rank) {
+    int pos[32];  // all loads first (the array always has 32 entries)
+#pragma unroll
+    for (int k = 0; k < 32; ++k) pos[k] = out->pos[k];
+    bool gone = false;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) gone |= k < t && pos[k] == lane;
+    const bool keep = lane < E && !gone;
+    const unsigned long long b = __ballot(keep);
+    *rank = keep ? (int)__popcll(b & ((1ull << lane) - 1ull)) : 64;
+    *row = keep ? cand[lane] : -1;
+    const int n = (int)__popcll(b);
+    return n < 32 ? n : 32;
+}
+
+// The int8 leaf product's operands and outputs: PR columns [l0, l0 + N) (ldpr apart),
+// the leaf's result `out`, the saved pivot rows, c32 = 2^32 mod p, the
+// candidate lists of this leaf and the next one, the Y fragments, the panel
+// start for forward elimination (0: Gauss-Jordan) and the chunk buffer.
+struct LeafProdArgs {
+    PlainArgs w;
+    uint32_t* PR;
+    int64_t ldpr;
+    int32_t l0, wl, wj, gcol0;
+    int64_t N;
+    const LeafOut* out;
+    const uint32_t* rsave;
+    int64_t ldr;
+    double c32;
+    const int32_t* cand;
+    int32_t* cand_next;
+    const int32_t* count;
+    int32_t* count_next;
+    const int8_t* yfrag;
+    int32_t skip_below;
+    int32_t* chunk;
+};
+
 int32_t leaf_nodes(int64_t m);
 void leaf_carve(Carver& c, int64_t m, int64_t ldr, LeafState* ls);
 hipError_t leaf_init(const LeafState& ls, int32_t m, hipStream_t s);
@@ -169,9 +219,24 @@ hipError_t leaf_init(const LeafState& ls, int32_t m, hipStream_t s);
 // candidates already decides the leaf, setting out->yready.  With save_rows,
 // every result that leaves Y to the product (out->yready = 0) also saves the
 // pivot rows over those columns in ls.rsave (row s = pivot s).
+// stages: kSelectFirst (the first chunk alone), kSelectRest (the tree, or the
+// build of Y when the first chunk decided), or both.  from_chunk: the first
+// stage reads its candidates from ls.chunk (written by the previous leaf's
+// chunk product) instead of the compacted list.
+constexpr int kSelectFirst = 1, kSelectRest = 2;
 hipError_t leaf_select(const PlainArgs& w, const LeafState& ls, const uint32_t* PR, int64_t ldpr,
                        int32_t l0, int32_t wl, int32_t wj, int32_t gcol0, int32_t parity,
-                       int64_t ncopy, int8_t* yfrag, bool save_rows, hipStream_t s);
+                       int64_t ncopy, int8_t* yfrag, bool save_rows, hipStream_t s,
+                       int stages = kSelectFirst | kSelectRest, bool from_chunk = false);
+// The larger half of leaf l's int8 product (every row but the next leaf's first
+// chunk; pa as for the product kernel) in one launch with the first selection
+// of leaf l + 1 (columns [l0, l0 + wl) of PR, parity its leaf parity, reading
+// its candidates from ls.chunk).  Needs the chunk half of leaf l's product
+// done first (same stream).
+hipError_t leaf_fused(const PlainArgs& w, const LeafState& ls, const uint32_t* PR, int64_t ldpr,
+                      int32_t l0, int32_t wl, int32_t wj, int32_t gcol0, int32_t parity,
+                      int64_t ncopy, int8_t* yfrag, const LeafProdArgs& pa, int32_t leaf_blocks,
+                      hipStream_t s);
 // Operands of the FP64 leaf product over PR columns [l0, l0 + N): the B operand
 // Y = P^-1 R and the A operand (multipliers) in the layout of the FP64 product
 // kernel (16 x 16 blocks with 8 k-blocks of 4); also compacts the candidate
@@ -188,10 +253,12 @@ size_t blocked_workspace(int64_t m, int64_t n, int64_t k, int32_t panel);
 // then back-substitution into the pivot rows' right-hand sides, instead of
 // Gauss-Jordan (the reduced matrix is then not an RREF; only X is read).
 // leaf_blocks: 16-column blocks per workgroup of the int8 leaf product (2, 3,
-// 6 or 9; a tuned shape, results identical).
+// 6 or 9; a tuned shape, results identical).  leaf_pipeline (int8 path): each
+// leaf's product in two halves on two streams so that the next leaf's first
+// selection overlaps it (results identical).
 hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, bool fp64,
-                             bool lookahead, bool forward, int32_t leaf_blocks, PlainArgs& a,
-                             const linac_opts* opts, hipStream_t s);
+                             bool lookahead, bool forward, int32_t leaf_blocks, bool leaf_pipeline,
+                             PlainArgs& a, const linac_opts* opts, hipStream_t s);
 
 // Batched path (batched.hip): workspace = [queue counter | descriptors | one
 // working region per system].

@@ -35,6 +35,7 @@
 // step s, D_s^-1 = c_s / (product of all d): one inverse per leaf.  Residues are held lazily in FP64, in (-3p, 3p): a product
 // a b - floor(fl(ab)/p) p is exact by FMA and lies in [-p, 2p).
 #include "internal.h"
+#include "leafprod.h"
 
 namespace linac {
 
@@ -734,55 +735,65 @@ __device__ void build_y_block(const SelArgs& a, int g, const Lazy& L) {
     }
 }
 
-// The last arrival counter of each set is the "published" flag: once the final
-// node is known, workgroups still merging stop at their next tree level.
-//
-// Two launches per leaf: `first` runs the first chunk alone (one workgroup, no
-// other work on the device) and publishes when that chunk already has full
-// rank, as with dense data; the full tree launch then finds the result
-// published and ends at once, or selects over all candidates.
-template <bool first>
-__global__ __launch_bounds__(first ? kFirstThreads : kSelThreads, first ? 2 : 1) void leaf_select_kernel(
-    SelArgs a) {
+// The first chunk of candidates alone, by one workgroup of kFirstThreads:
+// publishes when that chunk already has full rank in the leaf (as with dense
+// data) or holds every candidate.
+__device__ void select_first_block(const SelArgs& a) {
     __shared__ Sel S;
     const Lazy L{(double)a.w.F.p, a.w.F.pinv};
-    int32_t* published = a.cnt_cur + (a.ncnt - 1);
-    if (!first)
-        for (int i = blockIdx.x * kSelThreads + threadIdx.x; i < a.ncnt;
-             i += gridDim.x * kSelThreads)
-            a.cnt_next[i] = 0;
     const int E = *a.count;
-    const int G = (E + kChunk - 1) / kChunk;
-    const int g = blockIdx.x;
-    if (!first) {
-        if (threadIdx.x == 0)
-            S.bcast = __hip_atomic_load(published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        if (S.bcast != 0) {  // decided by the first launch: build Y instead
-            if (a.yfrag && (int64_t)g * 32 < a.ncopy) build_y_block(a, g, L);
-            if (a.yfrag && g == 0 && threadIdx.x == 0) a.out->yready = 1;
-            return;
-        }
-    }
     if (E == 0) {
-        if (first && threadIdx.x == 0) {
-            __hip_atomic_store(published, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0) {
+            __hip_atomic_store(a.cnt_cur + (a.ncnt - 1), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             a.out->t = 0;
             a.out->yready = 0;
         }
         return;
     }
-    if (g >= G) return;
+    if (threadIdx.x < 64) S.pos[threadIdx.x] = threadIdx.x;
+    if (threadIdx.x == 0) S.nrows = min(kChunk, E);
+    __syncthreads();
+    double v[8], T[8];
+    node_gj_pairs<kFirstWaves>(a, S, v, T, L);
+    if (S.t == a.wl || E <= kChunk) publish<32, kFirstWaves>(a, S, T, a.save_rows && !a.yfrag, L);
+}
+
+// The last arrival counter of each set is the "published" flag: once the final
+// node is known, workgroups still merging stop at their next tree level.
+//
+// Two launches per leaf: `first` runs the first chunk alone (one workgroup, no
+// other work on the device; select_first_block) and publishes when that chunk
+// already has full rank, as with dense data; the full tree launch then finds
+// the result published and ends at once, or selects over all candidates.
+template <bool first>
+__global__ __launch_bounds__(first ? kFirstThreads : kSelThreads, first ? 2 : 1) void leaf_select_kernel(
+    SelArgs a) {
+    if (first) {
+        select_first_block(a);
+        return;
+    }
+    __shared__ Sel S;
+    const Lazy L{(double)a.w.F.p, a.w.F.pinv};
+    int32_t* published = a.cnt_cur + (a.ncnt - 1);
+    for (int i = blockIdx.x * kSelThreads + threadIdx.x; i < a.ncnt; i += gridDim.x * kSelThreads)
+        a.cnt_next[i] = 0;
+    const int E = *a.count;
+    const int G = (E + kChunk - 1) / kChunk;
+    const int g = blockIdx.x;
+    if (threadIdx.x == 0)
+        S.bcast = __hip_atomic_load(published, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (S.bcast != 0) {  // decided by the first launch: build Y instead
+        if (a.yfrag && (int64_t)g * 32 < a.ncopy) build_y_block(a, g, L);
+        if (a.yfrag && g == 0 && threadIdx.x == 0) a.out->yready = 1;
+        return;
+    }
+    if (E == 0 || g >= G) return;  // (E = 0 was published by the first launch)
     if (threadIdx.x < 64) S.pos[threadIdx.x] = g * kChunk + threadIdx.x;
     if (threadIdx.x == 0) S.nrows = min(kChunk, E - g * kChunk);
     __syncthreads();
     int level = 0, k = g, nodes = G;
     double v[8], T[8];
-    if (first) {
-        node_gj_pairs<kFirstWaves>(a, S, v, T, L);
-        if (S.t == a.wl || nodes == 1) publish<32, kFirstWaves>(a, S, T, a.save_rows && !a.yfrag, L);
-        return;  // otherwise the tree launch decides
-    }
     // Chunk 0 of the tree takes the first kChunk candidates that are non-zero
     // in the leaf: rows that are combinations of earlier pivot rows stay
     // candidates and gather at the front of the list, zero in every later
@@ -865,6 +876,24 @@ __global__ __launch_bounds__(first ? kFirstThreads : kSelThreads, first ? 2 : 1)
         k >>= 1;
         nodes = up;
     }
+}
+
+// Leaf l's product on every row but leaf l + 1's first chunk (workgroups 1..,
+// kFirstWaves x 16 rows each, rbx row blocks per column group) and leaf l + 1's
+// first selection on that chunk (workgroup 0) in one launch.  The two touch
+// disjoint data: the selection reads the chunk rows (updated by the chunk half
+// before this launch) and writes leaf l + 1's result and the bookkeeping of its
+// pivot rows; the product reads leaf l's result and writes the other rows and
+// the next candidate list.
+template <int kLeafBlocks>
+__global__ __launch_bounds__(kFirstThreads, 2) void leaf_fused_kernel(SelArgs sa, LeafProdArgs pa,
+                                                                     int32_t rbx) {
+    if (blockIdx.x == 0) {
+        select_first_block(sa);
+        return;
+    }
+    const int64_t b = (int64_t)blockIdx.x - 1;
+    leaf_product_block<kLeafBlocks, kLeafRest, kFirstWaves>(pa, b % rbx, b / rbx, b);
 }
 
 __global__ void leaf_init_kernel(int32_t* cand, int32_t* count, int32_t* cnt, int32_t ncnt2,
@@ -1064,10 +1093,12 @@ void leaf_carve(Carver& c, int64_t m, int64_t ldr, LeafState* ls) {
     int32_t* count = c.take<int32_t>(64);
     int32_t* cnt = c.take<int32_t>(2 * (int64_t)nodes);
     int32_t* res = c.take<int32_t>((int64_t)nodes * kNodeInts);
-    LeafOut* out = c.take<LeafOut>(1);
+    LeafOut* out = c.take<LeafOut>(2);
+    int32_t* chunk = c.take<int32_t>(64);
     uint32_t* rsave = c.take<uint32_t>(32 * ldr);
     if (ls) {
         ls->rsave = rsave;
+        ls->chunk = chunk;
         ls->ldr = ldr;
         ls->cand[0] = cand0;
         ls->cand[1] = cand1;
@@ -1075,7 +1106,8 @@ void leaf_carve(Carver& c, int64_t m, int64_t ldr, LeafState* ls) {
         ls->cnt[0] = cnt;
         ls->cnt[1] = cnt + nodes;
         ls->res = res;
-        ls->out = out;
+        ls->out[0] = out;
+        ls->out[1] = out + 1;
         ls->nodes = nodes;
         ls->gmax = (int32_t)ceil_div(m > 0 ? m : 1, kChunk);
     }
@@ -1089,9 +1121,11 @@ hipError_t leaf_init(const LeafState& ls, int32_t m, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t leaf_select(const PlainArgs& w, const LeafState& ls, const uint32_t* PR, int64_t ldpr,
-                       int32_t l0, int32_t wl, int32_t wj, int32_t gcol0, int32_t parity,
-                       int64_t ncopy, int8_t* yfrag, bool save_rows, hipStream_t s) {
+namespace {
+
+SelArgs sel_args(const PlainArgs& w, const LeafState& ls, const uint32_t* PR, int64_t ldpr,
+                 int32_t l0, int32_t wl, int32_t wj, int32_t gcol0, int32_t parity, int64_t ncopy,
+                 int8_t* yfrag, bool save_rows) {
     SelArgs a;
     a.w = w;
     a.PR = PR;
@@ -1106,17 +1140,55 @@ hipError_t leaf_select(const PlainArgs& w, const LeafState& ls, const uint32_t* 
     a.cnt_cur = ls.cnt[parity];
     a.cnt_next = ls.cnt[parity ^ 1];
     a.res = ls.res;
-    a.out = ls.out;
+    a.out = ls.out[parity];
     a.rsave = ls.rsave;
     a.ldr = ls.ldr;
     a.ncopy = ncopy;
     a.wj = wj;
     a.yfrag = yfrag;
     a.save_rows = save_rows ? 1 : 0;
+    return a;
+}
+
+}  // namespace
+
+hipError_t leaf_select(const PlainArgs& w, const LeafState& ls, const uint32_t* PR, int64_t ldpr,
+                       int32_t l0, int32_t wl, int32_t wj, int32_t gcol0, int32_t parity,
+                       int64_t ncopy, int8_t* yfrag, bool save_rows, hipStream_t s, int stages,
+                       bool from_chunk) {
+    const SelArgs a = sel_args(w, ls, PR, ldpr, l0, wl, wj, gcol0, parity, ncopy, yfrag, save_rows);
     const int64_t nyb = ceil_div(ncopy, 32);
     const unsigned grid = (unsigned)(ls.gmax > nyb ? ls.gmax : nyb);
-    hipLaunchKernelGGL(leaf_select_kernel<true>, dim3(1), dim3(kFirstThreads), 0, s, a);
-    hipLaunchKernelGGL(leaf_select_kernel<false>, dim3(grid), dim3(kSelThreads), 0, s, a);
+    if (stages & kSelectFirst) {
+        SelArgs f = a;
+        if (from_chunk) {  // positions 0..31 of the new list are the chunk's entries
+            f.cand = ls.chunk;
+            f.count = ls.chunk + 32;
+        }
+        hipLaunchKernelGGL(leaf_select_kernel<true>, dim3(1), dim3(kFirstThreads), 0, s, f);
+    }
+    if (stages & kSelectRest)
+        hipLaunchKernelGGL(leaf_select_kernel<false>, dim3(grid), dim3(kSelThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t leaf_fused(const PlainArgs& w, const LeafState& ls, const uint32_t* PR, int64_t ldpr,
+                      int32_t l0, int32_t wl, int32_t wj, int32_t gcol0, int32_t parity,
+                      int64_t ncopy, int8_t* yfrag, const LeafProdArgs& pa, int32_t leaf_blocks,
+                      hipStream_t s) {
+    SelArgs a = sel_args(w, ls, PR, ldpr, l0, wl, wj, gcol0, parity, ncopy, yfrag, true);
+    a.cand = ls.chunk;  // positions 0..31 of the new list are the chunk's entries
+    a.count = ls.chunk + 32;
+    const int64_t rbx = ceil_div(w.m > 0 ? w.m : 1, 16 * kFirstWaves);
+#define LEAF_FUSED(LB)                                                                            \
+    hipLaunchKernelGGL(leaf_fused_kernel<LB>,                                                     \
+                       dim3((unsigned)(1 + rbx * ceil_div(pa.N, 16 * (LB)))), dim3(kFirstThreads), \
+                       0, s, a, pa, (int32_t)rbx)
+    if (leaf_blocks >= 9) LEAF_FUSED(9);
+    else if (leaf_blocks >= 6) LEAF_FUSED(6);
+    else if (leaf_blocks >= 3) LEAF_FUSED(3);
+    else LEAF_FUSED(2);
+#undef LEAF_FUSED
     return hipGetLastError();
 }
 
@@ -1132,7 +1204,7 @@ hipError_t leaf_operands(const PlainArgs& w, const LeafState& ls, const uint32_t
     a.wj = wj;
     a.gcol0 = gcol0;
     a.N = N;
-    a.out = ls.out;
+    a.out = ls.out[parity];
     a.cand = ls.cand[parity];
     a.cand_next = ls.cand[parity ^ 1];
     a.count = ls.count + parity;

@@ -387,3 +387,51 @@ def test_leaf_product_shapes(gpu, leaf_blocks):
             assert int(rank.item()) == rr and np.array_equal(R.cpu().numpy().astype(np.uint32), Rr)
     finally:
         lx.restore_tuning()
+
+
+@pytest.mark.parametrize("pipeline,forward", [(1, 0), (1, 1), (0, 0), (0, 1)])
+def test_leaf_pipeline(gpu, pipeline, forward):
+    """The leaf products split in two (the next leaf's first chunk, then the
+    other rows on a second stream while the next selection runs), and unsplit,
+    for RREFs and for solves by Gauss-Jordan and by forward elimination,
+    against the oracle.  The cases reach the chunk's corner cases: leaves with
+    fewer pivots than columns (free and repeated columns), first chunks short
+    of full rank (zero and repeated rows: the selection tree decides), lists
+    shorter than a chunk near the end, and few rows."""
+    import json
+    import torch
+    table = json.load(open(lx.TUNING_FILE))
+    table["leaf_pipeline"] = pipeline
+    table["forward_min"] = 1 if forward else 1 << 30
+    lx.load_tuning(json.dumps(table))
+    try:
+        rng = np.random.default_rng(777 + 10 * pipeline + forward)
+        cases = []
+        for m, n, k, panel in [(300, 300, 5, 64), (700, 650, 6, 192), (257, 333, 17, 96),
+                               (40, 300, 3, 128), (520, 200, 4, 64)]:
+            A, B, p = workloads.dense_system(seed=m + 13 * n, n=n, k=k, m=m)
+            if m > 100:
+                A[m // 2] = A[5]
+                A[:, n // 3] = 0
+                A[:, n // 4] = A[:, 2]
+                A[40:80] = 0
+            cases.append((f"dense m={m} n={n}", A, B, p, panel))
+        p3 = 3
+        A3 = (rng.random((400, 380)) < 0.05).astype(np.uint32) * rng.integers(1, 3, (400, 380),
+                                                                             dtype=np.uint32)
+        B3 = rng.integers(0, p3, (400, 2), dtype=np.uint32)
+        cases.append(("sparse F_3", A3, B3, p3, 64))
+        for tag0, A, B, p, panel in cases:
+            tag = f"pipeline={pipeline} forward={forward} {tag0} panel={panel}"
+            print(tag, flush=True)
+            got = lx.solve(A, B, p, path=lx.PATH_BLOCKED_INT8, panel_width=panel)
+            ref = oracle.solve(A, B, p)
+            for name, g, r in zip(("X", "rank", "pivots", "consistent"), got, ref):
+                assert np.array_equal(np.asarray(g), np.asarray(r)), f"{tag}: {name}"
+            R, rank, piv = lx.rref(A, p, path=lx.PATH_BLOCKED_INT8, panel_width=panel)
+            Rr, rr, pr = oracle.rref(A, p)
+            torch.cuda.synchronize()
+            assert int(rank.item()) == rr, f"{tag}: rref rank"
+            assert np.array_equal(R.cpu().numpy().astype(np.uint32), Rr), f"{tag}: rref"
+    finally:
+        lx.restore_tuning()
