@@ -24,12 +24,11 @@
  *   - Calls are asynchronous on the HIP stream `s` (NULL = the null stream);
  *     outputs are valid once the stream has been synchronised.  Calls on
  *     distinct streams with distinct workspaces may run concurrently and give
- *     the same results.  Library-internal resources shared per device: the
- *     blocked int8 path overlaps a panel's trailing update with the next panel
- *     on one side stream per device, and each leaf's product with the next
- *     leaf's pivot selection on a second one, so those parts of concurrent
- *     blocked calls on one device queue behind each other there; and
- *     linac_rref_batched calls on one device take turns on its lanes.
+ *     the same results.  Two library-internal resources are shared per
+ *     device: the blocked int8 path overlaps a panel's trailing update with
+ *     the next panel on one side stream per device, so the trailing parts of
+ *     concurrent blocked calls on one device queue behind each other there;
+ *     and linac_rref_batched calls on one device take turns on its lanes.
  *   - Errors are returned, never thrown.  All argument checks run on the host
  *     before any device work, so a non-OK return from a check leaves every
  *     buffer untouched.  On LINAC_E_HIP the outputs are unspecified and
@@ -383,8 +382,7 @@ linac_status linac_lup_u64(uint64_t* A, int64_t m, int64_t n, int64_t lda, uint6
  *                     int8 path's leaf product (a tile shape);
  *   "leaf_pipeline":  1 (default) or 0: whether the blocked int8 path splits each
  *                     leaf's product so that the next leaf's first pivot
- *                     selection overlaps it (on a second side stream that the
- *                     call joins back to s).
+ *                     selection runs in the same launch as its larger half.
  * Unknown keys are ignored.  Returns LINAC_E_INVALID_ARG (and keeps the current
  * table) for malformed text or out-of-range values.  Host only. */
 linac_status linac_load_tuning(const char* json);

@@ -19,24 +19,22 @@
 
 using namespace linac;
 
-hipError_t linac::side_stream(hipStream_t* out, int which) {
+hipError_t linac::side_stream(hipStream_t* out) {
     static std::mutex mu;
-    static std::vector<hipStream_t> streams;  // two per device
-    if (which != 0 && which != 1) return hipErrorInvalidValue;
+    static std::vector<hipStream_t> streams;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     std::lock_guard<std::mutex> lock(mu);
-    const size_t slot = 2 * (size_t)dev + (size_t)which;
-    if (streams.size() <= slot) streams.resize(2 * (size_t)dev + 2, nullptr);
-    if (!streams[slot]) {
-        e = hipStreamCreateWithFlags(&streams[slot], hipStreamNonBlocking);
+    if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
+    if (!streams[dev]) {
+        e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking);
         if (e != hipSuccess) {
-            streams[slot] = nullptr;
+            streams[dev] = nullptr;
             return e;
         }
     }
-    *out = streams[slot];
+    *out = streams[dev];
     return hipSuccess;
 }
 
@@ -346,7 +344,7 @@ hipError_t run_path(int path, void* ws, int64_t m, int64_t n, int64_t k, PlainAr
     forward = forward && (m < n ? m : n) >= t.forward_min;
     return blocked_eliminate(ws, m, n, k, panel_width(opts, m, n), path == LINAC_PATH_BLOCKED_FP64,
                              allow_overlap && t.lookahead != 0, forward, t.leaf_blocks,
-                             allow_overlap && t.leaf_pipeline != 0, a, opts, s);
+                             t.leaf_pipeline != 0, a, opts, s);
 }
 
 bool size_ok(int64_t m, int64_t n, int64_t k) {

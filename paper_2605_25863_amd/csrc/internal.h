@@ -91,11 +91,10 @@ struct LaunchTimer {
     }
 };
 
-// Side streams per device (created on first use, default priority) for work
-// that may overlap the caller's stream within one call; the call joins them back
-// to the caller's stream before returning.  which = 0: the trailing products';
-// 1: the leaf products'.
-hipError_t side_stream(hipStream_t* out, int which = 0);
+// A second stream per device (created on first use, default priority) for work
+// that may overlap the caller's stream within one call; the call joins it back
+// to the caller's stream before returning.
+hipError_t side_stream(hipStream_t* out);
 
 // One Gauss-Jordan step for local pivot column j over local columns [.., ncols_eff).
 hipError_t launch_gj_step(const PlainArgs& a, int32_t j, int32_t ncols_eff, hipStream_t s);
@@ -254,8 +253,8 @@ size_t blocked_workspace(int64_t m, int64_t n, int64_t k, int32_t panel);
 // Gauss-Jordan (the reduced matrix is then not an RREF; only X is read).
 // leaf_blocks: 16-column blocks per workgroup of the int8 leaf product (2, 3,
 // 6 or 9; a tuned shape, results identical).  leaf_pipeline (int8 path): each
-// leaf's product in two halves on two streams so that the next leaf's first
-// selection overlaps it (results identical).
+// leaf's product in two launches, the larger half beside the next leaf's first
+// selection (results identical).
 hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, bool fp64,
                              bool lookahead, bool forward, int32_t leaf_blocks, bool leaf_pipeline,
                              PlainArgs& a, const linac_opts* opts, hipStream_t s);
