@@ -177,9 +177,11 @@ struct Sel {
     int32_t pos[64];              // list positions of this node's rows (lane order)
     int32_t basis[32];            // list positions of the node's basis rows (pivot order)
     int32_t rows[32];             // their row ids (final node)
+    int32_t rowid[64];            // row id of each of the node's rows (lane order)
     int32_t sidx[64];             // lane -> pivot index, -1
     int32_t pl[32];               // pivot index -> lane
     int32_t pc[32];               // pivot index -> leaf column
+    int32_t cpv[32];              // leaf column -> pivot index, -1 (in-place elimination)
     double total;                 // product of all pivot values
     int32_t nrows;
     int32_t t;
@@ -221,6 +223,7 @@ __device__ __forceinline__ void node_gj(const SelArgs& a, Sel& S, double v[8], d
     const int r = R == 32 ? lane & 31 : lane;  // this lane's row within the node
     const int nrows = S.nrows;
     const int32_t row = r < nrows ? a.cand[S.pos[r]] : -1;
+    if (threadIdx.x < R) S.rowid[r] = row;
 #pragma unroll
     for (int k = 0; k < Y::kRegs; ++k) {
         const int c = Y::col(wave, h, k);
@@ -314,7 +317,10 @@ __device__ __forceinline__ void node_gj(const SelArgs& a, Sel& S, double v[8], d
         S.total = cprod;
     }
     __syncthreads();
-    if (threadIdx.x < t) S.basis[threadIdx.x] = S.pos[S.pl[threadIdx.x]];
+    if (threadIdx.x < t) {
+        S.basis[threadIdx.x] = S.pos[S.pl[threadIdx.x]];
+        S.rows[threadIdx.x] = S.rowid[S.pl[threadIdx.x]];
+    }
     __syncthreads();
 }
 
@@ -391,6 +397,7 @@ __device__ __forceinline__ void node_gj_pairs(const SelArgs& a, Sel& S, double v
     const int h = lane >> 5, r = lane & 31;
     const int nrows = S.nrows;
     const int32_t row = r < nrows ? a.cand[S.pos[r]] : -1;
+    if (threadIdx.x < 32) S.rowid[r] = row;
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
         const int c = pair_col<W>(k, h, wave);
@@ -575,7 +582,135 @@ __device__ __forceinline__ void node_gj_pairs(const SelArgs& a, Sel& S, double v
         S.total = cprod;
     }
     __syncthreads();
-    if (threadIdx.x < t) S.basis[threadIdx.x] = S.pos[S.pl[threadIdx.x]];
+    if (threadIdx.x < t) {
+        S.basis[threadIdx.x] = S.pos[S.pl[threadIdx.x]];
+        S.rows[threadIdx.x] = S.rowid[S.pl[threadIdx.x]];
+    }
+    __syncthreads();
+}
+
+// The first launch's elimination (eight waves, 32 rows), in place: the slot of
+// a leaf column holds that column until it becomes the pivot column of pivot
+// s, and from then on column s of the transform T (the in-place form of
+// Gauss-Jordan inversion).  Every slot is then live at every step, so a lane
+// updates two slots per pivot instead of two leaf and two transform registers.
+// Lane = 32 h + row; wave v holds pair 8 h + v, columns 16 h + 2 v and
+// 16 h + 2 v + 1, in x[0] and x[1] (the pair layout of node_gj_pairs<8>).  A
+// pivot (row q, value d, column j, column values f) maps every slot of every
+// row but q to d x - f x_q, and slot j to cprod on row q and -f cprod
+// elsewhere (the new pivot's transform column).  Slots of free columns hold
+// values that nothing reads.  Same pivots, P^-1 and results as node_gj_pairs.
+__device__ __forceinline__ void node_gj_inplace(const SelArgs& a, Sel& S, double x[2], const Lazy& L) {
+    constexpr int W = 8;
+    const int lane = threadIdx.x & 63, wave = uniform(threadIdx.x >> 6);
+    const int h = lane >> 5, r = lane & 31;
+    const int c0 = 16 * h + 2 * wave;  // this lane's columns: c0, c0 + 1
+    const int nrows = S.nrows;
+    const int32_t row = r < nrows ? a.cand[S.pos[r]] : -1;
+    if (threadIdx.x < 32) S.rowid[r] = row;
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+        x[k] = (row >= 0 && c0 + k < a.wl) ? (double)a.PR[(int64_t)row * a.ldpr + a.l0 + c0 + k] : 0.0;
+    if (threadIdx.x < 64) S.sidx[threadIdx.x] = -1;
+    if (threadIdx.x < 32) S.cpv[threadIdx.x] = -1;
+    const unsigned long long valid = nrows >= 32 ? 0xffffffffull : ((1ull << nrows) - 1ull);
+    unsigned long long chosen = 0;  // rows of this node (bits 0..31)
+    int t = 0;
+    double cprod = 1.0;
+    auto first_nz = [&](double v, int hh, unsigned long long excl) {
+        const double av = fabs(v);  // lazy value in (-3p, 3p): zero iff |v| is 0, p or 2p
+        const unsigned long long nz = __ballot(!(av == 0.0 || av == L.p || av == 2.0 * L.p));
+        const unsigned long long m = ((nz >> (32 * hh)) & 0xffffffffull) & valid & ~excl;
+        const int mlo = uniform((int)(uint32_t)m);
+        return mlo != 0 ? __builtin_ctz((uint32_t)mlo) : -1;
+    };
+    const int npairs = (a.wl + 1) >> 1;
+    // owner of pair P (wave P % 8, half P / 8): both pivots of the pair, posted
+    auto detect = [&](int P) {
+        const int hp = P / W;
+        const double xa = x[0];
+        double xb = x[1];
+        const int q1 = first_nz(xa, hp, chosen);
+        const double d1 = q1 >= 0 ? readlane_d(xa, 32 * hp + q1) : 0.0;
+        if (q1 >= 0) {
+            const double ub = readlane_d(xb, 32 * hp + q1);
+            if (r != q1) xb = lz_ff(d1, xb, xa, ub, L);
+        }
+        int q2 = -1;
+        double d2 = 0.0;
+        if (2 * P + 1 < a.wl) {
+            q2 = first_nz(xb, hp, chosen | (q1 >= 0 ? 1ull << q1 : 0ull));
+            d2 = q2 >= 0 ? readlane_d(xb, 32 * hp + q2) : 0.0;
+        }
+        const int buf = P & 1;
+        if (h == hp) {
+            S.f[buf][r] = xa;
+            S.f2[buf][r] = xb;
+        }
+        if (lane == 0) {
+            S.q[buf] = q1;
+            S.d[buf] = d1;
+            S.q2[buf] = q2;
+            S.d2[buf] = d2;
+        }
+    };
+    // one pivot on both slots: d x - f x_q off the pivot row, the transform
+    // column's start in the pivot column's slot
+    auto apply = [&](int q, double d, double f, int j, double cp) {
+        const int bp = pair_bpaddr(q);
+        double u[2], y[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) u[k] = pair_row(x[k], bp);
+        lz_ff_n<0, 2>(y, d, x, f, u, L);
+        const double inj = r == q ? cp : -lz_mul(f, cp, L);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) x[k] = c0 + k == j ? inj : (r != q ? y[k] : x[k]);
+    };
+    __syncthreads();
+    if (wave == 0 && a.wl > 0) detect(0);
+    for (int P = 0; P < npairs; ++P) {
+        __syncthreads();  // pair P posted; every wave is done with pair P - 1's post
+        const int buf = P & 1;
+        const int q1v = S.q[buf], q2v = S.q2[buf];
+        const double f1 = S.f[buf][r], f2 = S.f2[buf][r];
+        const double d1 = S.d[buf], d2 = S.d2[buf];
+        const int q1 = uniform(q1v), q2 = uniform(q2v);
+        const int j = 2 * P;
+        const int s1 = t, s2 = t + (q1 >= 0);
+        const double cp2 = q1 >= 0 ? lz_mul(cprod, d1, L) : cprod;  // cprod after pivot 1
+        if (threadIdx.x == 0) {
+            if (q1 >= 0) {
+                S.pl[s1] = q1;
+                S.pc[s1] = j;
+                S.cpv[j] = s1;
+                S.sidx[q1] = s1;
+                S.cp[s1] = cprod;
+            }
+            if (q2 >= 0) {
+                S.pl[s2] = q2;
+                S.pc[s2] = j + 1;
+                S.cpv[j + 1] = s2;
+                S.sidx[q2] = s2;
+                S.cp[s2] = cp2;
+            }
+        }
+        if (q1 >= 0) apply(q1, d1, f1, j, cprod);
+        if (q2 >= 0) apply(q2, d2, f2, j + 1, cp2);
+        if (q1 >= 0) chosen |= 1ull << q1;
+        if (q2 >= 0) chosen |= 1ull << q2;
+        if (P + 1 < npairs && wave == (P + 1) % W) detect(P + 1);
+        cprod = q2 >= 0 ? lz_mul(cp2, d2, L) : cp2;
+        t = s2 + (q2 >= 0);
+    }
+    if (threadIdx.x == 0) {
+        S.t = t;
+        S.total = cprod;
+    }
+    __syncthreads();
+    if (threadIdx.x < t) {
+        S.basis[threadIdx.x] = S.pos[S.pl[threadIdx.x]];
+        S.rows[threadIdx.x] = S.rowid[S.pl[threadIdx.x]];
+    }
     __syncthreads();
 }
 
@@ -618,9 +753,12 @@ __device__ void pick_nonzero_rows(const SelArgs& a, Sel& S, int E) {
 // Final node: P^-1, the leaf result, the pivot bookkeeping, and a copy of the
 // pivot rows over the columns the leaf updates (the product overwrites them).
 // R = 32: the pair layout of node_gj_pairs; R = 64: the layout of node_gj<64>.
-template <int R, int W>
+// kInPlace: T comes from node_gj_inplace (slot of leaf column c = transform
+// column S.cpv[c]).
+template <int R, int W, bool kInPlace = false>
 __device__ __forceinline__ void publish(const SelArgs& a, Sel& S, const double T[8], bool save_rows,
                                         const Lazy& L) {
+    static_assert(!kInPlace || (R == 32 && W == 8), "the in-place layout has eight waves");
     static_assert(R == 32 || W == 4, "the 64-row layout has four waves");
     constexpr int NR = R == 32 ? (W == 16 ? 1 : 16 / W) : 8;  // transform registers per lane
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -629,9 +767,7 @@ __device__ __forceinline__ void publish(const SelArgs& a, Sel& S, const double T
     auto colof = [&](int k) {
         return R == 32 ? pair_col<W>(k, h, wave) : Lay<64>::col(wave, 0, k);
     };
-    const int t = S.t;
-    if (threadIdx.x < t) S.rows[threadIdx.x] = a.cand[S.basis[threadIdx.x]];
-    __syncthreads();
+    const int t = S.t;  // (S.rows was set by the elimination that precedes every publish)
     if (threadIdx.x == 0) {
         __hip_atomic_store(a.cnt_cur + (a.ncnt - 1), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         S.bcast = a.w.state[0];
@@ -657,8 +793,9 @@ __device__ __forceinline__ void publish(const SelArgs& a, Sel& S, const double T
         const double dinv = lz_mul(S.cp[s], S.total, L);
 #pragma unroll
         for (int k = 0; k < NR; ++k) {
-            const int c = colof(k);
-            if (c < t) a.out->pinv[s * 32 + c] = (uint32_t)lz_canon(lz_mul(dinv, T[k], L), L);
+            const int c = kInPlace ? S.cpv[colof(k)] : colof(k);
+            if (kInPlace ? c >= 0 : c < t)
+                a.out->pinv[s * 32 + c] = (uint32_t)lz_canon(lz_mul(dinv, T[k], L), L);
         }
     }
     const int r0 = S.bcast;
@@ -753,9 +890,10 @@ __device__ void select_first_block(const SelArgs& a) {
     if (threadIdx.x < 64) S.pos[threadIdx.x] = threadIdx.x;
     if (threadIdx.x == 0) S.nrows = min(kChunk, E);
     __syncthreads();
-    double v[8], T[8];
-    node_gj_pairs<kFirstWaves>(a, S, v, T, L);
-    if (S.t == a.wl || E <= kChunk) publish<32, kFirstWaves>(a, S, T, a.save_rows && !a.yfrag, L);
+    static_assert(kFirstWaves == 8, "the in-place elimination has eight waves");
+    double x[8];
+    node_gj_inplace(a, S, x, L);
+    if (S.t == a.wl || E <= kChunk) publish<32, kFirstWaves, true>(a, S, x, a.save_rows && !a.yfrag, L);
 }
 
 // The last arrival counter of each set is the "published" flag: once the final
