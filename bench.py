@@ -48,6 +48,10 @@ slow them):
                 element update (one pivot applied to one entry) is 2 FMAs of
                 an exact split product, 4 flops against 78.6 TFLOP/s.  The
                 bound reported is the nearer of the two, the other beside it.
+  leaf chain    the sum of the leaves' selection and product launches per
+                solve and per leaf (with the leaf pipeline a launch runs one
+                leaf's product beside the next leaf's first selection, and its
+                time appears in both the leaf-product and selection records).
 The headline "roofline" is the kernel with the largest total time.
 """
 
@@ -230,7 +234,7 @@ def cpu_baseline(target_s: float = 15.0, single_thread: bool = True):
 
 
 PATHS = {"auto": 0, "plain": 1, "int8": 2, "fp64": 3}
-KERNEL_SOURCES = ["plain.hip", "blocked.hip", "leaf.hip", "field.h"]
+KERNEL_SOURCES = ["plain.hip", "blocked.hip", "leaf.hip", "leafprod.h", "field.h"]
 
 
 def _resolved_plan(lx, m, n, path_name, panel):
@@ -258,21 +262,31 @@ def _rooflines(kinds, m, n, ncols, path_name, panel, src_hash, workload):
         per_mac_ops, peak, unit = (32.0, I8_PEAK_TOPS, "TOP/s") if path_name == "int8" else \
             (2.0, FP64_PEAK_TFLOPS, "TFLOP/s")
         int8 = path_name == "int8"
-        for kind, macs, kname in (("leaf_product", leaf_macs,
-                                   "leaf_product_i8_kernel (leaf transform)" if int8
-                                   else "gemm_f64_kernel (leaf transform)"),
-                                  ("trail_product", trail_macs,
-                                   ("gemm_i8_kernel" if int8 else "gemm_f64_kernel")
-                                   + " (trailing update)")):
-            if kind in kinds:
-                nl, ms = kinds[kind]
+        # With the leaf pipeline a fused launch ("leaf_fused") runs a leaf's product on
+        # every row but the next leaf's first chunk beside that leaf's first
+        # selection, so its time is counted in both of those records (each then
+        # bounds its kernel's own time from above); "leaf_chain" is the total.
+        def merged(*names):
+            got = [kinds[k] for k in names if k in kinds]
+            return (sum(c for c, _ in got), sum(t for _, t in got)) if got else None
+        for kind, macs, kname, parts in (("leaf_product", leaf_macs,
+                                          "leaf_product_i8_kernel (leaf transform)" if int8
+                                          else "gemm_f64_kernel (leaf transform)",
+                                          ("leaf_product", "leaf_fused")),
+                                         ("trail_product", trail_macs,
+                                          ("gemm_i8_kernel" if int8 else "gemm_f64_kernel")
+                                          + " (trailing update)", ("trail_product",))):
+            got = merged(*parts)
+            if got:
+                nl, ms = got
                 out[kind] = {"bound": "mfma", "kernel": kname,
                              "launches": nl, "avg_launch_us": ms * 1e3 / nl,
                              "algorithmic_ops_per_launch": per_mac_ops * macs / nl,
                              "achieved": per_mac_ops * macs / (ms / 1e3) / 1e12, "peak": peak,
-                             "unit": unit}
-        if "select" in kinds:
-            nl, ms = kinds["select"]
+                             "unit": unit, "time_of": list(parts), "total_ms": ms}
+        got = merged("select", "leaf_fused")
+        if got:
+            nl, ms = got
             upd = select_updates(n, panel)
             out["select"] = {"bound": "alu", "kernel": "leaf_select_kernel (first chunk, then "
                                                        "the tree or Y launch)",
@@ -280,13 +294,24 @@ def _rooflines(kinds, m, n, ncols, path_name, panel, src_hash, workload):
                              "launches": nl, "avg_launch_us": ms * 1e3 / nl,
                              "algorithmic_updates_per_launch": upd / nl,
                              "achieved": upd / (ms / 1e3) / 1e9,
-                             "peak": SELECT_UPDATES_PEAK / 1e9, "unit": "Gupdates/s"}
+                             "peak": SELECT_UPDATES_PEAK / 1e9, "unit": "Gupdates/s",
+                             "time_of": ["select", "leaf_fused"], "total_ms": ms}
+        chain = merged("select", "leaf_product", "leaf_fused")
+        if chain:
+            leaves = sum(-(-min(panel, n - j0) // LEAF) for j0 in range(0, n, panel))
+            out["leaf_chain"] = {"bound": "latency", "kernel": "leaf selections and products",
+                                 "launches": chain[0], "avg_launch_us": chain[1] * 1e3 / chain[0],
+                                 "leaves": leaves, "us_per_leaf": round(chain[1] * 1e3 / leaves, 2),
+                                 "achieved": per_mac_ops * leaf_macs / (chain[1] / 1e3) / 1e12,
+                                 "peak": peak, "unit": unit,
+                                 "time_of": ["select", "leaf_product", "leaf_fused"],
+                                 "total_ms": chain[1]}
     for name, r in out.items():
         r["frac"] = float(f"{r['achieved'] / r['peak']:.3g}")
         r["achieved"] = float(f"{r['achieved']:.4g}")
         r["peak"] = float(f"{r['peak']:.4g}")
         r["avg_launch_us"] = round(r["avg_launch_us"], 3)
-        r["total_ms"] = round(kinds[name][1], 3)
+        r["total_ms"] = round(r["total_ms"] if "total_ms" in r else kinds[name][1], 3)
         r["traffic"] = measured_traffic(r["kernel"].split()[0], workload, src_hash)
     return out
 
@@ -359,7 +384,9 @@ def bench_dense(config: str, steps: int, warmup: int, path_name_req: str = "auto
         kinds = lt.by_kind()
         src_hash = kernel_source_hash(KERNEL_SOURCES)
         roofs = _rooflines(kinds, m, n, n + k, path_name, panel, src_hash, config)
-        dominant = max(roofs, key=lambda name: roofs[name]["total_ms"]) if roofs else None
+        # the dominant kernel (the leaf chain is a sum of kernels, not one)
+        single = [name for name in roofs if name != "leaf_chain"]
+        dominant = max(single, key=lambda name: roofs[name]["total_ms"]) if single else None
         rec["roofline"] = roofs.get(dominant)
         rec["rooflines"] = roofs
         rec["kernel_ms_by_kind"] = {kk: round(v[1], 3) for kk, v in kinds.items()}

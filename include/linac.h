@@ -93,7 +93,10 @@ enum {
     LINAC_KERNEL_TRAIL_PRODUCT = 3, /* blocked: panel transform applied to the trailing columns */
     LINAC_KERNEL_BATCHED = 4,       /* batched persistent launch */
     LINAC_KERNEL_SELECT = 5,        /* blocked: pivot selection of a leaf */
-    LINAC_KERNEL_OPERANDS = 6       /* blocked: building the MFMA operands of a product */
+    LINAC_KERNEL_OPERANDS = 6,      /* blocked: building the MFMA operands of a product */
+    LINAC_KERNEL_LEAF_FUSED = 7     /* blocked int8, leaf pipeline: a leaf's product on all rows
+                                       but the next leaf's first chunk, in one launch with that
+                                       leaf's first pivot selection */
 };
 
 /*

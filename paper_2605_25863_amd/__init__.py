@@ -81,7 +81,7 @@ class _Opts(ctypes.Structure):
 
 
 KERNEL_KINDS = {1: "step", 2: "leaf_product", 3: "trail_product", 4: "batched", 5: "select",
-                6: "operands"}
+                6: "operands", 7: "leaf_fused"}
 
 
 class _Matrix(ctypes.Structure):

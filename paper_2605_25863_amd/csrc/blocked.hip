@@ -729,7 +729,7 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
                     lt.after();
                     e = hipGetLastError();
                     if (e != hipSuccess) break;
-                    lt.before(LINAC_KERNEL_LEAF_PRODUCT);
+                    lt.before(LINAC_KERNEL_LEAF_FUSED);
                     e = leaf_fused(w, b.leaf, b.PR.M, b.PR.ld, l1, wl1, wj, j0 + l1, parity ^ 1,
                                    (int64_t)wj + wl1, yf, pa, leaf_blocks, s);
                     lt.after();
