@@ -386,21 +386,26 @@ __global__ void panel_writeback_kernel(PlainArgs w, Mat src, Mat dst, int64_t d0
 //    x(c, t) = W[q][n + t] - sum over c' >= j0 + wj of U[q][c'] x(c', t),
 // with x(c', t) = W[pivot row of c'][n + t] once its panel is done and 0 for a
 // free column c'.  bs_partial_kernel: a workgroup takes 64 columns c' and 16
-// panel columns (4 per wave, lane = right-hand side t); the columns' pivot rows
-// and U entries are loaded once, lane by column, and broadcast across the wave
-// while the x loads of eight columns are in flight together; each product is
-// exact and lazily reduced (lz_prod, in [-p, 2p)), 64 of them sum below 2^38, and
-// the sums of at most 2^15 workgroups meet in FP64 atomics below 2^53 (exact,
-// so the order of the additions does not matter).  bs_finish_kernel writes
-// x = W[q][n + t] - acc mod p into the pivot row and clears acc.
-__device__ __forceinline__ double lz_prod(double a, double b, const FieldConst& F) {
-    const double h = a * b;
-    const double l = __fma_rn(a, b, -h);
-    const double q = floor(h * F.pinv);
-    return __fma_rn(-q, F.dp, h) + l;
-}
-
+// panel columns (4 per wave, lane = right-hand side t).  The columns' pivot
+// rows and U entries are loaded once, lane by column, and read across the wave
+// by readlane; x is split into 16-bit halves, so a
+// product is two exact FMAs, and the 64 products of a workgroup sum below 2^53
+// in two FP64 accumulators per panel column, reduced once.  The reduced sums
+// (below 2^31) of the n / 64 workgroups meet in FP64 atomics, below 2^53 for
+// any n below 2^28 (exact, so the order of the additions does not matter).
+// bs_finish_kernel writes x = W[q][n + t] - acc mod p into the pivot row and
+// clears acc.
 constexpr int kBsCols = 64;  // columns c' per workgroup
+
+// The residue in [0, p) of an integer s with |s| < 2^53 (two quotient steps:
+// the first estimate is within 2^-20 of exact, the second within one).
+__device__ __forceinline__ double canon53(double s, const FieldConst& F) {
+    double r = __fma_rn(-floor(s * F.pinv), F.dp, s);
+    r = __fma_rn(-floor(r * F.pinv), F.dp, r);
+    if (r < 0.0) r += F.dp;
+    if (r >= F.dp) r -= F.dp;
+    return r;
+}
 
 __global__ __launch_bounds__(kThreads) void bs_partial_kernel(PlainArgs w, int32_t n, int32_t k,
                                                               int32_t j0, int32_t wj, double* acc) {
@@ -423,35 +428,41 @@ __global__ __launch_bounds__(kThreads) void bs_partial_kernel(PlainArgs w, int32
     const bool cin = cc < n;
     const int32_t spc = cin ? w.colpiv[cc] : -1;
     const int32_t xr_l = spc >= 0 ? w.pivrow[spc] : -1;
-    double u_l[4];
+    uint32_t u_l[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-        u_l[i] = (cin && prow[i] >= 0) ? (double)w.W[prow[i] * w.ld + cc] : 0.0;
+    for (int i = 0; i < 4; ++i) u_l[i] = (cin && prow[i] >= 0) ? w.W[prow[i] * w.ld + cc] : 0u;
     for (int32_t t0 = 0; t0 < k; t0 += 64) {
         const int32_t t = t0 + lane;
         const int32_t tc = t < k ? t : k - 1;
-        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        double sh[4] = {0.0, 0.0, 0.0, 0.0}, sl[4] = {0.0, 0.0, 0.0, 0.0};
         // eight columns per round: their x loads are issued together
         for (int c8 = 0; c8 < kBsCols; c8 += 8) {
-            double xv[8];
+            uint32_t xv[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int32_t xr = __builtin_amdgcn_readlane(xr_l, c8 + e);
-                xv[e] = xr >= 0 ? (double)w.W[(int64_t)xr * w.ld + n + tc] : 0.0;
+                xv[e] = xr >= 0 ? w.W[(int64_t)xr * w.ld + n + tc] : 0u;
             }
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
+                const double xh = (double)(xv[e] >> 16), xl = (double)(xv[e] & 0xffffu);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const double u = __shfl(u_l[i], c8 + e);
-                    a[i] += lz_prod(u, xv[e], w.F);
+                    // < 2^31: u xh < 2^46, u xl < 2^47
+                    const double u = (double)(uint32_t)__builtin_amdgcn_readlane((int)u_l[i], c8 + e);
+                    sh[i] = __fma_rn(u, xh, sh[i]);
+                    sl[i] = __fma_rn(u, xl, sl[i]);
                 }
             }
         }
         if (t < k) {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                if (prow[i] >= 0) atomicAdd(&acc[(int64_t)(cl0 + i) * k + t], a[i]);
+                if (prow[i] >= 0) {
+                    // sh < 2^52, sl < 2^53: (sh mod p) 2^16 + (sl mod p) < 2^48
+                    const double r = canon53(__fma_rn(canon53(sh[i], w.F), 65536.0, canon53(sl[i], w.F)), w.F);
+                    atomicAdd(&acc[(int64_t)(cl0 + i) * k + t], r);
+                }
         }
     }
 }
