@@ -1024,7 +1024,10 @@ __global__ __launch_bounds__(first ? kFirstThreads : kSelThreads, first ? 2 : 1)
 // pivot rows; the product reads leaf l's result and writes the other rows and
 // the next candidate list.
 template <int kLeafBlocks>
-__global__ __launch_bounds__(kFirstThreads, 2) void leaf_fused_kernel(SelArgs sa, LeafProdArgs pa,
+// (at most 128 VGPRs, so that two workgroups fit on a compute unit: with the
+// tuned six column blocks the product half needs 132 otherwise)
+__global__ __attribute__((amdgpu_flat_work_group_size(kFirstThreads, kFirstThreads),
+                          amdgpu_waves_per_eu(4, 8))) void leaf_fused_kernel(SelArgs sa, LeafProdArgs pa,
                                                                      int32_t rbx) {
     if (blockIdx.x == 0) {
         select_first_block(sa);
