@@ -324,17 +324,12 @@ __device__ __forceinline__ void node_gj(const SelArgs& a, Sel& S, double v[8], d
     __syncthreads();
 }
 
-// The 32-row elimination two columns per step (16 synchronisations per leaf
-// instead of 32).  Lane = 32 h + row; register 2k + e of wave v holds column
-// 2P + e of pair P = 8k + 4h + v (k, e in {0, 1}); T[] likewise.  The owner
-// wave of pair P finds the first column's pivot, applies it to the second
-// column itself, finds the second pivot and posts both; every wave then applies
-// the two pivots in order.  Same results as one column per step.
-// Column of register k in the pair layout of W waves (see node_gj_pairs).  With
-// 16 waves a lane holds one column: wave P has pair P, half h its column 2P + h.
+// The pair layout of the 32-row elimination (two columns per step: 16
+// synchronisations per leaf instead of 32).  Lane = 32 h + row; with W waves,
+// register 2k + e of wave v holds column 2P + e of pair P = 2Wk + Wh + v (k, e
+// in {0, 1}).
 template <int W>
 __device__ __forceinline__ int pair_col(int k, int h, int wave) {
-    if (W == 16) return 2 * wave + h;
     return 2 * (2 * W * (k >> 1) + W * h + wave) + (k & 1);
 }
 
@@ -350,49 +345,25 @@ __device__ __forceinline__ double pair_row(double x, int bpaddr) {
 
 __device__ __forceinline__ int pair_bpaddr(int q) { return (int)(((threadIdx.x & 32) + q) << 2); }
 
-// One pivot (row q, value d, column values f) on the leaf registers K0..K1-1,
-// columns after jj: straight-line code over whole registers, the result kept
-// per lane by a select, so the registers' FP64 chains interleave.
-template <int W, int K0, int K1>
-__device__ __forceinline__ void pair_leaf_pivot(double x[4], int q, double d, double f, int jj, int h,
-                                                int wave, int r, int wl, const Lazy& L) {
-    double u[4], y[4];
-    const int bp = pair_bpaddr(q);
-#pragma unroll
-    for (int k = K0; k < K1; ++k) u[k] = pair_row(x[k], bp);
-    lz_ff_n<K0, K1>(y, d, x, f, u, L);
-#pragma unroll
-    for (int k = K0; k < K1; ++k) {
-        const int c = pair_col<W>(k, h, wave);
-        x[k] = (c > jj && c < wl && r != q) ? y[k] : x[k];
-    }
-}
-
-// The same pivot on the transform registers 0..K1-1: columns before s are
-// updated, column s receives the pivot's new transform column (cp on the pivot
-// row, inj elsewhere), later columns are still zero.
-template <int W, int K1>
-__device__ __forceinline__ void pair_t_pivot(double x[4], int q, double d, double f, int s, double cp,
-                                             double inj, int h, int wave, int r, const Lazy& L) {
-    double u[4], y[4];
-    const int bp = pair_bpaddr(q);
-#pragma unroll
-    for (int k = 0; k < K1; ++k) u[k] = pair_row(x[k], bp);
-    lz_ff_n<0, K1>(y, d, x, f, u, L);
-#pragma unroll
-    for (int k = 0; k < K1; ++k) {
-        const int c = pair_col<W>(k, h, wave);
-        x[k] = c < s ? (r != q ? y[k] : x[k]) : (c == s ? (r == q ? cp : inj) : x[k]);
-    }
-}
-
+// The 32-row elimination in place: the slot of a leaf column holds that
+// column until it becomes the pivot column of pivot s, and from then on column
+// s of the transform T (the in-place form of Gauss-Jordan inversion).  Every
+// slot is then live at every step, so a lane updates its 16 / W slots per pivot
+// instead of the live part of 16 / W leaf and 16 / W transform registers.  The
+// slots follow the pair layout (slot k = register k of pair_col<W>): the
+// owner wave of pair P first brings the pair's two slots up to date, posts
+// both pivots, then updates its other slots.  A pivot (row q, value d, column
+// j, column values f) maps every slot of every row but q to d x - f x_q, and
+// slot j to cprod on row q and -f cprod elsewhere (the new pivot's transform
+// column).  Slots of free columns hold values that nothing reads.  The owner
+// wave of pair P finds the first column's pivot, applies it to the second
+// column itself, finds the second pivot and posts both; every wave then applies
+// the two pivots in order, which gives the results of one column per step.
+// S.cpv maps a column to its pivot.
 template <int W>
-__device__ __forceinline__ void node_gj_pairs(const SelArgs& a, Sel& S, double v[8], double T[8],
-                                              const Lazy& L) {
-    static_assert(W == 4 || W == 8 || W == 16, "4, 8 or 16 waves");
-    constexpr int NR = W == 16 ? 1 : 16 / W;  // leaf (and transform) registers per lane
-    // wave-uniform by construction; readfirstlane lets the compiler see it, so
-    // conditions on it stay scalar branches instead of exec-masked regions
+__device__ __forceinline__ void node_gj_inplace(const SelArgs& a, Sel& S, double x[], const Lazy& L) {
+    static_assert(W == 4 || W == 8, "four or eight waves");
+    constexpr int NR = 16 / W;  // slots per lane
     const int lane = threadIdx.x & 63, wave = uniform(threadIdx.x >> 6);
     const int h = lane >> 5, r = lane & 31;
     const int nrows = S.nrows;
@@ -401,216 +372,8 @@ __device__ __forceinline__ void node_gj_pairs(const SelArgs& a, Sel& S, double v
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
         const int c = pair_col<W>(k, h, wave);
-        v[k] = (row >= 0 && c < a.wl) ? (double)a.PR[(int64_t)row * a.ldpr + a.l0 + c] : 0.0;
-        T[k] = 0.0;
+        x[k] = (row >= 0 && c < a.wl) ? (double)a.PR[(int64_t)row * a.ldpr + a.l0 + c] : 0.0;
     }
-    if (threadIdx.x < 64) S.sidx[threadIdx.x] = -1;
-    const unsigned long long valid = nrows >= 32 ? 0xffffffffull : ((1ull << nrows) - 1ull);
-    unsigned long long chosen = 0;  // rows of this node (bits 0..31)
-    int t = 0;
-    double cprod = 1.0;
-    auto first_nz = [&](double x, int hh, unsigned long long excl) {
-        const double ax = fabs(x);  // lazy value in (-3p, 3p): zero iff |x| is 0, p or 2p
-        const unsigned long long nz = __ballot(!(ax == 0.0 || ax == L.p || ax == 2.0 * L.p));
-        const unsigned long long m = ((nz >> (32 * hh)) & 0xffffffffull) & valid & ~excl;
-        const int mlo = uniform((int)(uint32_t)m);
-        return mlo != 0 ? __builtin_ctz((uint32_t)mlo) : -1;
-    };
-    const int npairs = (a.wl + 1) >> 1;
-    // owner of pair P: post both pivots (the second column exists iff 2P + 1 < wl)
-    auto detect = [&](int P) {
-        if constexpr (W == 16) {
-            // half 0 holds the pair's first column, half 1 its second
-            const double x = v[0];
-            const int q1 = first_nz(x, 0, chosen);
-            const double d1 = q1 >= 0 ? readlane_d(x, q1) : 0.0;
-            double xb = x;
-            if (q1 >= 0) {
-                const double ub = readlane_d(x, 32 + q1);
-                const double fa = pair_row(x, r << 2);  // this row's first-column value
-                if (h == 1 && r != q1) xb = lz_ff(d1, x, fa, ub, L);
-            }
-            int q2 = -1;
-            double d2 = 0.0;
-            if (2 * P + 1 < a.wl) {
-                q2 = first_nz(xb, 1, chosen | (q1 >= 0 ? 1ull << q1 : 0ull));
-                d2 = q2 >= 0 ? readlane_d(xb, 32 + q2) : 0.0;
-            }
-            const int buf = P & 1;
-            if (h == 0) S.f[buf][r] = x;
-            else S.f2[buf][r] = xb;
-            if (lane == 0) {
-                S.q[buf] = q1;
-                S.d[buf] = d1;
-                S.q2[buf] = q2;
-                S.d2[buf] = d2;
-            }
-            return;
-        }
-        const int hp = (P / W) & 1, kp = P / (2 * W);
-        double xa = 0.0, xb = 0.0;  // registers 2 kp and 2 kp + 1, selected arithmetically
-#pragma unroll
-        for (int k = 0; k < NR / 2; ++k) {
-            xa = __fma_rn(v[2 * k], k == kp ? 1.0 : 0.0, xa);
-            xb = __fma_rn(v[2 * k + 1], k == kp ? 1.0 : 0.0, xb);
-        }
-        const int q1 = first_nz(xa, hp, chosen);
-        const double d1 = q1 >= 0 ? readlane_d(xa, 32 * hp + q1) : 0.0;
-        if (q1 >= 0) {
-            const double ub = readlane_d(xb, 32 * hp + q1);
-            if (r != q1) xb = lz_ff(d1, xb, xa, ub, L);
-        }
-        int q2 = -1;
-        double d2 = 0.0;
-        if (2 * P + 1 < a.wl) {
-            q2 = first_nz(xb, hp, chosen | (q1 >= 0 ? 1ull << q1 : 0ull));
-            d2 = q2 >= 0 ? readlane_d(xb, 32 * hp + q2) : 0.0;
-        }
-        const int buf = P & 1;
-        if (h == hp) {
-            S.f[buf][r] = xa;
-            S.f2[buf][r] = xb;
-        }
-        if (lane == 0) {
-            S.q[buf] = q1;
-            S.d[buf] = d1;
-            S.q2[buf] = q2;
-            S.d2[buf] = d2;
-        }
-    };
-    __syncthreads();
-    if (wave == 0 && a.wl > 0) detect(0);
-    for (int P = 0; P < npairs; ++P) {
-        __syncthreads();  // pair P posted; every wave is done with pair P - 1's post
-        const int buf = P & 1;
-        const int q1v = S.q[buf], q2v = S.q2[buf];
-        const double f1 = S.f[buf][r], f2 = S.f2[buf][r];
-        const double d1 = S.d[buf], d2 = S.d2[buf];
-        const int q1 = uniform(q1v), q2 = uniform(q2v);
-        const int j = 2 * P;
-        const int s1 = t, s2 = t + (q1 >= 0);
-        if (threadIdx.x == 0) {
-            if (q1 >= 0) {
-                S.pl[s1] = q1;
-                S.pc[s1] = j;
-                S.sidx[q1] = s1;
-                S.cp[s1] = cprod;
-            }
-            if (q2 >= 0) {
-                S.pl[s2] = q2;
-                S.pc[s2] = j + 1;
-                S.sidx[q2] = s2;
-                S.cp[s2] = q1 >= 0 ? lz_mul(cprod, d1, L) : cprod;
-            }
-        }
-        // Leaf columns first (the next pair's owner posts right after them),
-        // pivot 1 on every register before pivot 2.  Registers 0 and 1 hold
-        // columns below 16 only, registers 2 and 3 columns from 16 on, so the
-        // live registers follow from a scalar test.
-        const bool owner = P + 1 < npairs && wave == (P + 1) % W;
-        if constexpr (W == 4) {
-            if (!owner) {
-                if (q1 >= 0) {
-                    if (j < 16) pair_leaf_pivot<W, 0, 4>(v, q1, d1, f1, j, h, wave, r, a.wl, L);
-                    else pair_leaf_pivot<W, 2, 4>(v, q1, d1, f1, j, h, wave, r, a.wl, L);
-                }
-                if (q2 >= 0) {
-                    if (j + 1 < 16) pair_leaf_pivot<W, 0, 4>(v, q2, d2, f2, j + 1, h, wave, r, a.wl, L);
-                    else pair_leaf_pivot<W, 2, 4>(v, q2, d2, f2, j + 1, h, wave, r, a.wl, L);
-                }
-            }
-            if (q1 >= 0) chosen |= 1ull << q1;
-            if (q2 >= 0) chosen |= 1ull << q2;
-            if (owner) {
-                // the next pair's owner brings that pair's two registers up to
-                // date first, posts it, and only then updates its other registers
-                if (((P + 1) >> 3) == 0) {  // registers 0, 1 (columns below 16; here j < 16)
-                    if (q1 >= 0) pair_leaf_pivot<W, 0, 2>(v, q1, d1, f1, j, h, wave, r, a.wl, L);
-                    if (q2 >= 0) pair_leaf_pivot<W, 0, 2>(v, q2, d2, f2, j + 1, h, wave, r, a.wl, L);
-                    detect(P + 1);
-                    if (q1 >= 0) pair_leaf_pivot<W, 2, 4>(v, q1, d1, f1, j, h, wave, r, a.wl, L);
-                    if (q2 >= 0) pair_leaf_pivot<W, 2, 4>(v, q2, d2, f2, j + 1, h, wave, r, a.wl, L);
-                } else {  // registers 2, 3
-                    if (q1 >= 0) pair_leaf_pivot<W, 2, 4>(v, q1, d1, f1, j, h, wave, r, a.wl, L);
-                    if (q2 >= 0) pair_leaf_pivot<W, 2, 4>(v, q2, d2, f2, j + 1, h, wave, r, a.wl, L);
-                    detect(P + 1);
-                    if (q1 >= 0 && j < 16) pair_leaf_pivot<W, 0, 2>(v, q1, d1, f1, j, h, wave, r, a.wl, L);
-                    if (q2 >= 0 && j + 1 < 16)
-                        pair_leaf_pivot<W, 0, 2>(v, q2, d2, f2, j + 1, h, wave, r, a.wl, L);
-                }
-            }
-            // transform columns: pivot 1 at column s1, then pivot 2 at column s2
-            if (q1 >= 0) {
-                const double inj = -lz_mul(f1, cprod, L);
-                if (s1 < 16) pair_t_pivot<W, 2>(T, q1, d1, f1, s1, cprod, inj, h, wave, r, L);
-                else pair_t_pivot<W, 4>(T, q1, d1, f1, s1, cprod, inj, h, wave, r, L);
-            }
-            if (q2 >= 0) {
-                const double cp2 = q1 >= 0 ? lz_mul(cprod, d1, L) : cprod;
-                const double inj = -lz_mul(f2, cp2, L);
-                if (s2 < 16) pair_t_pivot<W, 2>(T, q2, d2, f2, s2, cp2, inj, h, wave, r, L);
-                else pair_t_pivot<W, 4>(T, q2, d2, f2, s2, cp2, inj, h, wave, r, L);
-            }
-        } else {
-            // eight waves: wave v holds columns 2 v, 2 v + 1 (half 0) and 16 + 2 v,
-            // 17 + 2 v (half 1) in registers 0 and 1; sixteen waves: columns 2 v
-            // and 2 v + 1 in register 0.  The owner's pair is among them.
-            const bool leaf_live = (W == 8 ? 17 : 1) + 2 * wave > j;  // a column after j
-            if (leaf_live && q1 >= 0) pair_leaf_pivot<W, 0, NR>(v, q1, d1, f1, j, h, wave, r, a.wl, L);
-            if (leaf_live && q2 >= 0)
-                pair_leaf_pivot<W, 0, NR>(v, q2, d2, f2, j + 1, h, wave, r, a.wl, L);
-            if (q1 >= 0) chosen |= 1ull << q1;
-            if (q2 >= 0) chosen |= 1ull << q2;
-            if (owner) detect(P + 1);
-            // transform columns up to s: live once s reaches this wave's first one
-            if (q1 >= 0 && 2 * wave <= s1) {
-                const double inj = -lz_mul(f1, cprod, L);
-                pair_t_pivot<W, NR>(T, q1, d1, f1, s1, cprod, inj, h, wave, r, L);
-            }
-            if (q2 >= 0 && 2 * wave <= s2) {
-                const double cp2 = q1 >= 0 ? lz_mul(cprod, d1, L) : cprod;
-                const double inj = -lz_mul(f2, cp2, L);
-                pair_t_pivot<W, NR>(T, q2, d2, f2, s2, cp2, inj, h, wave, r, L);
-            }
-        }
-        if (q1 >= 0) cprod = lz_mul(cprod, d1, L);
-        if (q2 >= 0) cprod = lz_mul(cprod, d2, L);
-        t = s2 + (q2 >= 0);
-    }
-    if (threadIdx.x == 0) {
-        S.t = t;
-        S.total = cprod;
-    }
-    __syncthreads();
-    if (threadIdx.x < t) {
-        S.basis[threadIdx.x] = S.pos[S.pl[threadIdx.x]];
-        S.rows[threadIdx.x] = S.rowid[S.pl[threadIdx.x]];
-    }
-    __syncthreads();
-}
-
-// The first launch's elimination (eight waves, 32 rows), in place: the slot of
-// a leaf column holds that column until it becomes the pivot column of pivot
-// s, and from then on column s of the transform T (the in-place form of
-// Gauss-Jordan inversion).  Every slot is then live at every step, so a lane
-// updates two slots per pivot instead of two leaf and two transform registers.
-// Lane = 32 h + row; wave v holds pair 8 h + v, columns 16 h + 2 v and
-// 16 h + 2 v + 1, in x[0] and x[1] (the pair layout of node_gj_pairs<8>).  A
-// pivot (row q, value d, column j, column values f) maps every slot of every
-// row but q to d x - f x_q, and slot j to cprod on row q and -f cprod
-// elsewhere (the new pivot's transform column).  Slots of free columns hold
-// values that nothing reads.  Same pivots, P^-1 and results as node_gj_pairs.
-__device__ __forceinline__ void node_gj_inplace(const SelArgs& a, Sel& S, double x[2], const Lazy& L) {
-    constexpr int W = 8;
-    const int lane = threadIdx.x & 63, wave = uniform(threadIdx.x >> 6);
-    const int h = lane >> 5, r = lane & 31;
-    const int c0 = 16 * h + 2 * wave;  // this lane's columns: c0, c0 + 1
-    const int nrows = S.nrows;
-    const int32_t row = r < nrows ? a.cand[S.pos[r]] : -1;
-    if (threadIdx.x < 32) S.rowid[r] = row;
-#pragma unroll
-    for (int k = 0; k < 2; ++k)
-        x[k] = (row >= 0 && c0 + k < a.wl) ? (double)a.PR[(int64_t)row * a.ldpr + a.l0 + c0 + k] : 0.0;
     if (threadIdx.x < 64) S.sidx[threadIdx.x] = -1;
     if (threadIdx.x < 32) S.cpv[threadIdx.x] = -1;
     const unsigned long long valid = nrows >= 32 ? 0xffffffffull : ((1ull << nrows) - 1ull);
@@ -625,11 +388,18 @@ __device__ __forceinline__ void node_gj_inplace(const SelArgs& a, Sel& S, double
         return mlo != 0 ? __builtin_ctz((uint32_t)mlo) : -1;
     };
     const int npairs = (a.wl + 1) >> 1;
-    // owner of pair P (wave P % 8, half P / 8): both pivots of the pair, posted
+    // owner of pair P (wave P % W, half (P / W) & 1, slots 2 kp and 2 kp + 1
+    // with kp = P / 2W): both pivots of the pair, posted
     auto detect = [&](int P) {
-        const int hp = P / W;
-        const double xa = x[0];
+        const int hp = (P / W) & 1, kp = P / (2 * W);
+        double xa = x[0];
         double xb = x[1];
+        if constexpr (NR == 4) {
+            if (kp != 0) {  // (uniform)
+                xa = x[2];
+                xb = x[3];
+            }
+        }
         const int q1 = first_nz(xa, hp, chosen);
         const double d1 = q1 >= 0 ? readlane_d(xa, 32 * hp + q1) : 0.0;
         if (q1 >= 0) {
@@ -654,18 +424,22 @@ __device__ __forceinline__ void node_gj_inplace(const SelArgs& a, Sel& S, double
             S.d2[buf] = d2;
         }
     };
-    // one pivot on both slots: d x - f x_q off the pivot row, the transform
-    // column's start in the pivot column's slot
-    auto apply = [&](int q, double d, double f, int j, double cp) {
+    // one pivot on slots K0..K1-1: d x - f x_q off the pivot row, inj (the
+    // transform column's start) in the pivot column's slot
+    auto apply = [&](auto k0, auto k1, int q, double d, double f, int j, double inj) {
+        constexpr int K0 = decltype(k0)::value, K1 = decltype(k1)::value;
         const int bp = pair_bpaddr(q);
-        double u[2], y[2];
+        double u[4], y[4];
 #pragma unroll
-        for (int k = 0; k < 2; ++k) u[k] = pair_row(x[k], bp);
-        lz_ff_n<0, 2>(y, d, x, f, u, L);
-        const double inj = r == q ? cp : -lz_mul(f, cp, L);
+        for (int k = K0; k < K1; ++k) u[k] = pair_row(x[k], bp);
+        lz_ff_n<K0, K1>(y, d, x, f, u, L);
 #pragma unroll
-        for (int k = 0; k < 2; ++k) x[k] = c0 + k == j ? inj : (r != q ? y[k] : x[k]);
+        for (int k = K0; k < K1; ++k)
+            x[k] = pair_col<W>(k, h, wave) == j ? inj : (r != q ? y[k] : x[k]);
     };
+    using I0 = std::integral_constant<int, 0>;
+    using I2 = std::integral_constant<int, 2>;
+    using IN = std::integral_constant<int, NR>;
     __syncthreads();
     if (wave == 0 && a.wl > 0) detect(0);
     for (int P = 0; P < npairs; ++P) {
@@ -694,11 +468,35 @@ __device__ __forceinline__ void node_gj_inplace(const SelArgs& a, Sel& S, double
                 S.cp[s2] = cp2;
             }
         }
-        if (q1 >= 0) apply(q1, d1, f1, j, cprod);
-        if (q2 >= 0) apply(q2, d2, f2, j + 1, cp2);
-        if (q1 >= 0) chosen |= 1ull << q1;
-        if (q2 >= 0) chosen |= 1ull << q2;
-        if (P + 1 < npairs && wave == (P + 1) % W) detect(P + 1);
+        const double inj1 = r == q1 ? cprod : -lz_mul(f1, cprod, L);
+        const double inj2 = r == q2 ? cp2 : -lz_mul(f2, cp2, L);
+        const bool owner = P + 1 < npairs && wave == (P + 1) % W;
+        if (NR == 4 && owner) {
+            // the next pair's owner: that pair's two slots, its post, the rest
+            if ((P + 1) / (2 * W) == 0) {
+                if (q1 >= 0) apply(I0{}, I2{}, q1, d1, f1, j, inj1);
+                if (q2 >= 0) apply(I0{}, I2{}, q2, d2, f2, j + 1, inj2);
+            } else {
+                if (q1 >= 0) apply(I2{}, IN{}, q1, d1, f1, j, inj1);
+                if (q2 >= 0) apply(I2{}, IN{}, q2, d2, f2, j + 1, inj2);
+            }
+            if (q1 >= 0) chosen |= 1ull << q1;
+            if (q2 >= 0) chosen |= 1ull << q2;
+            detect(P + 1);
+            if ((P + 1) / (2 * W) == 0) {
+                if (q1 >= 0) apply(I2{}, IN{}, q1, d1, f1, j, inj1);
+                if (q2 >= 0) apply(I2{}, IN{}, q2, d2, f2, j + 1, inj2);
+            } else {
+                if (q1 >= 0) apply(I0{}, I2{}, q1, d1, f1, j, inj1);
+                if (q2 >= 0) apply(I0{}, I2{}, q2, d2, f2, j + 1, inj2);
+            }
+        } else {
+            if (q1 >= 0) apply(I0{}, IN{}, q1, d1, f1, j, inj1);
+            if (q2 >= 0) apply(I0{}, IN{}, q2, d2, f2, j + 1, inj2);
+            if (q1 >= 0) chosen |= 1ull << q1;
+            if (q2 >= 0) chosen |= 1ull << q2;
+            if (owner) detect(P + 1);
+        }
         cprod = q2 >= 0 ? lz_mul(cp2, d2, L) : cp2;
         t = s2 + (q2 >= 0);
     }
@@ -752,15 +550,15 @@ __device__ void pick_nonzero_rows(const SelArgs& a, Sel& S, int E) {
 
 // Final node: P^-1, the leaf result, the pivot bookkeeping, and a copy of the
 // pivot rows over the columns the leaf updates (the product overwrites them).
-// R = 32: the pair layout of node_gj_pairs; R = 64: the layout of node_gj<64>.
+// R = 32: the pair layout of node_gj_inplace; R = 64: the layout of node_gj<64>.
 // kInPlace: T comes from node_gj_inplace (slot of leaf column c = transform
 // column S.cpv[c]).
 template <int R, int W, bool kInPlace = false>
 __device__ __forceinline__ void publish(const SelArgs& a, Sel& S, const double T[8], bool save_rows,
                                         const Lazy& L) {
-    static_assert(!kInPlace || (R == 32 && W == 8), "the in-place layout has eight waves");
+    static_assert(!kInPlace || (R == 32 && (W == 4 || W == 8)), "the in-place layout has four or eight waves");
     static_assert(R == 32 || W == 4, "the 64-row layout has four waves");
-    constexpr int NR = R == 32 ? (W == 16 ? 1 : 16 / W) : 8;  // transform registers per lane
+    constexpr int NR = R == 32 ? 16 / W : 8;  // transform registers per lane
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int h = R == 32 ? lane >> 5 : 0;
     const int r = R == 32 ? lane & 31 : lane;
@@ -892,7 +690,7 @@ __device__ void select_first_block(const SelArgs& a) {
     __syncthreads();
     static_assert(kFirstWaves == 8, "the in-place elimination has eight waves");
     double x[8];
-    node_gj_inplace(a, S, x, L);
+    node_gj_inplace<kFirstWaves>(a, S, x, L);
     if (S.t == a.wl || E <= kChunk) publish<32, kFirstWaves, true>(a, S, x, a.save_rows && !a.yfrag, L);
 }
 
@@ -939,8 +737,8 @@ __global__ __launch_bounds__(first ? kFirstThreads : kSelThreads, first ? 2 : 1)
     // adds nothing to the leaf's span, so node (level, 0) still spans what the
     // candidates before its range span, and the tree's finality rule holds.
     if (g == 0) pick_nonzero_rows<kSelWaves>(a, S, E);
-    node_gj_pairs<kSelWaves>(a, S, v, T, L);
-    int regs = 32;  // v, T hold the Gauss-Jordan of the node's basis rows in this layout (0: none)
+    node_gj_inplace<kSelWaves>(a, S, T, L);
+    int regs = 32;  // T holds the in-place Gauss-Jordan of the node's basis rows (64: v, T of node_gj<64>; 0: none)
     while (true) {
         const int t = S.t;
         if ((k == 0 && t == a.wl) || nodes == 1) {
@@ -948,12 +746,12 @@ __global__ __launch_bounds__(first ? kFirstThreads : kSelThreads, first ? 2 : 1)
                 if (threadIdx.x < t) S.pos[threadIdx.x] = S.basis[threadIdx.x];
                 if (threadIdx.x == 0) S.nrows = t;
                 __syncthreads();
-                node_gj_pairs<kSelWaves>(a, S, v, T, L);
+                node_gj_inplace<kSelWaves>(a, S, T, L);
                 regs = 32;
             }
             // the tree launch leaves Y to the product, which needs the rows as selected
             const bool save_rows = a.save_rows != 0;
-            if (regs == 32) publish<32, kSelWaves>(a, S, T, save_rows, L);
+            if (regs == 32) publish<32, kSelWaves, true>(a, S, T, save_rows, L);
             else publish<64, kSelWaves>(a, S, T, save_rows, L);
             return;
         }
