@@ -108,6 +108,14 @@ def _load():
         return _lib
     if not os.path.exists(_LIBPATH):
         raise RuntimeError(f"{_LIBPATH} is not built; run `python -m paper_2605_25863_amd.build`")
+    # torch ships its own HIP runtime under the same soname as the system one
+    # the library links; whichever loads first serves the whole process.  Load
+    # torch's first, so that both see the devices through one runtime (with the
+    # system runtime first, the library's calls found no device).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(_LIBPATH)
     vp, i64, u32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t
     optp = ctypes.POINTER(_Opts)
