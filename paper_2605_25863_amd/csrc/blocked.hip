@@ -176,10 +176,10 @@ __device__ __forceinline__ uint32_t fold7(const v16i* acc, int r, uint32_t add, 
 // [fresh_lo, fresh_hi)).  Block: 4 waves over a 128 x 32 tile; wave v owns rows
 // [(4*bx + v)*32, +32) and the block's 32 columns, with the seven group
 // accumulators of one 32x32 MFMA block.  The B fragments of a k-block (4 digit
-// planes x 1 KB) are shared through LDS, double-buffered: the next k-block is
-// loaded into registers while the MFMAs run on the current one, then written
-// to the other buffer.  A fragments (each wave needs only its own rows) are
-// prefetched into registers.  With grid.x = row tiles and a multiple of 8 of
+// planes x 1 KB) are shared through LDS, double-buffered; A fragments (each
+// wave needs only its own rows) stay in registers.  Both are fetched two
+// k-blocks ahead of the MFMAs that use them, so that an L2 or HBM round trip
+// overlaps two k-blocks of MFMA work.  With grid.x = row tiles and a multiple of 8 of
 // them, all blocks of one row tile run on the same XCD, so each XCD's L2 holds
 // one eighth of the A operand.
 // Tiles of 128 rows x 32 columns, taken by the workgroups in turn (row tiles
@@ -209,36 +209,31 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
         v16i acc[7];
         for (int g = 0; g < 7; ++g)
             for (int r = 0; r < 16; ++r) acc[g][r] = 0;
-        v4i stage, af[4], an[4];
-        stage = *(const v4i*)bsrc;
-        for (int l = 0; l < 4; ++l) af[l] = *(const v4i*)(asrc + l * 1024);
-        sB[0][wave * 64 + lane] = stage;  // the k loop's last barrier freed sB
+        // Operands two k-blocks ahead: A in three register sets, B through two
+        // staging registers into the two LDS buffers.  The loop is unrolled by
+        // six so that every set has a fixed register name and no load in flight
+        // is ever copied (a copy would wait for it).  Every step issues its
+        // loads unconditionally (the last k-block again near the end) and is
+        // reached from the step before it only: the wait counts then see one
+        // sequence of loads and wait only for the k-block in use.
+        v4i a0[4], a1[4], a2[4], b0, b1;
+        const int last = KB - 1;
+        auto load_a = [&](v4i (&dst4)[4], int kb) {
+            for (int l = 0; l < 4; ++l) dst4[l] = *(const v4i*)(asrc + ((int64_t)kb * 4 + l) * 1024);
+        };
+        const v4i first = *(const v4i*)bsrc;
+        load_a(a0, 0);
+        b1 = *(const v4i*)(bsrc + (int64_t)min(1, last) * 4 * 1024);
+        load_a(a1, min(1, last));
+        sB[0][wave * 64 + lane] = first;  // the k loop's last barrier freed sB
         __builtin_amdgcn_s_waitcnt(0);  // nothing in flight at the loop head
         __syncthreads();
-        for (int kb = 0; kb < KB; ++kb) {
-            const bool more = kb + 1 < KB;
-            if (more) {  // next k-block in flight while this one computes
-                stage = *(const v4i*)(bsrc + (int64_t)(kb + 1) * 4 * 1024);
-                for (int l = 0; l < 4; ++l)
-                    an[l] = *(const v4i*)(asrc + ((int64_t)(kb + 1) * 4 + l) * 1024);
-            }
-            const v4i* sb = sB[kb & 1];
-            v4i bf[4];
-            for (int lp = 0; lp < 4; ++lp) bf[lp] = sb[lp * 64 + lane];
-            for (int l = 0; l < 4; ++l)
-                for (int lp = 0; lp < 4; ++lp)
-                    acc[l + lp] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[l], bf[lp], acc[l + lp], 0, 0, 0);
-            if (more) {
-                sB[(kb + 1) & 1][wave * 64 + lane] = stage;
-                for (int l = 0; l < 4; ++l) af[l] = an[l];
-            }
-            __syncthreads();
-        }
-        // epilogue: 32x32 accumulator layout: lane L holds column L%32 and rows
-        // 8*(r/4) + 4*(L/32) + r%4 for r = 0..15.  All loads are issued before
-        // the first store so their latencies overlap (addresses clamped into the
-        // matrix so that every load is issued unconditionally; out-of-range
-        // values are discarded afterwards).
+        // The tile's C entries and its rows' bookkeeping, loaded now so that
+        // their latency passes under the k loop.  32x32 accumulator layout:
+        // lane L holds column L%32 and rows 8*(r/4) + 4*(L/32) + r%4 for r =
+        // 0..15.  Addresses are clamped into the matrix so that every load is
+        // issued unconditionally; out-of-range values are discarded in the
+        // epilogue.
         const int64_t col = cb * 32 + (lane & 31);
         const int64_t colc = col < N ? col : N - 1;
         int rcv[16];
@@ -249,6 +244,37 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
             rcv[r] = w.rowcol[rowc];
             cur[r] = __builtin_nontemporal_load(dst.M + rowc * dst.ld + col0 + colc);
         }
+        // step kb: issue k-block kb + 2 (A into fut, B into bload), multiply
+        // k-block kb (A in cur, B in LDS buffer kb & 1), store k-block kb + 1's B
+        // (staged in bstore one step earlier) into the other buffer
+        auto step = [&](int kb, v4i (&cur)[4], v4i (&fut)[4], v4i& bload, const v4i& bstore) {
+            const int nb = min(kb + 2, last);
+            bload = *(const v4i*)(bsrc + (int64_t)nb * 4 * 1024);
+            load_a(fut, nb);
+            const v4i* sb = sB[kb & 1];
+            v4i bf[4];
+            for (int lp = 0; lp < 4; ++lp) bf[lp] = sb[lp * 64 + lane];
+            for (int l = 0; l < 4; ++l)
+                for (int lp = 0; lp < 4; ++lp)
+                    acc[l + lp] = __builtin_amdgcn_mfma_i32_32x32x32_i8(cur[l], bf[lp], acc[l + lp], 0, 0, 0);
+            if (kb + 1 < KB) sB[(kb + 1) & 1][wave * 64 + lane] = bstore;
+            __syncthreads();
+        };
+        for (int kb = 0;; kb += 6) {
+            step(kb, a0, a2, b0, b1);
+            if (kb + 1 >= KB) break;
+            step(kb + 1, a1, a0, b1, b0);
+            if (kb + 2 >= KB) break;
+            step(kb + 2, a2, a1, b0, b1);
+            if (kb + 3 >= KB) break;
+            step(kb + 3, a0, a2, b1, b0);
+            if (kb + 4 >= KB) break;
+            step(kb + 4, a1, a0, b0, b1);
+            if (kb + 5 >= KB) break;
+            step(kb + 5, a2, a1, b1, b0);
+            if (kb + 6 >= KB) break;
+        }
+        // epilogue (C and the rows' bookkeeping were loaded before the k loop)
         if (col < N) {
             for (int r = 0; r < 16; ++r) {
                 const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
