@@ -173,60 +173,73 @@ __device__ __forceinline__ uint32_t fold7(const v16i* acc, int r, uint32_t add, 
 
 // Product update C = delta * C + A . B (mod p) on int8 MFMA (C = dst columns
 // [col0, col0 + N); delta = 0 for the rows whose pivot column lies in
-// [fresh_lo, fresh_hi)).  Block: 4 waves over a 128 x 32 tile; wave v owns rows
-// [(4*bx + v)*32, +32) and the block's 32 columns, with the seven group
-// accumulators of one 32x32 MFMA block.  The B fragments of a k-block (4 digit
-// planes x 1 KB) are shared through LDS, double-buffered; A fragments (each
-// wave needs only its own rows) stay in registers.  Both are fetched two
-// k-blocks ahead of the MFMAs that use them, so that an L2 or HBM round trip
-// overlaps two k-blocks of MFMA work.  With grid.x = row tiles and a multiple of 8 of
-// them, all blocks of one row tile run on the same XCD, so each XCD's L2 holds
-// one eighth of the A operand.
-// Tiles of 128 rows x 32 columns, taken by the workgroups in turn (row tiles
-// fastest, so that concurrent workgroups share their B slices in L2): a grid of
-// one workgroup per tile, or fewer that loop, which leaves compute units free
-// for other work on the device.
+// [fresh_lo, fresh_hi)).  Block: 4 waves over a 64 x 64 tile; wave v owns the
+// 32 x 32 block (row block v & 1, column block v >> 1) with the seven group
+// accumulators of one 32x32 MFMA block.  A k-block's operands (two row blocks
+// and two column blocks, 4 digit planes x 1 KB each, 16 KB) go through LDS,
+// double-buffered, each fragment read by the two waves that share its rows or
+// columns: per output, half the A traffic of a 32-column tile.  They are
+// fetched two k-blocks ahead into staging registers, so that an L2 or HBM
+// round trip overlaps two k-blocks of MFMA work.  Tiles are taken by the
+// workgroups in turn, row tiles fastest, so that concurrent workgroups share
+// their B slices in L2; with a multiple of 8 row tiles all tiles of one row
+// range run on the same XCD, whose L2 then holds one eighth of the A operand.
+// The grid is one workgroup per tile, or fewer that loop, which leaves compute
+// units free for other work on the device.
 __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat dst, int64_t col0,
                                                               int64_t N, const int8_t* Afrag,
                                                               const int8_t* Bfrag, int32_t KB,
                                                               int32_t fresh_lo, int32_t fresh_hi,
                                                               double c32, int32_t skip_below) {
-    __shared__ v4i sB[2][4 * 64];  // 2 x 4 KB
+    // [buffer][A row block 0, 1 | B column block 0, 1][digit plane][lane]
+    __shared__ v4i sop[2][4][4][64];  // 2 x 16 KB
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t mtiles = ceil_div(w.m, 128);
-    const int64_t ntiles = mtiles * ceil_div(N, 32);
+    const int rg = wave & 1, cg = wave >> 1;
+    const int64_t mtiles = ceil_div(w.m, 64);
+    const int64_t nb = ceil_div(N, 32);  // column blocks with built B fragments
+    const int64_t ntiles = mtiles * ceil_div(N, 64);
+    const int last = KB - 1;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t rt = tile % mtiles, ct = tile / mtiles;
         if (skip_below > 0) {  // forward elimination: a tile of earlier pivot rows only is skipped
-            const int64_t row = (tile % mtiles) * 128 + (threadIdx.x >> 1);
+            const int64_t row = rt * 64 + (threadIdx.x >> 2);
             int keep = 0;
-            if ((threadIdx.x & 1) == 0 && row < w.m) keep = !earlier_pivot(w.rowcol[row], skip_below);
+            if ((threadIdx.x & 3) == 0 && row < w.m) keep = !earlier_pivot(w.rowcol[row], skip_below);
             if (__syncthreads_or(keep) == 0) continue;
         }
-        const int64_t rb = (tile % mtiles) * 4 + wave;
-        const int64_t cb = tile / mtiles;
-        const int8_t* bsrc = Bfrag + (cb * KB * 4 + wave) * 1024 + lane * 16;  // wave v moves plane v
-        const int8_t* asrc = Afrag + (rb * KB * 4) * 1024 + lane * 16;
+        // this wave moves digit planes 2 cg, 2 cg + 1 of row block rg of A and
+        // of column block rg of B (a column block past the built ones reads
+        // the last one: its products fall on columns >= N and are dropped)
+        const int64_t cbl = ct * 2 + rg < nb ? ct * 2 + rg : nb - 1;
+        const int8_t* asrc = Afrag + ((rt * 2 + rg) * KB * 4 + 2 * cg) * 1024 + lane * 16;
+        const int8_t* bsrc = Bfrag + (cbl * KB * 4 + 2 * cg) * 1024 + lane * 16;
+        auto fetch = [&](v4i (&st)[4], int kb) {
+            const int64_t o = (int64_t)kb * 4 * 1024;
+            st[0] = *(const v4i*)(asrc + o);
+            st[1] = *(const v4i*)(asrc + o + 1024);
+            st[2] = *(const v4i*)(bsrc + o);
+            st[3] = *(const v4i*)(bsrc + o + 1024);
+        };
+        auto stash = [&](int buf, const v4i (&st)[4]) {
+            sop[buf][rg][2 * cg][lane] = st[0];
+            sop[buf][rg][2 * cg + 1][lane] = st[1];
+            sop[buf][2 + rg][2 * cg][lane] = st[2];
+            sop[buf][2 + rg][2 * cg + 1][lane] = st[3];
+        };
         v16i acc[7];
         for (int g = 0; g < 7; ++g)
             for (int r = 0; r < 16; ++r) acc[g][r] = 0;
-        // Operands two k-blocks ahead: A in three register sets, B through two
-        // staging registers into the two LDS buffers.  The loop is unrolled by
-        // six so that every set has a fixed register name and no load in flight
-        // is ever copied (a copy would wait for it).  Every step issues its
-        // loads unconditionally (the last k-block again near the end) and is
-        // reached from the step before it only: the wait counts then see one
-        // sequence of loads and wait only for the k-block in use.
-        v4i a0[4], a1[4], a2[4], b0, b1;
-        const int last = KB - 1;
-        auto load_a = [&](v4i (&dst4)[4], int kb) {
-            for (int l = 0; l < 4; ++l) dst4[l] = *(const v4i*)(asrc + ((int64_t)kb * 4 + l) * 1024);
-        };
-        const v4i first = *(const v4i*)bsrc;
-        load_a(a0, 0);
-        b1 = *(const v4i*)(bsrc + (int64_t)min(1, last) * 4 * 1024);
-        load_a(a1, min(1, last));
-        sB[0][wave * 64 + lane] = first;  // the k loop's last barrier freed sB
-        __builtin_amdgcn_s_waitcnt(0);  // nothing in flight at the loop head
+        // Two staging sets, unrolled by two so that each has a fixed register
+        // name and no load in flight is ever copied (a copy would wait for
+        // it).  Every step issues its loads unconditionally (the last k-block
+        // again near the end) and is reached from the step before it only:
+        // the wait counts then see one sequence of loads and wait only for the
+        // k-block being stored.
+        v4i s0[4], s1[4];
+        fetch(s0, 0);
+        fetch(s1, min(1, last));
+        __builtin_amdgcn_s_waitcnt(0);
+        stash(0, s0);  // the k loop's last barrier freed the buffers
         __syncthreads();
         // The tile's C entries and its rows' bookkeeping, loaded now so that
         // their latency passes under the k loop.  32x32 accumulator layout:
@@ -234,7 +247,8 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
         // 0..15.  Addresses are clamped into the matrix so that every load is
         // issued unconditionally; out-of-range values are discarded in the
         // epilogue.
-        const int64_t col = cb * 32 + (lane & 31);
+        const int64_t rb = rt * 2 + rg;
+        const int64_t col = (ct * 2 + cg) * 32 + (lane & 31);
         const int64_t colc = col < N ? col : N - 1;
         int rcv[16];
         uint32_t cur[16];
@@ -244,37 +258,26 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
             rcv[r] = w.rowcol[rowc];
             cur[r] = __builtin_nontemporal_load(dst.M + rowc * dst.ld + col0 + colc);
         }
-        // step kb: issue k-block kb + 2 (A into fut, B into bload), multiply
-        // k-block kb (A in cur, B in LDS buffer kb & 1), store k-block kb + 1's B
-        // (staged in bstore one step earlier) into the other buffer
-        auto step = [&](int kb, v4i (&cur)[4], v4i (&fut)[4], v4i& bload, const v4i& bstore) {
-            const int nb = min(kb + 2, last);
-            bload = *(const v4i*)(bsrc + (int64_t)nb * 4 * 1024);
-            load_a(fut, nb);
-            const v4i* sb = sB[kb & 1];
-            v4i bf[4];
-            for (int lp = 0; lp < 4; ++lp) bf[lp] = sb[lp * 64 + lane];
+        // step kb: issue k-block kb + 2 into fut, multiply k-block kb (LDS
+        // buffer kb & 1), store k-block kb + 1 (staged in ready one step
+        // earlier) into the other buffer
+        auto step = [&](int kb, v4i (&fut)[4], const v4i (&ready)[4]) {
+            fetch(fut, min(kb + 2, last));
+            v4i af[4], bf[4];
+            for (int l = 0; l < 4; ++l) af[l] = sop[kb & 1][rg][l][lane];
+            for (int l = 0; l < 4; ++l) bf[l] = sop[kb & 1][2 + cg][l][lane];
             for (int l = 0; l < 4; ++l)
                 for (int lp = 0; lp < 4; ++lp)
-                    acc[l + lp] = __builtin_amdgcn_mfma_i32_32x32x32_i8(cur[l], bf[lp], acc[l + lp], 0, 0, 0);
-            if (kb + 1 < KB) sB[(kb + 1) & 1][wave * 64 + lane] = bstore;
+                    acc[l + lp] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[l], bf[lp], acc[l + lp], 0, 0, 0);
+            if (kb + 1 < KB) stash((kb + 1) & 1, ready);
             __syncthreads();
         };
-        for (int kb = 0;; kb += 6) {
-            step(kb, a0, a2, b0, b1);
+        for (int kb = 0;; kb += 2) {
+            step(kb, s0, s1);
             if (kb + 1 >= KB) break;
-            step(kb + 1, a1, a0, b1, b0);
+            step(kb + 1, s1, s0);
             if (kb + 2 >= KB) break;
-            step(kb + 2, a2, a1, b0, b1);
-            if (kb + 3 >= KB) break;
-            step(kb + 3, a0, a2, b1, b0);
-            if (kb + 4 >= KB) break;
-            step(kb + 4, a1, a0, b0, b1);
-            if (kb + 5 >= KB) break;
-            step(kb + 5, a2, a1, b1, b0);
-            if (kb + 6 >= KB) break;
         }
-        // epilogue (C and the rows' bookkeeping were loaded before the k loop)
         if (col < N) {
             for (int r = 0; r < 16; ++r) {
                 const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -579,7 +582,7 @@ hipError_t run_product(const PlainArgs& w, bool fp64, const int8_t* Af, const in
                            (const double*)Bf, KB, ceil_div(N, 16), fresh_lo, fresh_hi);
     } else {
         const double c32 = (double)((((uint64_t)1) << 32) % w.F.p);
-        const int64_t tiles = ceil_div(m, 128) * ceil_div(N, 32);
+        const int64_t tiles = ceil_div(m, 64) * ceil_div(N, 64);
         const int64_t grid = max_wgs > 0 && max_wgs < tiles ? max_wgs : tiles;
         hipLaunchKernelGGL(gemm_i8_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, w, dst, col0, N,
                            Af, Bf, KB, fresh_lo, fresh_hi, c32, skip_below);
