@@ -171,28 +171,56 @@ __device__ __forceinline__ uint32_t fold7(const v16i* acc, int r, uint32_t add, 
                   c32, F);
 }
 
+// One fragment row of 64 lanes x 16 bytes straight from global memory into
+// LDS (lane i's 16 bytes land at lds + 16 i); the wave's vector-memory count
+// covers it like a load.
+__device__ __forceinline__ void lds_dma16(const int8_t* g, v4i* lds) {
+    __builtin_amdgcn_global_load_lds((const void*)g, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+}
+
+// s_waitcnt with only the vector-memory count (expcnt and lgkmcnt at their
+// no-wait maxima): wait until at most n of this wave's vector-memory
+// operations are outstanding.
+template <int n>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(n >= 0 && n < 16, "vmcnt in the low field");
+    __builtin_amdgcn_s_waitcnt(n | (0x7 << 4) | (0xF << 8));
+}
+
+// A workgroup barrier that orders the compiler's memory accesses but adds no
+// wait of its own (the k loop waits for its LDS copies explicitly).
+__device__ __forceinline__ void bare_barrier() {
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    __asm__ volatile("" ::: "memory");
+}
+
 // Product update C = delta * C + A . B (mod p) on int8 MFMA (C = dst columns
 // [col0, col0 + N); delta = 0 for the rows whose pivot column lies in
 // [fresh_lo, fresh_hi)).  Block: 4 waves over a 64 x 64 tile; wave v owns the
 // 32 x 32 block (row block v & 1, column block v >> 1) with the seven group
 // accumulators of one 32x32 MFMA block.  A k-block's operands (two row blocks
 // and two column blocks, 4 digit planes x 1 KB each, 16 KB) go through LDS,
-// double-buffered, each fragment read by the two waves that share its rows or
-// columns: per output, half the A traffic of a 32-column tile.  They are
-// fetched two k-blocks ahead into staging registers, so that an L2 or HBM
-// round trip overlaps two k-blocks of MFMA work.  Tiles are taken by the
-// workgroups in turn, row tiles fastest, so that concurrent workgroups share
-// their B slices in L2; with a multiple of 8 row tiles all tiles of one row
-// range run on the same XCD, whose L2 then holds one eighth of the A operand.
-// The grid is one workgroup per tile, or fewer that loop, which leaves compute
-// units free for other work on the device.
+// each fragment read by the two waves that share its rows or columns: per
+// output, half the A traffic of a 32-column tile.  They are copied from global
+// memory straight into a ring of four LDS stages, three k-blocks ahead of the
+// MFMAs that use them, so that an L2 or HBM round trip overlaps three k-blocks
+// of MFMA work without holding registers.  Tiles are taken by the workgroups
+// in turn, row tiles fastest, so that concurrent workgroups share their B
+// slices in L2; with a multiple of 8 row tiles all tiles of one row range run
+// on the same XCD, whose L2 then holds one eighth of the A operand.  The grid
+// is one workgroup per tile, or fewer that loop, which leaves compute units
+// free for other work on the device.
 __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat dst, int64_t col0,
                                                               int64_t N, const int8_t* Afrag,
                                                               const int8_t* Bfrag, int32_t KB,
                                                               int32_t fresh_lo, int32_t fresh_hi,
                                                               double c32, int32_t skip_below) {
-    // [buffer][A row block 0, 1 | B column block 0, 1][digit plane][lane]
-    __shared__ v4i sop[2][4][4][64];  // 2 x 16 KB
+    // four stages, each [A row block 0, 1 | B column block 0, 1][digit plane][lane]
+    // (separate arrays, so that the compiler sees a stage's reads apart from
+    // the copies in flight into the others)
+    __shared__ v4i st0[4][4][64], st1[4][4][64], st2[4][4][64], st3[4][4][64];  // 4 x 16 KB
+    typedef v4i Stage[4][4][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int rg = wave & 1, cg = wave >> 1;
     const int64_t mtiles = ceil_div(w.m, 64);
@@ -201,52 +229,21 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
     const int last = KB - 1;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t rt = tile % mtiles, ct = tile / mtiles;
+        // (both barriers also wait for every copy of the previous tile and
+        // for every wave to be done with its stages)
         if (skip_below > 0) {  // forward elimination: a tile of earlier pivot rows only is skipped
             const int64_t row = rt * 64 + (threadIdx.x >> 2);
             int keep = 0;
             if ((threadIdx.x & 3) == 0 && row < w.m) keep = !earlier_pivot(w.rowcol[row], skip_below);
             if (__syncthreads_or(keep) == 0) continue;
+        } else {
+            __syncthreads();
         }
-        // this wave moves digit planes 2 cg, 2 cg + 1 of row block rg of A and
-        // of column block rg of B (a column block past the built ones reads
-        // the last one: its products fall on columns >= N and are dropped)
-        const int64_t cbl = ct * 2 + rg < nb ? ct * 2 + rg : nb - 1;
-        const int8_t* asrc = Afrag + ((rt * 2 + rg) * KB * 4 + 2 * cg) * 1024 + lane * 16;
-        const int8_t* bsrc = Bfrag + (cbl * KB * 4 + 2 * cg) * 1024 + lane * 16;
-        auto fetch = [&](v4i (&st)[4], int kb) {
-            const int64_t o = (int64_t)kb * 4 * 1024;
-            st[0] = *(const v4i*)(asrc + o);
-            st[1] = *(const v4i*)(asrc + o + 1024);
-            st[2] = *(const v4i*)(bsrc + o);
-            st[3] = *(const v4i*)(bsrc + o + 1024);
-        };
-        auto stash = [&](int buf, const v4i (&st)[4]) {
-            sop[buf][rg][2 * cg][lane] = st[0];
-            sop[buf][rg][2 * cg + 1][lane] = st[1];
-            sop[buf][2 + rg][2 * cg][lane] = st[2];
-            sop[buf][2 + rg][2 * cg + 1][lane] = st[3];
-        };
-        v16i acc[7];
-        for (int g = 0; g < 7; ++g)
-            for (int r = 0; r < 16; ++r) acc[g][r] = 0;
-        // Two staging sets, unrolled by two so that each has a fixed register
-        // name and no load in flight is ever copied (a copy would wait for
-        // it).  Every step issues its loads unconditionally (the last k-block
-        // again near the end) and is reached from the step before it only:
-        // the wait counts then see one sequence of loads and wait only for the
-        // k-block being stored.
-        v4i s0[4], s1[4];
-        fetch(s0, 0);
-        fetch(s1, min(1, last));
-        __builtin_amdgcn_s_waitcnt(0);
-        stash(0, s0);  // the k loop's last barrier freed the buffers
-        __syncthreads();
-        // The tile's C entries and its rows' bookkeeping, loaded now so that
-        // their latency passes under the k loop.  32x32 accumulator layout:
-        // lane L holds column L%32 and rows 8*(r/4) + 4*(L/32) + r%4 for r =
-        // 0..15.  Addresses are clamped into the matrix so that every load is
-        // issued unconditionally; out-of-range values are discarded in the
-        // epilogue.
+        // The tile's C entries and its rows' bookkeeping first (the k loop's
+        // first wait then covers them).  32x32 accumulator layout: lane L holds
+        // column L%32 and rows 8*(r/4) + 4*(L/32) + r%4 for r = 0..15.
+        // Addresses are clamped into the matrix so that every load is issued
+        // unconditionally; out-of-range values are discarded in the epilogue.
         const int64_t rb = rt * 2 + rg;
         const int64_t col = (ct * 2 + cg) * 32 + (lane & 31);
         const int64_t colc = col < N ? col : N - 1;
@@ -258,25 +255,53 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
             rcv[r] = w.rowcol[rowc];
             cur[r] = __builtin_nontemporal_load(dst.M + rowc * dst.ld + col0 + colc);
         }
-        // step kb: issue k-block kb + 2 into fut, multiply k-block kb (LDS
-        // buffer kb & 1), store k-block kb + 1 (staged in ready one step
-        // earlier) into the other buffer
-        auto step = [&](int kb, v4i (&fut)[4], const v4i (&ready)[4]) {
-            fetch(fut, min(kb + 2, last));
+        // this wave copies digit planes 2 cg, 2 cg + 1 of row block rg of A and
+        // of column block rg of B (a column block past the built ones reads
+        // the last one: its products fall on columns >= N and are dropped)
+        const int64_t cbl = ct * 2 + rg < nb ? ct * 2 + rg : nb - 1;
+        const int8_t* asrc = Afrag + ((rt * 2 + rg) * KB * 4 + 2 * cg) * 1024 + lane * 16;
+        const int8_t* bsrc = Bfrag + (cbl * KB * 4 + 2 * cg) * 1024 + lane * 16;
+        // Four copies per wave and k-block.  Every step copies one k-block,
+        // the last one again once the tile has no more (into a stage that is
+        // not read again), so that before each step exactly the copies of the
+        // two k-blocks after it may still be in flight.
+        auto copy = [&](Stage& st, int kb) {
+            const int64_t o = (int64_t)min(kb, last) * 4 * 1024;
+            lds_dma16(asrc + o, &st[rg][2 * cg][0]);
+            lds_dma16(asrc + o + 1024, &st[rg][2 * cg + 1][0]);
+            lds_dma16(bsrc + o, &st[2 + rg][2 * cg][0]);
+            lds_dma16(bsrc + o + 1024, &st[2 + rg][2 * cg + 1][0]);
+        };
+        copy(st0, 0);
+        copy(st1, 1);
+        copy(st2, 2);
+        v16i acc[7];
+        for (int g = 0; g < 7; ++g)
+            for (int r = 0; r < 16; ++r) acc[g][r] = 0;
+        // step kb: wait for this wave's copies of k-block kb (at most those of
+        // kb + 1 and kb + 2 outstanding), barrier (every wave's copies of kb
+        // have landed, and every wave is done with stage kb - 1), copy k-block
+        // kb + 3 into stage kb - 1, multiply k-block kb
+        auto step = [&](const Stage& cur_st, Stage& next_st, int kb) {
+            wait_vm<8>();
+            bare_barrier();
+            copy(next_st, kb + 3);
             v4i af[4], bf[4];
-            for (int l = 0; l < 4; ++l) af[l] = sop[kb & 1][rg][l][lane];
-            for (int l = 0; l < 4; ++l) bf[l] = sop[kb & 1][2 + cg][l][lane];
+            for (int l = 0; l < 4; ++l) af[l] = cur_st[rg][l][lane];
+            for (int l = 0; l < 4; ++l) bf[l] = cur_st[2 + cg][l][lane];
             for (int l = 0; l < 4; ++l)
                 for (int lp = 0; lp < 4; ++lp)
                     acc[l + lp] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[l], bf[lp], acc[l + lp], 0, 0, 0);
-            if (kb + 1 < KB) stash((kb + 1) & 1, ready);
-            __syncthreads();
         };
-        for (int kb = 0;; kb += 2) {
-            step(kb, s0, s1);
+        for (int kb = 0;; kb += 4) {
+            step(st0, st3, kb);
             if (kb + 1 >= KB) break;
-            step(kb + 1, s1, s0);
+            step(st1, st0, kb + 1);
             if (kb + 2 >= KB) break;
+            step(st2, st1, kb + 2);
+            if (kb + 3 >= KB) break;
+            step(st3, st2, kb + 3);
+            if (kb + 4 >= KB) break;
         }
         if (col < N) {
             for (int r = 0; r < 16; ++r) {
