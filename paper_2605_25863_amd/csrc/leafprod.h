@@ -18,20 +18,24 @@ __device__ __forceinline__ bool earlier_pivot(int32_t rowcol, int32_t skip_below
     return rowcol >= 0 && rowcol < skip_below;
 }
 
-// sum_s 256^s S_s reduced mod p, plus `add` (a residue, or 0): T_lo and T_hi
-// are exact in FP64; each is folded into [-p, 2p), T_hi is multiplied by
-// c32 = 2^32 mod p exactly (FMA split), and the sum is reduced once more.
+// sum_s 256^s S_s reduced mod p, plus `add` (a residue, or 0).  With K <= 512
+// and |digit| <= 128 every |S_s| < 2^25, so T_lo = S_0 + ... + 2^24 S_3 (below
+// 2^50) and T_hi = S_4 + 256 S_5 + 65536 S_6 (below 2^40) are exact in FP64.
+// T_hi times c32 = 2^32 mod p (below 2^71) is split exactly by an FMA into its
+// rounded head h and an integer tail l (|l| <= 2^18); h is reduced once into
+// [-p, 2p) (h / p < 2^40, so the floor of h / p is off by at most one and the
+// FMA's difference, an integer below 2p, is exact).  The sum of that, l, T_lo
+// and `add` stays an integer below 2^51, and one more reduction with two
+// corrections gives the residue.
 __device__ __forceinline__ uint32_t fold7s(int32_t s0, int32_t s1, int32_t s2, int32_t s3, int32_t s4,
                                            int32_t s5, int32_t s6, uint32_t add, double c32,
                                            const FieldConst& F) {
     const double lo = __fma_rn(16777216.0, (double)s3,
                                __fma_rn(65536.0, (double)s2, __fma_rn(256.0, (double)s1, (double)s0)));
     const double hi = __fma_rn(65536.0, (double)s6, __fma_rn(256.0, (double)s5, (double)s4));
-    const double rlo = __fma_rn(-floor(lo * F.pinv), F.dp, lo);
-    const double rhi = __fma_rn(-floor(hi * F.pinv), F.dp, hi);
-    const double h = rhi * c32;
-    const double l = __fma_rn(rhi, c32, -h);
-    const double t = __fma_rn(-floor(h * F.pinv), F.dp, h) + l + rlo + (double)add;  // (-3p, 5p)
+    const double h = hi * c32;
+    const double l = __fma_rn(hi, c32, -h);
+    const double t = __fma_rn(-floor(h * F.pinv), F.dp, h) + l + lo + (double)add;
     double r2 = __fma_rn(-floor(t * F.pinv), F.dp, t);
     if (r2 < 0.0) r2 += F.dp;
     if (r2 >= F.dp) r2 -= F.dp;
