@@ -311,6 +311,9 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
                 dst.M[row * dst.ld + col0 + col] = fold7(acc, r, fresh ? 0u : cur[r], c32, w.F);
             }
         }
+        // the copies of the last steps (a k-block copied again into stages no
+        // longer read) must land before this workgroup's LDS can be handed on
+        wait_vm<0>();
     }
 }
 
