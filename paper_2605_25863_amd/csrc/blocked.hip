@@ -247,13 +247,29 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
         const int64_t rb = rt * 2 + rg;
         const int64_t col = (ct * 2 + cg) * 32 + (lane & 31);
         const int64_t colc = col < N ? col : N - 1;
+        // Lane rows row0 + 8 (r / 4) + r % 4: four group bases 8 rows apart and
+        // offsets of 0..3 rows give every address with additions only (no
+        // 64-bit multiply per entry).
+        const int64_t row0 = rb * 32 + 4 * (lane >> 5);
+        const int64_t ld = dst.ld, ld2 = ld + ld, ld3 = ld2 + ld, ld8 = ld << 3;
+        const int64_t roff[4] = {0, ld, ld2, ld3};
         int rcv[16];
         uint32_t cur[16];
-        for (int r = 0; r < 16; ++r) {
-            const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            const int64_t rowc = row < w.m ? row : w.m - 1;
-            rcv[r] = w.rowcol[rowc];
-            cur[r] = __builtin_nontemporal_load(dst.M + rowc * dst.ld + col0 + colc);
+        if (rb * 32 + 32 <= w.m) {  // (uniform) every row of the block is inside the matrix
+            const uint32_t* g = dst.M + row0 * ld + col0 + colc;
+            const int32_t* rc = w.rowcol + row0;
+            for (int q = 0; q < 4; ++q, g += ld8, rc += 8)
+                for (int e = 0; e < 4; ++e) {
+                    rcv[4 * q + e] = rc[e];
+                    cur[4 * q + e] = __builtin_nontemporal_load(g + roff[e]);
+                }
+        } else {
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = row0 + 8 * (r >> 2) + (r & 3);
+                const int64_t rowc = row < w.m ? row : w.m - 1;
+                rcv[r] = w.rowcol[rowc];
+                cur[r] = __builtin_nontemporal_load(dst.M + rowc * ld + col0 + colc);
+            }
         }
         // this wave copies digit planes 2 cg, 2 cg + 1 of row block rg of A and
         // of column block rg of B (a column block past the built ones reads
@@ -304,12 +320,14 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
             if (kb + 4 >= KB) break;
         }
         if (col < N) {
-            for (int r = 0; r < 16; ++r) {
-                const int64_t row = rb * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                if (row >= w.m || earlier_pivot(rcv[r], skip_below)) continue;
-                const bool fresh = rcv[r] >= fresh_lo && rcv[r] < fresh_hi;  // a pivot row of this panel
-                dst.M[row * dst.ld + col0 + col] = fold7(acc, r, fresh ? 0u : cur[r], c32, w.F);
-            }
+            uint32_t* g = dst.M + row0 * ld + col0 + col;
+            for (int q = 0; q < 4; ++q, g += ld8)
+                for (int e = 0; e < 4; ++e) {
+                    const int r = 4 * q + e;
+                    if (row0 + 8 * q + e >= w.m || earlier_pivot(rcv[r], skip_below)) continue;
+                    const bool fresh = rcv[r] >= fresh_lo && rcv[r] < fresh_hi;  // a pivot row of this panel
+                    g[roff[e]] = fold7(acc, r, fresh ? 0u : cur[r], c32, w.F);
+                }
         }
         // the copies of the last steps (a k-block copied again into stages no
         // longer read) must land before this workgroup's LDS can be handed on
