@@ -98,9 +98,9 @@ __device__ __forceinline__ uint32_t xs_value(const PlainArgs& w, Mat src, int32_
 // B operand: X_S split into digits, stored in the lane order of the 32x32x32
 // int8 MFMA: fragment (cb, kb, l') is 64 lanes x 16 bytes; lane L holds digit
 // l' of column cb*32 + L%32 and rows k = kb*32 + 16*(L/32) + i, i = 0..15.
-__global__ void build_b_kernel(PlainArgs w, Mat src, int32_t gslot0, int32_t wj, int64_t col0,
-                               int64_t N, int64_t inj0, int32_t KB, int64_t NB, int8_t* Bfrag) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void build_b_at(const PlainArgs& w, Mat src, int32_t gslot0, int32_t wj, int64_t col0,
+                                           int64_t N, int64_t inj0, int32_t KB, int64_t NB, int8_t* Bfrag,
+                                           int64_t gid) {
     if (gid >= NB * KB * 64) return;
     const int L = (int)(gid & 63);
     const int64_t t = gid >> 6;
@@ -126,9 +126,8 @@ __global__ void build_b_kernel(PlainArgs w, Mat src, int32_t gslot0, int32_t wj,
 // A operand: the transform block E = ebuf columns [ecol0, ecol0 + wj), split
 // into digits, in MFMA lane order: fragment (rb, kb, l) is 64 lanes x 16 bytes;
 // lane L holds row rb*32 + L%32 and k = kb*32 + 16*(L/32) + i.
-__global__ void build_a_kernel(PlainArgs w, Mat ebuf, int64_t ecol0, int32_t wj, int32_t KB,
-                               int64_t MB, int8_t* Afrag) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void build_a_at(const PlainArgs& w, Mat ebuf, int64_t ecol0, int32_t wj, int32_t KB,
+                                           int64_t MB, int8_t* Afrag, int64_t gid) {
     if (gid >= MB * KB * 64) return;
     const int L = (int)(gid & 63);
     const int64_t t = gid >> 6;
@@ -440,9 +439,8 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(PlainArgs w, Mat dst
 
 // Write columns [0, width) of src into dst columns [d0, d0 + width); pivot
 // columns (bookkeeping columns gcol0 + js) become unit vectors.
-__global__ void panel_writeback_kernel(PlainArgs w, Mat src, Mat dst, int64_t d0, int32_t width,
-                                       int32_t gcol0, int32_t skip_below) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void writeback_at(const PlainArgs& w, Mat src, Mat dst, int64_t d0, int32_t width,
+                                             int32_t gcol0, int32_t skip_below, int64_t gid) {
     if (gid >= (int64_t)w.m * width) return;
     const int64_t r = gid / width;
     if (earlier_pivot(w.rowcol[r], skip_below)) return;
@@ -452,6 +450,31 @@ __global__ void panel_writeback_kernel(PlainArgs w, Mat src, Mat dst, int64_t d0
     if (s >= 0) v = (w.pivrow[s] == r) ? 1u : 0u;
     else v = src.M[r * src.ld + js];
     dst.M[r * dst.ld + d0 + js] = v;
+}
+
+__global__ void panel_writeback_kernel(PlainArgs w, Mat src, Mat dst, int64_t d0, int32_t width,
+                                       int32_t gcol0, int32_t skip_below) {
+    writeback_at(w, src, dst, d0, width, gcol0, skip_below, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// The int8 trailing product's operands and the panel's write-back in one
+// launch: workgroups [0, gb) build B, [gb, gb + ga) build A, the rest write the
+// reduced panel back into W.  The three touch disjoint data (B reads the pivot
+// rows right of the panel, A the transform block of PR, the write-back the
+// panel block of PR and the panel's columns of W, which neither product
+// reads), so they run side by side instead of as three dependent launches.
+__global__ void panel_operands_kernel(PlainArgs w, Mat W, Mat PR, int32_t j0, int32_t wj, int64_t col0,
+                                      int64_t N, int32_t KB, int64_t NB, int64_t MB, int8_t* Afrag,
+                                      int8_t* Bfrag, int32_t skip_below, int32_t gb, int32_t ga) {
+    const int64_t b = blockIdx.x;
+    if (b < gb) {
+        build_b_at(w, W, j0, wj, col0, N, (int64_t)-1, KB, NB, Bfrag, b * blockDim.x + threadIdx.x);
+    } else if (b < gb + ga) {
+        build_a_at(w, PR, (int64_t)wj, wj, KB, MB, Afrag, (b - gb) * blockDim.x + threadIdx.x);
+    } else {
+        writeback_at(w, PR, W, (int64_t)j0, wj, j0, skip_below,
+                     (b - gb - ga) * blockDim.x + threadIdx.x);
+    }
 }
 
 // Back-substitution after forward elimination (the solve).  The pivot row q of
@@ -639,10 +662,12 @@ hipError_t run_product(const PlainArgs& w, bool fp64, const int8_t* Af, const in
 
 // Operands of the trailing update of panel [j0, j0 + wj) over dst columns
 // [col0, col0 + N): A = PR's transform block (columns [wj, 2 wj)), B = X_S,
-// the pivot rows of bookkeeping columns [j0, j0 + wj) read from dst.  Returns
-// the number of k-blocks.
+// the pivot rows of bookkeeping columns [j0, j0 + wj) read from dst.  On the
+// int8 path the same launch also writes the reduced panel back into dst.
+// Returns the number of k-blocks.
 int32_t trailing_operands(const Blocked& b, const PlainArgs& w, bool fp64, Mat dst, int32_t j0,
-                          int32_t wj, int64_t col0, int64_t N, hipStream_t s, LaunchTimer& lt) {
+                          int32_t wj, int64_t col0, int64_t N, int32_t skip_below, hipStream_t s,
+                          LaunchTimer& lt) {
     const int64_t m = w.m;
     lt.before(LINAC_KERNEL_OPERANDS);
     int32_t KB;
@@ -658,10 +683,10 @@ int32_t trailing_operands(const Blocked& b, const PlainArgs& w, bool fp64, Mat d
         KB = (int32_t)ceil_div(wj, 32);
         const int64_t NB = ceil_div(N, 32);
         const int64_t MB = ceil_div(m, 128) * 4;
-        hipLaunchKernelGGL(build_b_kernel, dim3((unsigned)ceil_div(NB * KB * 64, 256)), dim3(256), 0,
-                           s, w, dst, j0, wj, col0, N, (int64_t)-1, KB, NB, b.Bfrag);
-        hipLaunchKernelGGL(build_a_kernel, dim3((unsigned)ceil_div(MB * KB * 64, 256)), dim3(256), 0,
-                           s, w, b.PR, (int64_t)wj, wj, KB, MB, b.Afrag);
+        const int32_t gb = (int32_t)ceil_div(NB * KB * 64, 256), ga = (int32_t)ceil_div(MB * KB * 64, 256);
+        const int32_t gw = (int32_t)ceil_div(m * wj, 256);
+        hipLaunchKernelGGL(panel_operands_kernel, dim3((unsigned)(gb + ga + gw)), dim3(256), 0, s, w, dst,
+                           b.PR, j0, wj, col0, N, KB, NB, MB, b.Afrag, b.Bfrag, skip_below, gb, ga);
     }
     lt.after();
     return KB;
@@ -843,7 +868,7 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
         if (N > 0) {
             if (opts && opts->ev_begin && outer_products == 0) (void)hipEventRecord(opts->ev_begin, s);
             const int64_t col0 = (int64_t)j0 + wj;
-            const int32_t KB = trailing_operands(b, w, fp64, Wm, j0, wj, col0, N, s, lt);
+            const int32_t KB = trailing_operands(b, w, fp64, Wm, j0, wj, col0, N, skip_below, s, lt);
             e = hipGetLastError();
             // the next panel's columns now, the rest on the side stream
             const int64_t n1 = lookahead && N > panel ? panel : N;
@@ -862,9 +887,11 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
             }
             ++outer_products;
         }
-        hipLaunchKernelGGL(panel_writeback_kernel, dim3((unsigned)ceil_div(m * wj, 256)), dim3(256),
-                           0, s, w, b.PR, Wm, (int64_t)j0, wj, j0, skip_below);
-        if (e == hipSuccess) e = hipGetLastError();
+        if (fp64 || N <= 0) {  // (the int8 operand launch above wrote the panel back already)
+            hipLaunchKernelGGL(panel_writeback_kernel, dim3((unsigned)ceil_div(m * wj, 256)), dim3(256),
+                               0, s, w, b.PR, Wm, (int64_t)j0, wj, j0, skip_below);
+            if (e == hipSuccess) e = hipGetLastError();
+        }
     }
     if (t2_pending) {
         const hipError_t e2 = hipStreamWaitEvent(s, ev_t2, 0);
