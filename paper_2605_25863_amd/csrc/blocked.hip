@@ -788,6 +788,7 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
             // block up to this leaf's pivots (beyond it every row is still zero)
             const int64_t N = (int64_t)wj + wl;
             int8_t* yf = fp64 || !select_y ? nullptr : b.Yfrag;
+            const bool piped = pipeline && l0 + kLeaf < wj;  // (see the product below)
             lt.before(LINAC_KERNEL_SELECT);
             e = leaf_select(w, b.leaf, b.PR.M, b.PR.ld, l0, wl, wj, j0 + l0, parity, N, yf, !fp64, s,
                             first_done ? kSelectRest : kSelectFirst | kSelectRest);
@@ -824,13 +825,15 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
                 pa.yfrag = b.Yfrag;
                 pa.skip_below = skip_below;
                 pa.chunk = b.leaf.chunk;
+                pa.ymode = piped ? 1 : 0;  // (a chunk launch stores the Y it forms)
+                pa.ystore = b.Yfrag;
 #define LEAF_PRODUCT(LB, MODE)                                                                      \
     hipLaunchKernelGGL((leaf_product_i8_kernel<LB, MODE>),                                          \
                        dim3((unsigned)(MODE == kLeafChunk ? 1 : ceil_div(m, 64)),                   \
                             (unsigned)ceil_div(N, 16 * (LB))),                                      \
                        dim3(kThreads), 0, s, pa)
                 const int32_t l1 = l0 + kLeaf;  // the next leaf of this panel, if any
-                if (pipeline && l1 < wj) {
+                if (piped) {
                     // The next leaf's first chunk is updated first; then one launch
                     // runs the next leaf's first selection (on that chunk) beside the
                     // update of the other rows.
@@ -840,9 +843,11 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
                     lt.after();
                     e = hipGetLastError();
                     if (e != hipSuccess) break;
+                    LeafProdArgs pr = pa;
+                    pr.ymode = 2;  // Y built by the selection or stored by the chunk launch
                     lt.before(LINAC_KERNEL_LEAF_FUSED);
                     e = leaf_fused(w, b.leaf, b.PR.M, b.PR.ld, l1, wl1, wj, j0 + l1, parity ^ 1,
-                                   (int64_t)wj + wl1, yf, pa, leaf_blocks, s);
+                                   (int64_t)wj + wl1, yf, pr, leaf_blocks, s);
                     lt.after();
                     first_done = true;
                 } else {

@@ -206,6 +206,14 @@ struct LeafProdArgs {
     const int8_t* yfrag;
     int32_t skip_below;
     int32_t* chunk;
+    // Y's source: 0 = yfrag when the selection built it (out->yready), else
+    // every workgroup forms its own slices from the saved pivot rows; 1 (the
+    // chunk launch of a pipelined leaf, one workgroup per column group) = as 0,
+    // and slices formed here are also stored in ystore (= yfrag); 2 (the
+    // launch of the other rows after that chunk launch) = yfrag, built by the
+    // selection or stored by the chunk launch
+    int32_t ymode;
+    int8_t* ystore;
 };
 
 int32_t leaf_nodes(int64_t m);

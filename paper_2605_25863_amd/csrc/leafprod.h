@@ -61,13 +61,16 @@ constexpr int kLeafAll = 0, kLeafChunk = 1, kLeafRest = 2;
 // registers).
 // Operand lanes of the 16x16x32 int8 MFMA: A(i, k) in lane i + 16 (k / 8), byte
 // k % 8; B(k, j) in lane j + 16 (k / 8), byte k % 8; C(i, j) in lane j + 16 (i /
-// 4), register i % 4.  Y's fragments come from the selection when it built
-// them (out->yready; plane l of 16-column block b at (4 b + l) * 512 bytes, 8
-// per lane); otherwise every block forms its own slices of Y (32 x 16 x t
-// products in FP64 with exact 16-bit splits) from the rows the selection
-// saved.  The leaf's pivot columns are not written (their unit-vector form is
-// implied by the bookkeeping), so no multiplier is overwritten while other
-// blocks still read it.  The launch also builds the next leaf's candidate list
+// 4), register i % 4.  Y's fragments (plane l of 16-column block b at
+// (4 b + l) * 512 bytes, 8 per lane) come from the selection when it built
+// them (out->yready: the first chunk decided the leaf); otherwise every block
+// forms its own slices of Y (32 x 16 x t products in FP64 with exact 16-bit
+// splits) from the rows the selection saved.  In a pipelined leaf the chunk
+// launch (ymode 1, one workgroup per column group) stores the slices it forms,
+// and the launch of the other rows (ymode 2) reads them instead of forming
+// its own in every workgroup.  The leaf's pivot columns are not written (their
+// unit-vector form is implied by the bookkeeping), so no multiplier is
+// overwritten while other blocks still read it.  The launch also builds the next leaf's candidate list
 // (one entry per thread).
 // kLeafBlocks: 16-column blocks per workgroup (a tuned shape: 2, 3, 6 or 9;
 // the multipliers' digits are built once and reused across the blocks, and
@@ -156,7 +159,7 @@ __device__ __forceinline__ void leaf_product_block(const LeafProdArgs& a, int64_
     // All loads below use addresses clamped into their arrays and are issued
     // unconditionally (values out of range are discarded afterwards), so they
     // overlap instead of waiting one by one.
-    const bool yready = out->yready != 0;
+    const bool yready = a.ymode == 2 || out->yready != 0;
     // multipliers of this lane's A row (row 16 rb + L%16, k = 8 (L/16) + e)
     const int64_t arow = row_at(rb * 16 + (lane & 15));
     const int64_t arowc = arow < w.m ? arow : w.m - 1;
@@ -268,6 +271,8 @@ __device__ __forceinline__ void leaf_product_block(const LeafProdArgs& a, int64_
             }
             __syncthreads();
             for (int l = 0; l < 4; ++l) __builtin_memcpy(&bf[l], sB[l][lane], 8);
+            if (a.ymode == 1 && wave == 0)  // the slice for the launch of the other rows
+                for (int l = 0; l < 4; ++l) *(long*)(a.ystore + (cb * 4 + l) * 512 + lane * 8) = bf[l];
         }
         v4i acc[7];
         for (int g = 0; g < 7; ++g)
