@@ -209,12 +209,16 @@ __device__ __forceinline__ void bare_barrier() {
 // slices in L2; with a multiple of 8 row tiles all tiles of one row range run
 // on the same XCD, whose L2 then holds one eighth of the A operand.  The grid
 // is one workgroup per tile, or fewer that loop, which leaves compute units
-// free for other work on the device.
+// free for other work on the device.  With out.M set the results go to out
+// (columns from 0) instead of dst, and out's columns [ezero, ezero + N) of
+// the same rows are set to zero: the next panel's columns written straight
+// into the panel buffer, with its transform block cleared.
 __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat dst, int64_t col0,
                                                               int64_t N, const int8_t* Afrag,
                                                               const int8_t* Bfrag, int32_t KB,
                                                               int32_t fresh_lo, int32_t fresh_hi,
-                                                              double c32, int32_t skip_below) {
+                                                              double c32, int32_t skip_below, Mat out,
+                                                              int32_t ezero) {
     // four stages, each [A row block 0, 1 | B column block 0, 1][digit plane][lane]
     // (separate arrays, so that the compiler sees a stage's reads apart from
     // the copies in flight into the others)
@@ -318,7 +322,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
             step(st3, st2, kb + 3);
             if (kb + 4 >= KB) break;
         }
-        if (col < N) {
+        if (col < N && !out.M) {
             uint32_t* g = dst.M + row0 * ld + col0 + col;
             for (int q = 0; q < 4; ++q, g += ld8)
                 for (int e = 0; e < 4; ++e) {
@@ -327,6 +331,21 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
                     const bool fresh = rcv[r] >= fresh_lo && rcv[r] < fresh_hi;  // a pivot row of this panel
                     g[roff[e]] = fold7(acc, r, fresh ? 0u : cur[r], c32, w.F);
                 }
+        } else if (col < N) {
+            // (a pivot row of this panel also keeps its entries in dst: in
+            // forward elimination it takes no part in the next panel, whose
+            // write-back then skips it, and back-substitution reads them there)
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = row0 + 8 * (r >> 2) + (r & 3);
+                if (row >= w.m) continue;
+                uint32_t* o = out.M + row * out.ld;
+                o[ezero + col] = 0u;
+                if (earlier_pivot(rcv[r], skip_below)) continue;
+                const bool fresh = rcv[r] >= fresh_lo && rcv[r] < fresh_hi;  // a pivot row of this panel
+                const uint32_t v = fold7(acc, r, fresh ? 0u : cur[r], c32, w.F);
+                o[col] = v;
+                if (fresh) dst.M[row * ld + col0 + col] = v;
+            }
         }
         // the copies of the last steps (a k-block copied again into stages no
         // longer read) must land before this workgroup's LDS can be handed on
@@ -642,7 +661,7 @@ size_t carve_blocked(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, B
 hipError_t run_product(const PlainArgs& w, bool fp64, const int8_t* Af, const int8_t* Bf, Mat dst,
                        int64_t col0, int64_t N, int32_t KB, int32_t fresh_lo, int32_t fresh_hi,
                        hipStream_t s, LaunchTimer& lt, int kind, int64_t max_wgs = 0,
-                       int32_t skip_below = 0) {
+                       int32_t skip_below = 0, Mat out = Mat{nullptr, 0}, int32_t ezero = 0) {
     const int64_t m = w.m;
     lt.before(kind, s);
     if (fp64) {
@@ -654,7 +673,7 @@ hipError_t run_product(const PlainArgs& w, bool fp64, const int8_t* Af, const in
         const int64_t tiles = ceil_div(m, 64) * ceil_div(N, 64);
         const int64_t grid = max_wgs > 0 && max_wgs < tiles ? max_wgs : tiles;
         hipLaunchKernelGGL(gemm_i8_kernel, dim3((unsigned)grid), dim3(kThreads), 0, s, w, dst, col0, N,
-                           Af, Bf, KB, fresh_lo, fresh_hi, c32, skip_below);
+                           Af, Bf, KB, fresh_lo, fresh_hi, c32, skip_below, out, ezero);
     }
     lt.after();
     return hipGetLastError();
@@ -773,13 +792,16 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
     // next leaf's first selection, which overlaps them.
     const bool pipeline = !fp64 && leaf_pipeline;
     bool t2_pending = false;
+    bool pr_ready = false;  // the next panel's columns are in PR already
     if (e == hipSuccess) e = leaf_init(b.leaf, (int32_t)m, s);
     int32_t leaf_index = 0;
     for (int32_t j0 = 0; j0 < n && e == hipSuccess; j0 += panel) {
         const int32_t wj = (int32_t)(n - j0 < panel ? n - j0 : panel);
         const int32_t skip_below = forward ? j0 : 0;
-        hipLaunchKernelGGL(panel_extract_kernel, dim3(tiles, (unsigned)ceil_div(b.PR.ld, 256)),
-                           dim3(kThreads), 0, s, w.m, Wm, (int64_t)j0, b.PR, wj);
+        if (!pr_ready)  // (else the previous trailing product wrote this panel into PR)
+            hipLaunchKernelGGL(panel_extract_kernel, dim3(tiles, (unsigned)ceil_div(b.PR.ld, 256)),
+                               dim3(kThreads), 0, s, w.m, Wm, (int64_t)j0, b.PR, wj);
+        pr_ready = false;
         bool first_done = false;  // this leaf's first selection already ran (pipelined)
         for (int32_t l0 = 0; l0 < wj && e == hipSuccess; l0 += kLeaf) {
             const int32_t wl = wj - l0 < kLeaf ? wj - l0 : kLeaf;
@@ -875,12 +897,23 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
             const int64_t col0 = (int64_t)j0 + wj;
             const int32_t KB = trailing_operands(b, w, fp64, Wm, j0, wj, col0, N, skip_below, s, lt);
             e = hipGetLastError();
-            // the next panel's columns now, the rest on the side stream
-            const int64_t n1 = lookahead && N > panel ? panel : N;
+            // The next panel's columns now, the rest on the side stream.  On the
+            // int8 path the next panel's columns go straight into PR (with its
+            // transform block cleared), so that panel needs no copy; that takes
+            // a width that keeps the remaining B fragments 32-aligned.
+            const int64_t wnext = n - (j0 + wj) < panel ? n - (j0 + wj) : panel;
+            const bool direct = !fp64 && wnext > 0 && wnext % 32 == 0;
+            const int64_t n1 = direct ? wnext : (lookahead && N > panel ? panel : N);
             if (e == hipSuccess)
                 e = run_product(w, fp64, b.Afrag, b.Bfrag, Wm, col0, n1, KB, j0, j0 + wj, s, lt,
-                                LINAC_KERNEL_TRAIL_PRODUCT, 0, skip_below);
-            if (e == hipSuccess && n1 < N) {
+                                LINAC_KERNEL_TRAIL_PRODUCT, 0, skip_below,
+                                direct ? b.PR : Mat{nullptr, 0}, (int32_t)wnext);
+            pr_ready = direct && e == hipSuccess;
+            if (e == hipSuccess && n1 < N && !lookahead) {  // the rest on this stream
+                e = run_product(w, fp64, b.Afrag, b.Bfrag + (n1 / 32) * KB * 4 * 1024, Wm, col0 + n1,
+                                N - n1, KB, j0, j0 + wj, s, lt, LINAC_KERNEL_TRAIL_PRODUCT, 0,
+                                skip_below);
+            } else if (e == hipSuccess && n1 < N) {
                 e = hipEventRecord(ev_t1, s);
                 if (e == hipSuccess) e = hipStreamWaitEvent(side, ev_t1, 0);
                 if (e == hipSuccess)
