@@ -34,6 +34,8 @@
 // than A.  For p < 2^21 the centred residues are below 2^20 and the product
 // can instead run on FP64 MFMA directly: every partial sum is below K * 2^40,
 // exact while K <= 8192.
+#include <type_traits>
+
 #include "internal.h"
 #include "leafprod.h"
 
@@ -164,6 +166,10 @@ __device__ __forceinline__ void build_a_at(const PlainArgs& w, Mat ebuf, int64_t
     }
 }
 
+// k-blocks of 32 in one trailing product: panels are at most 512 columns wide
+// (the fold is exact up to K = 512)
+constexpr int kMaxKB = 16;
+
 __device__ __forceinline__ uint32_t fold7(const v16i* acc, int r, uint32_t add, double c32,
                                           const FieldConst& F) {
     return fold7s(acc[0][r], acc[1][r], acc[2][r], acc[3][r], acc[4][r], acc[5][r], acc[6][r], add,
@@ -182,8 +188,8 @@ __device__ __forceinline__ void lds_dma16(const int8_t* g, v4i* lds) {
 // operations are outstanding.
 template <int n>
 __device__ __forceinline__ void wait_vm() {
-    static_assert(n >= 0 && n < 16, "vmcnt in the low field");
-    __builtin_amdgcn_s_waitcnt(n | (0x7 << 4) | (0xF << 8));
+    static_assert(n >= 0 && n < 64, "six-bit vmcnt");
+    __builtin_amdgcn_s_waitcnt((n & 15) | (0x7 << 4) | (0xF << 8) | ((n >> 4) << 14));
 }
 
 // A workgroup barrier that orders the compiler's memory accesses but adds no
@@ -204,7 +210,10 @@ __device__ __forceinline__ void bare_barrier() {
 // output, half the A traffic of a 32-column tile.  They are copied from global
 // memory straight into a ring of four LDS stages, three k-blocks ahead of the
 // MFMAs that use them, so that an L2 or HBM round trip overlaps three k-blocks
-// of MFMA work without holding registers.  Tiles are taken by the workgroups
+// of MFMA work without holding registers.  A tile's C entries are loaded
+// after its first k-block, behind the copies, so that the first step waits
+// for operands only, and a workgroup retires without waiting for its stores
+// to complete.  Tiles are taken by the workgroups
 // in turn, row tiles fastest, so that concurrent workgroups share their B
 // slices in L2; with a multiple of 8 row tiles all tiles of one row range run
 // on the same XCD, whose L2 then holds one eighth of the A operand.  The grid
@@ -232,8 +241,11 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
     const int last = KB - 1;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t rt = tile % mtiles, ct = tile / mtiles;
-        // (both barriers also wait for every copy of the previous tile and
-        // for every wave to be done with its stages)
+        // The stores of the previous tile (if this workgroup had one) first:
+        // the k steps below count the loads in flight, and stores need not
+        // complete in order with loads.  (The barriers below also wait for
+        // every wave to be done with its stages.)
+        wait_vm<0>();
         if (skip_below > 0) {  // forward elimination: a tile of earlier pivot rows only is skipped
             const int64_t row = rt * 64 + (threadIdx.x >> 2);
             int keep = 0;
@@ -256,22 +268,16 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
         const int64_t row0 = rb * 32 + 4 * (lane >> 5);
         const int64_t ld = dst.ld, ld2 = ld + ld, ld3 = ld2 + ld, ld8 = ld << 3;
         const int64_t roff[4] = {0, ld, ld2, ld3};
+        const bool full = rb * 32 + 32 <= w.m;  // (uniform) every row of the block is inside the matrix
         int rcv[16];
-        uint32_t cur[16];
-        if (rb * 32 + 32 <= w.m) {  // (uniform) every row of the block is inside the matrix
-            const uint32_t* g = dst.M + row0 * ld + col0 + colc;
+        if (full) {
             const int32_t* rc = w.rowcol + row0;
-            for (int q = 0; q < 4; ++q, g += ld8, rc += 8)
-                for (int e = 0; e < 4; ++e) {
-                    rcv[4 * q + e] = rc[e];
-                    cur[4 * q + e] = __builtin_nontemporal_load(g + roff[e]);
-                }
+            for (int q = 0; q < 4; ++q, rc += 8)
+                for (int e = 0; e < 4; ++e) rcv[4 * q + e] = rc[e];
         } else {
             for (int r = 0; r < 16; ++r) {
                 const int64_t row = row0 + 8 * (r >> 2) + (r & 3);
-                const int64_t rowc = row < w.m ? row : w.m - 1;
-                rcv[r] = w.rowcol[rowc];
-                cur[r] = __builtin_nontemporal_load(dst.M + rowc * ld + col0 + colc);
+                rcv[r] = w.rowcol[row < w.m ? row : w.m - 1];
             }
         }
         // this wave copies digit planes 2 cg, 2 cg + 1 of row block rg of A and
@@ -301,8 +307,8 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
         // kb + 1 and kb + 2 outstanding), barrier (every wave's copies of kb
         // have landed, and every wave is done with stage kb - 1), copy k-block
         // kb + 3 into stage kb - 1, multiply k-block kb
-        auto step = [&](const Stage& cur_st, Stage& next_st, int kb) {
-            wait_vm<8>();
+        auto step = [&](auto vm, const Stage& cur_st, Stage& next_st, int kb) {
+            wait_vm<decltype(vm)::value>();
             bare_barrier();
             copy(next_st, kb + 3);
             v4i af[4], bf[4];
@@ -312,16 +318,51 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
                 for (int lp = 0; lp < 4; ++lp)
                     acc[l + lp] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[l], bf[lp], acc[l + lp], 0, 0, 0);
         };
-        for (int kb = 0;; kb += 4) {
-            step(st0, st3, kb);
-            if (kb + 1 >= KB) break;
-            step(st1, st0, kb + 1);
-            if (kb + 2 >= KB) break;
-            step(st2, st1, kb + 2);
-            if (kb + 3 >= KB) break;
-            step(st3, st2, kb + 3);
-            if (kb + 4 >= KB) break;
+        typedef std::integral_constant<int, 8> Ahead;
+        typedef std::integral_constant<int, 24> AheadC;
+        uint32_t cur[16];
+        step(Ahead{}, st0, st3, 0);
+        // The tile's C entries, issued after the copies of k-block 3: exactly
+        // 16 loads per lane, which the next three steps' waits allow to be
+        // outstanding beside the copies of the two k-blocks ahead.
+        __asm__ volatile("" ::: "memory");
+        if (full) {
+            const uint32_t* g = dst.M + row0 * ld + col0 + colc;
+            for (int q = 0; q < 4; ++q, g += ld8)
+                for (int e = 0; e < 4; ++e) cur[4 * q + e] = __builtin_nontemporal_load(g + roff[e]);
+        } else {
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = row0 + 8 * (r >> 2) + (r & 3);
+                cur[r] = __builtin_nontemporal_load(dst.M + (row < w.m ? row : w.m - 1) * ld + col0 + colc);
+            }
         }
+        do {
+            if (KB <= 1) break;
+            step(AheadC{}, st1, st0, 1);
+            if (KB <= 2) break;
+            step(AheadC{}, st2, st1, 2);
+            if (KB <= 3) break;
+            step(AheadC{}, st3, st2, 3);
+#pragma unroll
+            for (int kb = 4; kb < kMaxKB; kb += 4) {
+                if (kb >= KB) break;
+                step(Ahead{}, st0, st3, kb);
+                if (kb + 1 >= KB) break;
+                step(Ahead{}, st1, st0, kb + 1);
+                if (kb + 2 >= KB) break;
+                step(Ahead{}, st2, st1, kb + 2);
+                if (kb + 3 >= KB) break;
+                step(Ahead{}, st3, st2, kb + 3);
+            }
+        } while (false);
+        // The C loads and the copies of the last steps (a k-block copied
+        // again into stages no longer read) have landed: the workgroup's LDS
+        // can be handed on once its stores are issued.  (The empty asm hands
+        // the values over as new definitions: the compiler's own wait
+        // analysis loses the count of the C loads at the joins of the k steps
+        // and would otherwise wait for every store before each fold.)
+        wait_vm<0>();
+        for (int r = 0; r < 16; ++r) __asm__ volatile("" : "+v"(cur[r]));
         if (col < N && !out.M) {
             uint32_t* g = dst.M + row0 * ld + col0 + col;
             for (int q = 0; q < 4; ++q, g += ld8)
@@ -347,9 +388,6 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
                 if (fresh) dst.M[row * ld + col0 + col] = v;
             }
         }
-        // the copies of the last steps (a k-block copied again into stages no
-        // longer read) must land before this workgroup's LDS can be handed on
-        wait_vm<0>();
     }
 }
 
@@ -669,6 +707,7 @@ hipError_t run_product(const PlainArgs& w, bool fp64, const int8_t* Af, const in
                            dim3(kThreads), 0, s, w, dst, col0, N, (const double*)Af,
                            (const double*)Bf, KB, ceil_div(N, 16), fresh_lo, fresh_hi);
     } else {
+        if (KB < 1 || KB > kMaxKB) return hipErrorInvalidValue;
         const double c32 = (double)((((uint64_t)1) << 32) % w.F.p);
         const int64_t tiles = ceil_div(m, 64) * ceil_div(N, 64);
         const int64_t grid = max_wgs > 0 && max_wgs < tiles ? max_wgs : tiles;
