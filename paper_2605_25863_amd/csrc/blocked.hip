@@ -370,7 +370,8 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
                     const int r = 4 * q + e;
                     if (row0 + 8 * q + e >= w.m || earlier_pivot(rcv[r], skip_below)) continue;
                     const bool fresh = rcv[r] >= fresh_lo && rcv[r] < fresh_hi;  // a pivot row of this panel
-                    g[roff[e]] = fold7(acc, r, fresh ? 0u : cur[r], c32, w.F);
+                    // (streamed past L2, where the A and B fragments stay)
+                    __builtin_nontemporal_store(fold7(acc, r, fresh ? 0u : cur[r], c32, w.F), g + roff[e]);
                 }
         } else if (col < N) {
             // (a pivot row of this panel also keeps its entries in dst: in
