@@ -68,6 +68,7 @@ def _cmp_rref(A, p, panel, tag):
     (129, 700, 9, None, 128),
     (600, 600, 8, None, 512),
     (700, 650, 6, None, 192),
+    (800, 760, 4, None, 320),
     (900, 880, 5, None, 384),
     (1000, 1000, 3, workloads.MERSENNE31, 384),
     (64, 64, 1, 2, 32),
@@ -132,9 +133,9 @@ def test_c2_slice_against_oracle(gpu):
             assert np.array_equal(np.asarray(g), np.asarray(r)), f"c2 slice panel={panel}: {name}"
 
 
-@pytest.mark.parametrize("panel", [192, 384])
+@pytest.mark.parametrize("panel", [192, 320, 384])
 def test_structured_wide_panels(gpu, panel):
-    """Free columns inside 192- and 384-wide panels, a zero block, duplicated
+    """Free columns inside 192-, 320- and 384-wide panels, a zero block, duplicated
     columns, inconsistent right-hand sides; solve and RREF against the oracle."""
     rng = np.random.default_rng(panel)
     p = workloads.draw_prime31(rng)
