@@ -653,6 +653,7 @@ struct Blocked {
     Mat PR;       // outer panel [panel | E]
     int8_t* Afrag;
     int8_t* Bfrag;
+    int64_t abytes, bbytes;  // sizes of the two fragment buffers
     int8_t* Yfrag;  // the int8 leaf products' right operand (kept apart from the trailing one)
     double* bs_acc; // back-substitution sums of one panel: panel x max(k, 1)
     LeafState leaf;
@@ -685,6 +686,8 @@ size_t carve_blocked(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, B
         b->PR = Mat{PR, ldpr};
         b->Afrag = A;
         b->Bfrag = B;
+        b->abytes = abytes;
+        b->bbytes = bbytes;
         b->Yfrag = Y;
         b->bs_acc = acc;
         b->leaf = ls;
@@ -726,7 +729,7 @@ hipError_t run_product(const PlainArgs& w, bool fp64, const int8_t* Af, const in
 // Returns the number of k-blocks.
 int32_t trailing_operands(const Blocked& b, const PlainArgs& w, bool fp64, Mat dst, int32_t j0,
                           int32_t wj, int64_t col0, int64_t N, int32_t skip_below, hipStream_t s,
-                          LaunchTimer& lt) {
+                          LaunchTimer& lt, int8_t* Af, int8_t* Bf, int64_t nb_cols) {
     const int64_t m = w.m;
     lt.before(LINAC_KERNEL_OPERANDS);
     int32_t KB;
@@ -735,20 +738,35 @@ int32_t trailing_operands(const Blocked& b, const PlainArgs& w, bool fp64, Mat d
         const int64_t NB = ceil_div(N, 16);
         const int64_t MB = ceil_div(m, 64) * 4;
         hipLaunchKernelGGL(build_b_f64_kernel, dim3((unsigned)ceil_div(NB * KB * 64, 256)), dim3(256),
-                           0, s, w, dst, j0, wj, col0, N, (int64_t)-1, KB, NB, (double*)b.Bfrag);
+                           0, s, w, dst, j0, wj, col0, N, (int64_t)-1, KB, NB, (double*)Bf);
         hipLaunchKernelGGL(build_a_f64_kernel, dim3((unsigned)ceil_div(MB * KB * 64, 256)), dim3(256),
-                           0, s, w, b.PR, (int64_t)wj, wj, KB, MB, (double*)b.Afrag);
+                           0, s, w, b.PR, (int64_t)wj, wj, KB, MB, (double*)Af);
     } else {
         KB = (int32_t)ceil_div(wj, 32);
-        const int64_t NB = ceil_div(N, 32);
+        const int64_t NB = ceil_div(nb_cols, 32);
         const int64_t MB = ceil_div(m, 128) * 4;
         const int32_t gb = (int32_t)ceil_div(NB * KB * 64, 256), ga = (int32_t)ceil_div(MB * KB * 64, 256);
         const int32_t gw = (int32_t)ceil_div(m * wj, 256);
         hipLaunchKernelGGL(panel_operands_kernel, dim3((unsigned)(gb + ga + gw)), dim3(256), 0, s, w, dst,
-                           b.PR, j0, wj, col0, N, KB, NB, MB, b.Afrag, b.Bfrag, skip_below, gb, ga);
+                           b.PR, j0, wj, col0, nb_cols, KB, NB, MB, Af, Bf, skip_below, gb, ga);
     }
     lt.after();
     return KB;
+}
+
+// The B fragments of trailing columns [col0, col0 + N) alone (int8 path; Bf is
+// the fragment of column col0), for the part of a split trailing product that
+// runs on the side stream.
+hipError_t trailing_b_rest(const Blocked& b, const PlainArgs& w, Mat dst, int32_t j0, int32_t wj,
+                           int64_t col0, int64_t N, int32_t KB, int8_t* Bf, hipStream_t s,
+                           LaunchTimer& lt) {
+    const int64_t NB = ceil_div(N, 32);
+    const int32_t gb = (int32_t)ceil_div(NB * KB * 64, 256);
+    lt.before(LINAC_KERNEL_OPERANDS, s);
+    hipLaunchKernelGGL(panel_operands_kernel, dim3((unsigned)gb), dim3(256), 0, s, w, dst, b.PR, j0, wj,
+                       col0, N, KB, NB, (int64_t)0, (int8_t*)nullptr, Bf, 0, gb, 0);
+    lt.after();
+    return hipGetLastError();
 }
 
 // Panels from the last to the first (see bs_partial_kernel).
@@ -808,7 +826,7 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
     int64_t outer_products = 0;
     LaunchTimer lt(opts, s);
     hipStream_t side = nullptr;
-    hipEvent_t ev_t1 = nullptr, ev_t2 = nullptr;
+    hipEvent_t ev_t1 = nullptr, ev_t2 = nullptr, ev_t3 = nullptr;
     const bool lookahead = overlap && !fp64 && n > panel;
     forward = forward && !fp64 && k > 0;  // the int8 path with right-hand sides to solve for
     // Y built by the selection's second launch when the first one decided the
@@ -822,8 +840,10 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
         e = side_stream(&side);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_t1, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_t2, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev_t3, hipEventDisableTiming);
         if (e != hipSuccess) {
             if (ev_t1) (void)hipEventDestroy(ev_t1);
+            if (ev_t2) (void)hipEventDestroy(ev_t2);
             return e;
         }
     }
@@ -832,7 +852,9 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
     // next leaf's first selection, which overlaps them.
     const bool pipeline = !fp64 && leaf_pipeline;
     bool t2_pending = false;
+    bool t3_pending = false;  // the side stream's first part of a split remainder is in flight
     bool pr_ready = false;  // the next panel's columns are in PR already
+    int32_t opset = 0;      // operand fragment set of the current panel (two alternate, int8 path)
     if (e == hipSuccess) e = leaf_init(b.leaf, (int32_t)m, s);
     int32_t leaf_index = 0;
     for (int32_t j0 = 0; j0 < n && e == hipSuccess; j0 += panel) {
@@ -926,40 +948,78 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
             ++leaf_index;
         }
         if (e != hipSuccess) break;
-        if (t2_pending) {  // the previous remainder writes the columns read next
+        const int64_t N = ncols - (j0 + wj);
+        const int64_t col0 = (int64_t)j0 + wj;
+        // The next panel's columns now, the rest on the side stream.  On the
+        // int8 path the next panel's columns go straight into PR (with its
+        // transform block cleared), so that panel needs no copy; that takes a
+        // width that keeps the remaining B fragments 32-aligned.
+        const int64_t wnext = n - (j0 + wj) < panel ? n - (j0 + wj) : panel;
+        const bool direct = !fp64 && wnext > 0 && wnext % 32 == 0;
+        const int64_t n1 = direct ? wnext : (lookahead && N > panel ? panel : N);
+        // Split remainder (int8 look-ahead, forward elimination): the columns of
+        // the panel after next first, in a launch of their own, so that the next
+        // panel waits for those only; the B fragments of the columns after them
+        // are built on the side stream, behind the previous remainder, whose
+        // later columns they read.  Two fragment sets alternate between panels,
+        // since the side stream may still read this panel's set while the next
+        // panel's operands are built.  (Under Gauss-Jordan the remainder hides
+        // behind the leaves and the extra launches only add to them.)
+        const int64_t after = n - (j0 + wj) - wnext;
+        const int64_t w2 = after < panel ? after : panel;
+        const bool split = N > 0 && lookahead && forward && direct && w2 > 0 && w2 % 32 == 0 &&
+                           n1 + w2 < N;
+        // The previous remainder writes the columns read next: its first part
+        // covers this panel's next-panel columns, all that a split panel reads on
+        // this stream; any other panel builds B over every trailing column and
+        // waits for all of it.
+        if (split && t3_pending) {
+            e = hipStreamWaitEvent(s, ev_t3, 0);
+        } else if (t2_pending) {
             e = hipStreamWaitEvent(s, ev_t2, 0);
             t2_pending = false;
-            if (e != hipSuccess) break;
         }
-        const int64_t N = ncols - (j0 + wj);
+        t3_pending = false;
+        if (e != hipSuccess) break;
         if (N > 0) {
             if (opts && opts->ev_begin && outer_products == 0) (void)hipEventRecord(opts->ev_begin, s);
-            const int64_t col0 = (int64_t)j0 + wj;
-            const int32_t KB = trailing_operands(b, w, fp64, Wm, j0, wj, col0, N, skip_below, s, lt);
+            int8_t* Af = b.Afrag;
+            int8_t* Bf = b.Bfrag;
+            if (lookahead && !fp64) {  // (the int8 fragments take half of each buffer)
+                Af += (size_t)opset * (b.abytes / 2);
+                Bf += (size_t)opset * (b.bbytes / 2);
+                opset ^= 1;
+            }
+            const int32_t KB = trailing_operands(b, w, fp64, Wm, j0, wj, col0, N, skip_below, s, lt, Af,
+                                                 Bf, split ? n1 : N);
             e = hipGetLastError();
-            // The next panel's columns now, the rest on the side stream.  On the
-            // int8 path the next panel's columns go straight into PR (with its
-            // transform block cleared), so that panel needs no copy; that takes
-            // a width that keeps the remaining B fragments 32-aligned.
-            const int64_t wnext = n - (j0 + wj) < panel ? n - (j0 + wj) : panel;
-            const bool direct = !fp64 && wnext > 0 && wnext % 32 == 0;
-            const int64_t n1 = direct ? wnext : (lookahead && N > panel ? panel : N);
             if (e == hipSuccess)
-                e = run_product(w, fp64, b.Afrag, b.Bfrag, Wm, col0, n1, KB, j0, j0 + wj, s, lt,
+                e = run_product(w, fp64, Af, Bf, Wm, col0, n1, KB, j0, j0 + wj, s, lt,
                                 LINAC_KERNEL_TRAIL_PRODUCT, 0, skip_below,
                                 direct ? b.PR : Mat{nullptr, 0}, (int32_t)wnext);
             pr_ready = direct && e == hipSuccess;
+            int8_t* Bf1 = Bf + (n1 / 32) * KB * 4 * 1024;
             if (e == hipSuccess && n1 < N && !lookahead) {  // the rest on this stream
-                e = run_product(w, fp64, b.Afrag, b.Bfrag + (n1 / 32) * KB * 4 * 1024, Wm, col0 + n1,
-                                N - n1, KB, j0, j0 + wj, s, lt, LINAC_KERNEL_TRAIL_PRODUCT, 0,
-                                skip_below);
+                e = run_product(w, fp64, Af, Bf1, Wm, col0 + n1, N - n1, KB, j0, j0 + wj, s, lt,
+                                LINAC_KERNEL_TRAIL_PRODUCT, 0, skip_below);
             } else if (e == hipSuccess && n1 < N) {
                 e = hipEventRecord(ev_t1, s);
                 if (e == hipSuccess) e = hipStreamWaitEvent(side, ev_t1, 0);
-                if (e == hipSuccess)
-                    e = run_product(w, fp64, b.Afrag, b.Bfrag + (n1 / 32) * KB * 4 * 1024, Wm,
-                                    col0 + n1, N - n1, KB, j0, j0 + wj, side, lt,
+                if (e == hipSuccess && split) {
+                    e = trailing_b_rest(b, w, Wm, j0, wj, col0 + n1, N - n1, KB, Bf1, side, lt);
+                    if (e == hipSuccess)
+                        e = run_product(w, fp64, Af, Bf1, Wm, col0 + n1, w2, KB, j0, j0 + wj, side, lt,
+                                        LINAC_KERNEL_TRAIL_PRODUCT, side_wgs, skip_below);
+                    if (e == hipSuccess) e = hipEventRecord(ev_t3, side);
+                    t3_pending = e == hipSuccess;
+                    if (e == hipSuccess)
+                        e = run_product(w, fp64, Af, Bf1 + (w2 / 32) * KB * 4 * 1024, Wm, col0 + n1 + w2,
+                                        N - n1 - w2, KB, j0, j0 + wj, side, lt,
+                                        LINAC_KERNEL_TRAIL_PRODUCT, side_wgs, skip_below);
+                } else if (e == hipSuccess) {
+                    e = run_product(w, fp64, Af, Bf1, Wm, col0 + n1, N - n1, KB, j0, j0 + wj, side, lt,
                                     LINAC_KERNEL_TRAIL_PRODUCT, side_wgs, skip_below);
+                }
                 if (e == hipSuccess) e = hipEventRecord(ev_t2, side);
                 t2_pending = e == hipSuccess;
             }
@@ -978,6 +1038,7 @@ hipError_t blocked_eliminate(void* ws, int64_t m, int64_t n, int64_t k, int32_t 
     if (forward && e == hipSuccess) e = back_substitute(b, n, k, panel, s);
     if (ev_t1) (void)hipEventDestroy(ev_t1);
     if (ev_t2) (void)hipEventDestroy(ev_t2);
+    if (ev_t3) (void)hipEventDestroy(ev_t3);
     if (opts && opts->ev_end && outer_products > 0) (void)hipEventRecord(opts->ev_end, s);
     if (opts && opts->dominant_launches) *opts->dominant_launches = outer_products;
     return e;
