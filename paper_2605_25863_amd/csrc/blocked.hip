@@ -100,6 +100,7 @@ __device__ __forceinline__ uint32_t xs_value(const PlainArgs& w, Mat src, int32_
 // B operand: X_S split into digits, stored in the lane order of the 32x32x32
 // int8 MFMA: fragment (cb, kb, l') is 64 lanes x 16 bytes; lane L holds digit
 // l' of column cb*32 + L%32 and rows k = kb*32 + 16*(L/32) + i, i = 0..15.
+template <bool kNeg = false>  // (kNeg: fragments of -X_S)
 __device__ __forceinline__ void build_b_at(const PlainArgs& w, Mat src, int32_t gslot0, int32_t wj, int64_t col0,
                                            int64_t N, int64_t inj0, int32_t KB, int64_t NB, int8_t* Bfrag,
                                            int64_t gid) {
@@ -114,7 +115,8 @@ __device__ __forceinline__ void build_b_at(const PlainArgs& w, Mat src, int32_t 
     for (int i = 0; i < 16; ++i) {
         const int k = kb * 32 + 16 * (L >> 5) + i;
         int8_t d[4];
-        digits4(centre(xs_value(w, src, gslot0, wj, col0, N, inj0, k, col), p), d);
+        const int32_t c = centre(xs_value(w, src, gslot0, wj, col0, N, inj0, k, col), p);
+        digits4(kNeg ? -c : c, d);
         for (int l = 0; l < 4; ++l) out[l][i] = d[l];
     }
     int8_t* base = Bfrag + ((cb * KB + kb) * 4) * 1024 + L * 16;
@@ -222,12 +224,19 @@ __device__ __forceinline__ void bare_barrier() {
 // (columns from 0) instead of dst, and out's columns [ezero, ezero + N) of
 // the same rows are set to zero: the next panel's columns written straight
 // into the panel buffer, with its transform block cleared.
-__global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat dst, int64_t col0,
-                                                              int64_t N, const int8_t* Afrag,
-                                                              const int8_t* Bfrag, int32_t KB,
-                                                              int32_t fresh_lo, int32_t fresh_hi,
-                                                              double c32, int32_t skip_below, Mat out,
-                                                              int32_t ezero) {
+// Rows a product leaves alone: in the trailing update the pivot rows of earlier
+// panels (forward elimination; skip_below = the panel's first column, else 0),
+// in the back-substitution update every row but those.
+template <bool kBack>
+__device__ __forceinline__ bool row_left(int32_t rowcol, int32_t skip_below) {
+    return kBack ? !(rowcol >= 0 && rowcol < skip_below) : earlier_pivot(rowcol, skip_below);
+}
+
+template <bool kBack>
+__device__ __forceinline__ void gemm_i8_body(const PlainArgs& w, Mat dst, int64_t col0, int64_t N,
+                                             const int8_t* Afrag, const int8_t* Bfrag, int32_t KB,
+                                             int32_t fresh_lo, int32_t fresh_hi, double c32,
+                                             int32_t skip_below, Mat out, int32_t ezero) {
     // four stages, each [A row block 0, 1 | B column block 0, 1][digit plane][lane]
     // (separate arrays, so that the compiler sees a stage's reads apart from
     // the copies in flight into the others)
@@ -249,7 +258,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
         if (skip_below > 0) {  // forward elimination: a tile of earlier pivot rows only is skipped
             const int64_t row = rt * 64 + (threadIdx.x >> 2);
             int keep = 0;
-            if ((threadIdx.x & 3) == 0 && row < w.m) keep = !earlier_pivot(w.rowcol[row], skip_below);
+            if ((threadIdx.x & 3) == 0 && row < w.m) keep = !row_left<kBack>(w.rowcol[row], skip_below);
             if (__syncthreads_or(keep) == 0) continue;
         } else {
             __syncthreads();
@@ -368,7 +377,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
             for (int q = 0; q < 4; ++q, g += ld8)
                 for (int e = 0; e < 4; ++e) {
                     const int r = 4 * q + e;
-                    if (row0 + 8 * q + e >= w.m || earlier_pivot(rcv[r], skip_below)) continue;
+                    if (row0 + 8 * q + e >= w.m || row_left<kBack>(rcv[r], skip_below)) continue;
                     const bool fresh = rcv[r] >= fresh_lo && rcv[r] < fresh_hi;  // a pivot row of this panel
                     // (streamed past L2, where the A and B fragments stay)
                     __builtin_nontemporal_store(fold7(acc, r, fresh ? 0u : cur[r], c32, w.F), g + roff[e]);
@@ -382,7 +391,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
                 if (row >= w.m) continue;
                 uint32_t* o = out.M + row * out.ld;
                 o[ezero + col] = 0u;
-                if (earlier_pivot(rcv[r], skip_below)) continue;
+                if (row_left<kBack>(rcv[r], skip_below)) continue;
                 const bool fresh = rcv[r] >= fresh_lo && rcv[r] < fresh_hi;  // a pivot row of this panel
                 const uint32_t v = fold7(acc, r, fresh ? 0u : cur[r], c32, w.F);
                 o[col] = v;
@@ -390,6 +399,27 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat d
             }
         }
     }
+}
+
+__global__ __launch_bounds__(kThreads, 2) void gemm_i8_kernel(PlainArgs w, Mat dst, int64_t col0,
+                                                              int64_t N, const int8_t* Afrag,
+                                                              const int8_t* Bfrag, int32_t KB,
+                                                              int32_t fresh_lo, int32_t fresh_hi,
+                                                              double c32, int32_t skip_below, Mat out,
+                                                              int32_t ezero) {
+    gemm_i8_body<false>(w, dst, col0, N, Afrag, Bfrag, KB, fresh_lo, fresh_hi, c32, skip_below, out,
+                        ezero);
+}
+
+// The back-substitution update of one panel (see back_substitute): the
+// right-hand sides (dst columns [col0, col0 + N)) of the pivot rows of earlier
+// panels (rowcol below j0) become C + A . B, A = their entries in the panel's
+// columns, B = -x of the panel's columns.
+__global__ __launch_bounds__(kThreads, 2) void bs_product_kernel(PlainArgs w, Mat dst, int64_t col0,
+                                                                 int64_t N, const int8_t* Afrag,
+                                                                 const int8_t* Bfrag, int32_t KB,
+                                                                 double c32, int32_t j0) {
+    gemm_i8_body<true>(w, dst, col0, N, Afrag, Bfrag, KB, 0, 0, c32, j0, Mat{nullptr, 0}, 0);
 }
 
 // The int8 leaf product (leafprod.h) over a grid of 64-row blocks (x) and
@@ -538,112 +568,22 @@ __global__ void panel_operands_kernel(PlainArgs w, Mat W, Mat PR, int32_t j0, in
 // Back-substitution after forward elimination (the solve).  The pivot row q of
 // a column c in panel [j0, j0 + wj) is 1 at c and 0 at every other pivot column
 // of its panel and of the panels before it; right of its panel it keeps
-// entries U[q][c'].  So, panel by panel from the last,
-//    x(c, t) = W[q][n + t] - sum over c' >= j0 + wj of U[q][c'] x(c', t),
-// with x(c', t) = W[pivot row of c'][n + t] once its panel is done and 0 for a
-// free column c'.  bs_partial_kernel: a workgroup takes 64 columns c' and 16
-// panel columns (4 per wave, lane = right-hand side t).  The columns' pivot
-// rows and U entries are loaded once, lane by column, and read across the wave
-// by readlane; x is split into 16-bit halves, so a
-// product is two exact FMAs, and the 64 products of a workgroup sum below 2^53
-// in two FP64 accumulators per panel column, reduced once.  The reduced sums
-// (below 2^31) of the n / 64 workgroups meet in FP64 atomics, below 2^53 for
-// any n below 2^28 (exact, so the order of the additions does not matter).
-// bs_finish_kernel writes x = W[q][n + t] - acc mod p into the pivot row and
-// clears acc.
-constexpr int kBsCols = 64;  // columns c' per workgroup
-
-// The residue in [0, p) of an integer s with |s| < 2^53 (two quotient steps:
-// the first estimate is within 2^-20 of exact, the second within one).
-__device__ __forceinline__ double canon53(double s, const FieldConst& F) {
-    double r = __fma_rn(-floor(s * F.pinv), F.dp, s);
-    r = __fma_rn(-floor(r * F.pinv), F.dp, r);
-    if (r < 0.0) r += F.dp;
-    if (r >= F.dp) r -= F.dp;
-    return r;
-}
-
-__global__ __launch_bounds__(kThreads) void bs_partial_kernel(PlainArgs w, int32_t n, int32_t k,
-                                                              int32_t j0, int32_t wj, double* acc) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int32_t c_lo = j0 + wj + blockIdx.x * kBsCols;
-    const int32_t cl0 = blockIdx.y * 16 + wave * 4;  // the wave's first panel column
-    int64_t prow[4];
-    bool any = false;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int32_t cl = cl0 + i;
-        const int32_t sp = cl < wj ? w.colpiv[j0 + cl] : -1;
-        prow[i] = sp >= 0 ? (int64_t)w.pivrow[sp] : -1;
-        any = any || prow[i] >= 0;
-    }
-    if (!any) return;  // uniform over the wave; no barrier below
-    // lane L describes column c_lo + L: the row holding its x (-1: free or past
-    // n) and the four U entries of this wave's rows, all loaded at once
-    const int32_t cc = c_lo + lane;
-    const bool cin = cc < n;
-    const int32_t spc = cin ? w.colpiv[cc] : -1;
-    const int32_t xr_l = spc >= 0 ? w.pivrow[spc] : -1;
-    uint32_t u_l[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) u_l[i] = (cin && prow[i] >= 0) ? w.W[prow[i] * w.ld + cc] : 0u;
-    for (int32_t t0 = 0; t0 < k; t0 += 64) {
-        const int32_t t = t0 + lane;
-        const int32_t tc = t < k ? t : k - 1;
-        double sh[4] = {0.0, 0.0, 0.0, 0.0}, sl[4] = {0.0, 0.0, 0.0, 0.0};
-        // eight columns per round: their x loads are issued together
-        for (int c8 = 0; c8 < kBsCols; c8 += 8) {
-            uint32_t xv[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int32_t xr = __builtin_amdgcn_readlane(xr_l, c8 + e);
-                xv[e] = xr >= 0 ? w.W[(int64_t)xr * w.ld + n + tc] : 0u;
-            }
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const double xh = (double)(xv[e] >> 16), xl = (double)(xv[e] & 0xffffu);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    // < 2^31: u xh < 2^46, u xl < 2^47
-                    const double u = (double)(uint32_t)__builtin_amdgcn_readlane((int)u_l[i], c8 + e);
-                    sh[i] = __fma_rn(u, xh, sh[i]);
-                    sl[i] = __fma_rn(u, xl, sl[i]);
-                }
-            }
-        }
-        if (t < k) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                if (prow[i] >= 0) {
-                    // sh < 2^52, sl < 2^53: (sh mod p) 2^16 + (sl mod p) < 2^48
-                    const double r = canon53(__fma_rn(canon53(sh[i], w.F), 65536.0, canon53(sl[i], w.F)), w.F);
-                    atomicAdd(&acc[(int64_t)(cl0 + i) * k + t], r);
-                }
-        }
-    }
-}
-
-__global__ void bs_finish_kernel(PlainArgs w, int32_t n, int32_t k, int32_t j0, int32_t wj, double* acc) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (int64_t)wj * k) return;
-    const int32_t cl = (int32_t)(gid / k), t = (int32_t)(gid % k);
-    const double sum = acc[gid];
-    acc[gid] = 0.0;
-    const int32_t sp = w.colpiv[j0 + cl];
-    if (sp < 0) return;
-    uint32_t* x = w.W + (int64_t)w.pivrow[sp] * w.ld + n + t;
-    // sum is an integer below 2^53 in magnitude: two lazy quotient steps bring
-    // it into [-p, 2p) (the first quotient is within 2^-20 of exact), then canonical
-    double r = __fma_rn(-floor(sum * w.F.pinv), w.F.dp, sum);
-    r = __fma_rn(-floor(r * w.F.pinv), w.F.dp, r);
-    if (r < 0.0) r += w.F.dp;
-    if (r >= w.F.dp) r -= w.F.dp;
-    *x = sub_mod(*x, (uint32_t)r, w.F.p);
-}
-
-__global__ void bs_clear_kernel(double* acc, int64_t count) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid < count) acc[gid] = 0.0;
+// entries U[q][c'].  So x(c, t) = W[q][n + t] once the terms of every later
+// column have been taken off: panel by panel from the last, the right-hand
+// sides of the pivot rows of the earlier panels become
+//    W[q'][n + t] - sum over c in the panel of U[q'][c] x(c, t),
+// with x(c, t) = W[pivot row of c][n + t] (0 for a free column): one int8 MFMA
+// product per panel with K = the panel width (A = those rows' entries in the
+// panel's columns, B = -x), reduced exactly as the trailing update is.
+// bs_operands_kernel builds its fragments: the first gb blocks B, the rest A.
+__global__ void bs_operands_kernel(PlainArgs w, Mat W, int32_t j0, int32_t wj, int64_t col0, int64_t N,
+                                   int32_t KB, int64_t NB, int64_t MB, int8_t* Afrag, int8_t* Bfrag,
+                                   int32_t gb) {
+    const int64_t b = blockIdx.x;
+    if (b < gb)
+        build_b_at<true>(w, W, j0, wj, col0, N, (int64_t)-1, KB, NB, Bfrag, b * blockDim.x + threadIdx.x);
+    else
+        build_a_at(w, W, (int64_t)j0, wj, KB, MB, Afrag, (b - gb) * blockDim.x + threadIdx.x);
 }
 
 constexpr int32_t kLeaf = 32;  // inner panel width of the two-level reduction
@@ -655,7 +595,6 @@ struct Blocked {
     int8_t* Bfrag;
     int64_t abytes, bbytes;  // sizes of the two fragment buffers
     int8_t* Yfrag;  // the int8 leaf products' right operand (kept apart from the trailing one)
-    double* bs_acc; // back-substitution sums of one panel: panel x max(k, 1)
     LeafState leaf;
     int32_t panel;
 };
@@ -678,7 +617,6 @@ size_t carve_blocked(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, B
     int8_t* A = c.take<int8_t>(abytes);
     int8_t* B = c.take<int8_t>(bbytes);
     int8_t* Y = c.take<int8_t>(Nl * kLeaf * 4);
-    double* acc = c.take<double>((int64_t)panel * (k > 0 ? k : 1));
     LeafState ls;
     leaf_carve(c, m, Nl, &ls);
     if (b) {
@@ -689,7 +627,6 @@ size_t carve_blocked(void* ws, int64_t m, int64_t n, int64_t k, int32_t panel, B
         b->abytes = abytes;
         b->bbytes = bbytes;
         b->Yfrag = Y;
-        b->bs_acc = acc;
         b->leaf = ls;
         b->panel = panel;
     }
@@ -769,21 +706,25 @@ hipError_t trailing_b_rest(const Blocked& b, const PlainArgs& w, Mat dst, int32_
     return hipGetLastError();
 }
 
-// Panels from the last to the first (see bs_partial_kernel).
+// Panels from the last to the first (see bs_operands_kernel); the first panel
+// has no earlier pivot rows to update.
 hipError_t back_substitute(const Blocked& b, int64_t n, int64_t k, int32_t panel, hipStream_t s) {
     const PlainArgs& w = b.w;
-    const int64_t cnt = (int64_t)panel * k;
-    hipLaunchKernelGGL(bs_clear_kernel, dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, s, b.bs_acc, cnt);
+    const int64_t m = w.m;
+    const Mat Wm{w.W, w.ld};
+    const double c32 = (double)((((uint64_t)1) << 32) % w.F.p);
     const int64_t last = (n - 1) / panel * panel;
-    for (int64_t j0 = last; j0 >= 0; j0 -= panel) {
+    for (int64_t j0 = last; j0 > 0; j0 -= panel) {
         const int32_t wj = (int32_t)(n - j0 < panel ? n - j0 : panel);
-        const int64_t after = n - j0 - wj;
-        if (after <= 0) continue;  // the last panel: nothing to its right
-        hipLaunchKernelGGL(bs_partial_kernel,
-                           dim3((unsigned)ceil_div(after, kBsCols), (unsigned)ceil_div(wj, 16)),
-                           dim3(kThreads), 0, s, w, (int32_t)n, (int32_t)k, (int32_t)j0, wj, b.bs_acc);
-        hipLaunchKernelGGL(bs_finish_kernel, dim3((unsigned)ceil_div((int64_t)wj * k, 256)), dim3(256),
-                           0, s, w, (int32_t)n, (int32_t)k, (int32_t)j0, wj, b.bs_acc);
+        const int32_t KB = (int32_t)ceil_div(wj, 32);
+        if (KB > kMaxKB) return hipErrorInvalidValue;
+        const int64_t NB = ceil_div(k, 32), MB = ceil_div(m, 128) * 4;
+        const int32_t gb = (int32_t)ceil_div(NB * KB * 64, 256), ga = (int32_t)ceil_div(MB * KB * 64, 256);
+        hipLaunchKernelGGL(bs_operands_kernel, dim3((unsigned)(gb + ga)), dim3(256), 0, s, w, Wm,
+                           (int32_t)j0, wj, n, k, KB, NB, MB, b.Afrag, b.Bfrag, gb);
+        hipLaunchKernelGGL(bs_product_kernel, dim3((unsigned)(ceil_div(m, 64) * ceil_div(k, 64))),
+                           dim3(kThreads), 0, s, w, Wm, n, k, (const int8_t*)b.Afrag,
+                           (const int8_t*)b.Bfrag, KB, c32, (int32_t)j0);
     }
     return hipGetLastError();
 }
